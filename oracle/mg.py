@@ -1,0 +1,210 @@
+"""Geometric multigrid V-cycle on the Q1 hierarchy (oracle).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Readings of the paper taken here (each is listed with its reason in the
+design notes of the repository):
+
+* Gauss-Seidel, Eq. (1), is read with the division by the diagonal entry
+  that the printed formula omits.
+* "Red-black" Gauss-Seidel on Q1 couples nodes of the same colour (through
+  the diagonal neighbours in 2D and the edge neighbours in 3D), so a
+  parallel in-place half-sweep would be order dependent.  A half-sweep on
+  colour c therefore updates every node of colour c simultaneously from the
+  values at the start of the half-sweep.  Colour c = (sum of node
+  coordinates) mod 2.  Pre-smoothing runs colour 0 then 1; post-smoothing
+  runs 1 then 0, so that the cycle is symmetric.
+* Damped Jacobi uses omega = 2/3 unless told otherwise.
+* The coarsest level is solved exactly by a dense Cholesky factorisation
+  (Algorithm 1 allows a direct solver there, Sec. 5.3).
+* Coarse operators are rediscretised on every level (not Galerkin
+  products); for variable kappa the coarse cell value is the geometric mean
+  of its children.
+* The outer iteration (Sec. 5.5.1) starts from u = 0 and stops after the
+  first cycle whose relative residual ||b - A u||_2 / ||b||_2 over the
+  unknowns is <= tol.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from .q1 import assemble, interior_coords, kappa_hierarchy
+from .transfer import prolongation
+
+
+@dataclass
+class Hierarchy:
+    dim: int
+    n: int
+    levels: int
+    smoother: str = "rbgs"          # "jacobi" or "rbgs"
+    nu_pre: int = 2
+    nu_post: int = 2
+    omega: float = 2.0 / 3.0
+    A: list = field(default_factory=list)       # A[l], l = 0 finest
+    diag: list = field(default_factory=list)
+    P: list = field(default_factory=list)       # P[l]: level l+1 -> level l
+    mask: list = field(default_factory=list)    # colour-0 boolean mask
+    coarse_factor: object = None
+    nl: list = field(default_factory=list)
+    # float32 copies for the iterative-refinement inner cycle
+    A32: list = field(default_factory=list)
+    diag32: list = field(default_factory=list)
+    P32: list = field(default_factory=list)
+
+
+def colour_mask(dim, n, colour):
+    """Boolean mask over the unknowns: (sum of coordinates) mod 2 == colour."""
+    s = sum(interior_coords(dim, n))
+    return (s % 2) == colour
+
+
+def build_hierarchy(dim, n, levels, kappa=None, smoother="rbgs", nu_pre=2,
+                    nu_post=2, omega=2.0 / 3.0, fp32=False):
+    """Assemble every level's operator and the transfers (Sec. 5.1)."""
+    if levels < 1 or n % (1 << (levels - 1)) != 0 or (n >> (levels - 1)) < 2:
+        raise ValueError("need n divisible by 2^(levels-1) and n_c >= 2")
+    H = Hierarchy(dim=dim, n=n, levels=levels, smoother=smoother,
+                  nu_pre=nu_pre, nu_post=nu_post, omega=omega)
+    kaps = kappa_hierarchy(dim, n, levels, kappa)
+    for l in range(levels):
+        nl = n >> l
+        A = assemble(dim, nl, kaps[l])
+        H.nl.append(nl)
+        H.A.append(A)
+        H.diag.append(A.diagonal().copy())
+        H.mask.append(colour_mask(dim, nl, 0))
+        if l < levels - 1:
+            H.P.append(prolongation(dim, nl))
+    Ac = H.A[-1].toarray()
+    H.coarse_factor = sla.cho_factor(Ac, lower=True)
+    if fp32:
+        H.A32 = [A.astype(np.float32) for A in H.A]
+        H.diag32 = [d.astype(np.float32) for d in H.diag]
+        H.P32 = [P.astype(np.float32) for P in H.P]
+    return H
+
+
+# --------------------------------------------------------------------------
+# smoothers (Eq. (1); Algorithm 1 steps "pre-smoothing" / "post-smoothing")
+# --------------------------------------------------------------------------
+
+def jacobi_sweep(A, diag, x, b, omega):
+    """x + omega D^-1 (b - A x)."""
+    r = b - A @ x
+    return x + omega * (r / diag)
+
+
+def rb_half_sweep(A, diag, x, b, mask):
+    """Update the nodes selected by ``mask`` simultaneously from x."""
+    r = b - A @ x
+    return np.where(mask, x + r / diag, x)
+
+
+def smooth(H, l, x, b, pre, fp32=False):
+    A = H.A32[l] if fp32 else H.A[l]
+    diag = H.diag32[l] if fp32 else H.diag[l]
+    nu = H.nu_pre if pre else H.nu_post
+    if H.smoother == "jacobi":
+        om = np.float32(H.omega) if fp32 else H.omega
+        for _ in range(nu):
+            x = jacobi_sweep(A, diag, x, b, om)
+        return x
+    red = H.mask[l]
+    order = (red, ~red) if pre else (~red, red)
+    for _ in range(nu):
+        for m in order:
+            x = rb_half_sweep(A, diag, x, b, m)
+    return x
+
+
+def coarse_solve(H, b, fp32=False):
+    """Exact solve on the coarsest level with the FP64 Cholesky factor."""
+    if fp32:
+        return sla.cho_solve(H.coarse_factor, b.astype(np.float64)).astype(np.float32)
+    return sla.cho_solve(H.coarse_factor, b)
+
+
+# --------------------------------------------------------------------------
+# V-cycle (Algorithm 1) and the outer iteration
+# --------------------------------------------------------------------------
+
+def vcycle(H, l, x, b, fp32=False):
+    """One V-cycle on level l for A_l x = b, starting from x.
+
+    Steps in the order of Algorithm 1: pre-smoothing, restriction of the
+    residual, recursive solve of the residual equation from a zero guess
+    (exact on the coarsest level), prolongation of the correction added to
+    x, post-smoothing.
+    """
+    if l == H.levels - 1:
+        return coarse_solve(H, b, fp32)
+    A = H.A32[l] if fp32 else H.A[l]
+    P = H.P32[l] if fp32 else H.P[l]
+    x = smooth(H, l, x, b, pre=True, fp32=fp32)
+    r = b - A @ x
+    bc = P.T @ r
+    zero = np.zeros(bc.shape[0], dtype=bc.dtype)
+    e = vcycle(H, l + 1, zero, bc, fp32)
+    x = x + P @ e
+    x = smooth(H, l, x, b, pre=False, fp32=fp32)
+    return x
+
+
+def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
+    """Outer fixed-point iteration of V-cycles (Sec. 5.5.1) in FP64.
+
+    Returns (u, iters, hist, status) with hist[0] = 1 and hist[k] the
+    relative residual after cycle k; status is "ok", "maxit" or "diverged".
+    """
+    b = np.asarray(b, dtype=np.float64)
+    A = H.A[0]
+    nb = np.linalg.norm(b)
+    u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64)
+    hist = [1.0]
+    if nb == 0.0:
+        return np.zeros_like(b), 0, hist, "ok"
+    for k in range(1, max_iter + 1):
+        u = vcycle(H, 0, u, b)
+        rho = np.linalg.norm(b - A @ u) / nb
+        hist.append(rho)
+        if not np.isfinite(rho) or rho > diverge:
+            return u, k, hist, "diverged"
+        if rho <= tol:
+            return u, k, hist, "ok"
+    return u, max_iter, hist, "maxit"
+
+
+def solve_ir(H, b, tol, max_iter=100, diverge=1e3):
+    """FP32-inner / FP64-outer iterative refinement.
+
+    FP64: r = b - A u, s = ||r||; the correction equation is solved
+    approximately by one float32 V-cycle (operators rounded from the FP64
+    assembly, coarse solve in FP64) applied to float32(r / s) from a zero
+    guess; then u += s * float64(c).  Stops like :func:`solve`.
+    """
+    if not H.A32:
+        raise ValueError("hierarchy built without fp32=True")
+    b = np.asarray(b, dtype=np.float64)
+    A = H.A[0]
+    nb = np.linalg.norm(b)
+    u = np.zeros_like(b)
+    hist = [1.0]
+    if nb == 0.0:
+        return u, 0, hist, "ok"
+    r = b.copy()
+    for k in range(1, max_iter + 1):
+        s = np.linalg.norm(r)
+        r32 = (r / s).astype(np.float32)
+        c32 = vcycle(H, 0, np.zeros_like(r32), r32, fp32=True)
+        u = u + s * c32.astype(np.float64)
+        r = b - A @ u
+        rho = np.linalg.norm(r) / nb
+        hist.append(rho)
+        if not np.isfinite(rho) or rho > diverge:
+            return u, k, hist, "diverged"
+        if rho <= tol:
+            return u, k, hist, "ok"
+    return u, max_iter, hist, "maxit"

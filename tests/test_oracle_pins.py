@@ -1,0 +1,399 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by the
+mathematics, not by the oracle itself.
+
+Each test names what a plausible mistake in the oracle would break:
+element factors, assembly indices, transfer weights/scaling, smoother
+arithmetic, colour order, cycle structure, stopping rule, coefficient
+coarsening, exact references.
+"""
+
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+from paper_1609_04809_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- element
+
+def _element_by_quadrature(dim, h, q=3):
+    """int grad(phi_a) . grad(phi_b) over [0,h]^d by Gauss quadrature,
+    with the trilinear basis evaluated point by point."""
+    xi, wq = np.polynomial.legendre.leggauss(q)
+    xi, wq = 0.5 * (xi + 1.0), 0.5 * wq
+    verts = [tuple((a >> d) & 1 for d in range(dim)) for a in range(2 ** dim)]
+    K = np.zeros((2 ** dim, 2 ** dim))
+    for pt in itertools.product(range(q), repeat=dim):
+        s = [xi[p] for p in pt]
+        w = np.prod([wq[p] for p in pt]) * h ** dim
+        grads = []
+        for v in verts:
+            g = []
+            for e in range(dim):
+                val = (1.0 if v[e] else -1.0) / h
+                for d in range(dim):
+                    if d != e:
+                        val *= s[d] if v[d] else 1.0 - s[d]
+                g.append(val)
+            grads.append(np.array(g))
+        for a in range(2 ** dim):
+            for b in range(2 ** dim):
+                K[a, b] += w * grads[a] @ grads[b]
+    return K
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("h", [1.0, 0.125])
+def test_element_matrix_matches_quadrature(dim, h):
+    K = O.element_matrix(dim, h)
+    np.testing.assert_allclose(K, _element_by_quadrature(dim, h), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(K, K.T, atol=0)
+    np.testing.assert_allclose(K.sum(axis=1), 0.0, atol=1e-14)
+
+
+def test_assembled_stencil_closed_forms():
+    # 2D Poisson: centre 8/3, all eight neighbours -1/3 (h independent)
+    n = 8
+    A = O.assemble(2, n).toarray()
+    c = 3 + (n - 1) * 3                       # interior node (4, 4)
+    row = A[c].reshape(n - 1, n - 1)
+    np.testing.assert_allclose(row[2:5, 2:5],
+                               [[-1 / 3, -1 / 3, -1 / 3],
+                                [-1 / 3, 8 / 3, -1 / 3],
+                                [-1 / 3, -1 / 3, -1 / 3]], atol=1e-15)
+    # 3D Poisson: centre 8h/3, faces 0, edges -h/6, corners -h/12
+    n = 8
+    h = 1.0 / n
+    A = O.assemble(3, n)
+    c = 3 + 7 * 3 + 49 * 3
+    row = A[c].toarray().reshape(7, 7, 7)[2:5, 2:5, 2:5]
+    for dz, dy, dx in itertools.product((-1, 0, 1), repeat=3):
+        k = abs(dx) + abs(dy) + abs(dz)
+        want = {0: 8 * h / 3, 1: 0.0, 2: -h / 6, 3: -h / 12}[k]
+        assert abs(row[dz + 1, dy + 1, dx + 1] - want) < 1e-15
+    # structural pattern: (3n-5)^d stored entries (faces kept as zeros)
+    assert A.nnz == (3 * n - 5) ** 3
+    assert O.assemble(2, 16).nnz == (3 * 16 - 5) ** 2
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+def test_symmetric_spd_and_spectrum(dim, n):
+    A = O.assemble(dim, n)
+    assert abs(A - A.T).max() == 0.0
+    Ad = A.toarray()
+    sla.cholesky(Ad, lower=True)                          # SPD
+    ev = np.sort(np.linalg.eigvalsh(Ad))
+    np.testing.assert_allclose(ev, np.sort(O.dst_eigenvalues(dim, n).ravel()),
+                               rtol=1e-12, atol=1e-13)
+
+
+def test_row_sums_vanish_away_from_boundary():
+    n = 10
+    A = O.assemble(3, n)
+    x, y, z = O.interior_coords(3, n)
+    inner = (x > 1) & (x < n - 1) & (y > 1) & (y < n - 1) & (z > 1) & (z < n - 1)
+    rs = np.asarray(A.sum(axis=1)).ravel()
+    np.testing.assert_allclose(rs[inner], 0.0, atol=1e-15)
+    assert np.all(rs[~inner] > 0)
+
+
+def test_constant_kappa_scales_and_variable_kappa_spd():
+    n = 6
+    kap = np.full(n ** 3, 3.5)
+    np.testing.assert_allclose((O.assemble(3, n, kap) - 3.5 * O.assemble(3, n)).toarray(),
+                               0.0, atol=1e-14)
+    kap = W.kappa_lognormal(3, n, seed=3)
+    A = O.assemble(3, n, kap)
+    assert abs(A - A.T).max() < 1e-15
+    sla.cholesky(A.toarray(), lower=True)
+    # one cell on its own: perturbing kappa_c changes exactly the couplings
+    # of that cell's interior vertices by (dk) K_e
+    kap2 = kap.copy()
+    cell = (2, 3, 1)                            # (x, y, z)
+    ci = cell[0] + n * cell[1] + n * n * cell[2]
+    kap2[ci] += 1.0
+    D = (O.assemble(3, n, kap2) - A).toarray()
+    Ke = O.element_matrix(3, 1.0 / n)
+    verts = [((a >> 0) & 1, (a >> 1) & 1, (a >> 2) & 1) for a in range(8)]
+    idx = [(cell[0] + v[0] - 1) + (n - 1) * (cell[1] + v[1] - 1)
+           + (n - 1) ** 2 * (cell[2] + v[2] - 1) for v in verts]
+    want = np.zeros_like(D)
+    for a in range(8):
+        for b in range(8):
+            want[idx[a], idx[b]] += Ke[a, b]
+    np.testing.assert_allclose(D, want, atol=1e-14)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 12), (3, 6)])
+def test_matrix_free_and_row_routes_equal_csr(dim, n, rng):
+    kap = W.kappa_lognormal(dim, n, seed=7)
+    A = O.assemble(dim, n, kap)
+    x = rng.uniform(-1, 1, (n + 1) ** dim)
+    y = O.apply_matfree(dim, n, kap, x.reshape((n + 1,) * dim))
+    xi = O.to_interior(dim, n, x)
+    np.testing.assert_allclose(O.to_interior(dim, n, y), A @ xi, rtol=0, atol=1e-14)
+    nodes = np.stack(O.interior_coords(dim, n), axis=1)[::3]
+    np.testing.assert_allclose(O.apply_rows(dim, n, kap, x, nodes), (A @ xi)[::3],
+                               atol=1e-14)
+
+
+# ---------------------------------------------------------------- transfers
+
+def _interpolate_coarse(dim, nf, coarse_int):
+    """Evaluate the coarse Q1 function (mesh 2h) at every fine interior node
+    directly from the hat-function definition."""
+    nc = nf // 2
+    H = 1.0 / nc
+    cc = np.stack(O.interior_coords(dim, nc), axis=1) * H      # coarse node coords
+    fc = np.stack(O.interior_coords(dim, nf), axis=1) / nf     # fine node coords
+    out = np.zeros(fc.shape[0])
+    for I in range(cc.shape[0]):
+        phi = np.ones(fc.shape[0])
+        for d in range(dim):
+            phi *= np.maximum(0.0, 1.0 - np.abs(fc[:, d] - cc[I, d]) / H)
+        out += coarse_int[I] * phi
+    return out
+
+
+@pytest.mark.parametrize("dim,nf", [(2, 8), (2, 12), (3, 8)])
+def test_prolongation_is_q1_interpolation(dim, nf, rng):
+    c = rng.uniform(-1, 1, (nf // 2 - 1) ** dim)
+    P = O.prolongation(dim, nf)
+    np.testing.assert_allclose(P @ c, _interpolate_coarse(dim, nf, c), atol=1e-14)
+    R = O.restriction(dim, nf)
+    assert abs(R - P.T).max() == 0.0
+    # R has weights 1, 1/2, 1/4(, 1/8): a coarse row sums to at most 2^d
+    # (exactly 2^d away from the boundary) -- no 2^-d scaling
+    assert np.isclose(np.asarray(R.sum(axis=1)).max(), 2.0 ** dim)
+
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (3, 8)])
+@pytest.mark.parametrize("kval", [1.0, 2.5])
+def test_galerkin_identity_constant_kappa(dim, n, kval):
+    """With constant kappa, rediscretisation equals the Galerkin product
+    P^T A_f P; this pins the prolongation weights and R = P^T unscaled."""
+    kf = np.full(n ** dim, kval)
+    kc = O.kappa_coarsen(dim, n, kf)
+    Af = O.assemble(dim, n, kf)
+    Ac = O.assemble(dim, n // 2, kc)
+    P = O.prolongation(dim, n)
+    np.testing.assert_allclose((P.T @ Af @ P).toarray(), Ac.toarray(), atol=1e-14)
+
+
+def test_kappa_geometric_mean():
+    # coarse value of children (1, 4, 16, 64, ...) in a product pattern
+    n = 4
+    k = np.ones((n, n, n))
+    k[::2, ::2, ::2] = 256.0                     # one child of eight is 256
+    kc = O.kappa_coarsen(3, n, k.ravel())
+    np.testing.assert_allclose(kc, 2.0, rtol=1e-15)   # 256^(1/8) = 2
+    kh = O.kappa_hierarchy(3, 8, 3, np.full(512, 5.0))
+    assert [len(x) for x in kh] == [512, 64, 8]
+    np.testing.assert_allclose(kh[2], 5.0, rtol=1e-15)
+
+
+# ---------------------------------------------------------------- exact refs
+
+@pytest.mark.parametrize("dim,n", [(2, 16), (2, 9), (3, 8), (3, 5)])
+def test_dst_solve_equals_sparse_direct(dim, n, rng):
+    b = rng.uniform(-1, 1, (n - 1) ** dim)
+    A = O.assemble(dim, n)
+    u = O.dst_solve(dim, n, b)
+    np.testing.assert_allclose(u, O.sparse_solve(A, b), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(u, O.dense_solve(A, b), rtol=0, atol=1e-12)
+
+
+def test_manufactured_load_and_closed_form_solution():
+    for dim, n in [(2, 16), (2, 64), (3, 8), (3, 16)]:
+        f = lambda *xs, d=dim: d * np.pi ** 2 * np.prod([np.sin(np.pi * x) for x in xs], axis=0)
+        bq = O.assemble_load_quadrature(dim, n, f)
+        b = W.rhs_manufactured(dim, n)
+        np.testing.assert_allclose(b, bq, rtol=1e-12, atol=1e-15)
+        u = O.sparse_solve(O.assemble(dim, n), b)
+        coords = O.interior_coords(dim, n)
+        v = np.prod([np.sin(np.pi * c / n) for c in coords], axis=0)
+        alpha = O.manufactured_factor(dim, 1.0 / n)
+        np.testing.assert_allclose(u, alpha * v, rtol=0, atol=1e-13)
+    # the factor's size: alpha - 1 ~ (d-1)(pi h)^2 / 12
+    assert abs((O.manufactured_factor(2, 1 / 64) - 1) - 2.0081e-4) < 1e-8
+    assert abs((O.manufactured_factor(3, 1 / 256) - 1) - 2.5100e-5) < 1e-9
+
+
+def _l2_error_2d(n, u_int):
+    """|| u - u_h ||_L2 by 4x4 Gauss points per cell, u_h bilinear."""
+    U = O.to_full(2, n, u_int)
+    h = 1.0 / n
+    xi, wq = np.polynomial.legendre.leggauss(4)
+    xi, wq = 0.5 * (xi + 1), 0.5 * wq
+    err = 0.0
+    cy, cx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    for p in range(4):
+        for q in range(4):
+            sx, sy = xi[p], xi[q]
+            uh = (U[cy, cx] * (1 - sx) * (1 - sy) + U[cy, cx + 1] * sx * (1 - sy)
+                  + U[cy + 1, cx] * (1 - sx) * sy + U[cy + 1, cx + 1] * sx * sy)
+            x, y = (cx + sx) * h, (cy + sy) * h
+            ue = np.sin(np.pi * x) * np.sin(np.pi * y)
+            err += wq[p] * wq[q] * h * h * np.sum((ue - uh) ** 2)
+    return np.sqrt(err)
+
+
+def test_l2_convergence_order_two():
+    errs = []
+    for n in (8, 16, 32, 64):
+        H = O.build_hierarchy(2, n, 2, smoother="jacobi")
+        u, k, hist, st = O.solve(H, W.rhs_manufactured(2, n), 1e-12)
+        assert st == "ok"
+        errs.append(_l2_error_2d(n, u))
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.8 < r < 4.2 for r in ratios), ratios
+
+
+# ---------------------------------------------------------------- smoothers
+
+@pytest.mark.parametrize("dim,n,k", [(2, 16, (3, 5)), (3, 8, (1, 6, 2))])
+def test_jacobi_damps_sine_modes_exactly(dim, n, k):
+    h = 1.0 / n
+    coords = O.interior_coords(dim, n)
+    v = np.prod([np.sin(np.pi * kk * c / n) for kk, c in zip(k, coords)], axis=0)
+    kh = [(2 / h) * (1 - np.cos(np.pi * kk / n)) for kk in k]
+    mh = [(h / 3) * (2 + np.cos(np.pi * kk / n)) for kk in k]
+    lam = sum(kh[d] * np.prod([mh[e] for e in range(dim) if e != d]) for d in range(dim))
+    aii = 8 / 3 if dim == 2 else 8 * h / 3
+    A = O.assemble(dim, n)
+    x = O.jacobi_sweep(A, A.diagonal(), v, np.zeros_like(v), 2 / 3)
+    np.testing.assert_allclose(x, (1 - (2 / 3) * lam / aii) * v, atol=1e-14)
+
+
+def test_rb_half_sweep_touches_one_colour_only(rng):
+    n = 8
+    A = O.assemble(3, n)
+    x = rng.uniform(-1, 1, 7 ** 3)
+    b = rng.uniform(-1, 1, 7 ** 3)
+    m = O.colour_mask(3, n, 0)
+    y = O.rb_half_sweep(A, A.diagonal(), x, b, m)
+    np.testing.assert_array_equal(y[~m], x[~m])
+    # updated nodes satisfy their own equation w.r.t. the start values
+    r = b - A @ x
+    np.testing.assert_allclose(y[m], x[m] + r[m] / A.diagonal()[m], atol=1e-15)
+    # colour 0 contains the node (1,1,1)? 1+1+1 odd -> colour 1
+    assert not m[0]
+
+
+# ---------------------------------------------------------------- the cycle
+
+def _cycle_matrix(H, l):
+    """Error propagation matrix of one V-cycle on level l, built densely
+    from its definition: E = S_post (I - P B_{l+1} P^T A) S_pre, with
+    B = A^-1 on the coarsest level and B = (I - E) A^-1 above it."""
+    A = H.A[l].toarray()
+    N = A.shape[0]
+    I = np.eye(N)
+    if l == H.levels - 1:
+        return np.zeros((N, N))
+    Dinv = np.diag(1.0 / np.diag(A))
+    if H.smoother == "jacobi":
+        S = I - H.omega * Dinv @ A
+        Spre = np.linalg.matrix_power(S, H.nu_pre)
+        Spost = np.linalg.matrix_power(S, H.nu_post)
+    else:
+        m0 = np.diag(H.mask[l].astype(float))
+        m1 = I - m0
+        S0 = I - m0 @ Dinv @ A
+        S1 = I - m1 @ Dinv @ A
+        Spre = np.linalg.matrix_power(S1 @ S0, H.nu_pre)       # colour 0 first
+        Spost = np.linalg.matrix_power(S0 @ S1, H.nu_post)     # colour 1 first
+    Ac = H.A[l + 1].toarray()
+    Ec = _cycle_matrix(H, l + 1)
+    B = (np.eye(Ac.shape[0]) - Ec) @ np.linalg.inv(Ac)
+    P = H.P[l].toarray()
+    return Spost @ (I - P @ B @ P.T @ A) @ Spre
+
+
+@pytest.mark.parametrize("dim,n,levels", [(2, 8, 2), (2, 16, 3), (3, 8, 3), (2, 16, 2)])
+@pytest.mark.parametrize("smoother", ["jacobi", "rbgs"])
+def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, rng):
+    H = O.build_hierarchy(dim, n, levels, smoother=smoother)
+    N = (n - 1) ** dim
+    x = rng.uniform(-1, 1, N)
+    b = rng.uniform(-1, 1, N)
+    E = _cycle_matrix(H, 0)
+    ustar = np.linalg.solve(H.A[0].toarray(), b)
+    want = E @ x + (np.eye(N) - E) @ ustar
+    np.testing.assert_allclose(O.vcycle(H, 0, x, b), want, rtol=0, atol=1e-12)
+
+
+def test_h_independent_contraction():
+    for dim, sizes, bound in [(2, (16, 32, 64, 128), 0.12), (3, (8, 16, 32), 0.1)]:
+        rates = []
+        for n in sizes:
+            H = O.build_hierarchy(dim, n, int(np.log2(n)) - (1 if dim == 2 else 0),
+                                  smoother="rbgs")
+            b = W.rhs_uniform(dim, n, 0)
+            u, k, hist, st = O.solve(H, b, 1e-11)
+            rates.append((hist[k] / hist[1]) ** (1.0 / (k - 1)))
+        assert max(rates) < bound, rates
+        assert rates[-1] < 1.6 * rates[0] + 0.02, rates
+
+
+def test_solve_stopping_rule_and_zero_rhs():
+    H = O.build_hierarchy(2, 32, 4, smoother="jacobi")
+    b = W.rhs_uniform(2, 32, 1)
+    u, k, hist, st = O.solve(H, b, 1e-9)
+    assert st == "ok" and hist[0] == 1.0 and len(hist) == k + 1
+    assert hist[k] <= 1e-9 < hist[k - 1]
+    np.testing.assert_allclose(hist[k], np.linalg.norm(b - H.A[0] @ u) / np.linalg.norm(b))
+    u0, k0, h0, s0 = O.solve(H, np.zeros_like(b), 1e-9)
+    assert k0 == 0 and s0 == "ok" and not u0.any()
+    u1, k1, h1, s1 = O.solve(H, b, 1e-30, max_iter=3)
+    assert s1 == "maxit" and k1 == 3
+
+
+@pytest.mark.parametrize("dim,n,levels,kap", [(2, 64, 5, False), (3, 32, 5, False),
+                                              (3, 16, 4, True)])
+def test_fp32_ir_reaches_fp64_accuracy(dim, n, levels, kap):
+    kappa = W.kappa_lognormal(dim, n, 2) if kap else None
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother="rbgs", fp32=True)
+    b = W.rhs_uniform(dim, n, 0)
+    u64, k64, _, s64 = O.solve(H, b, 1e-8)
+    u32, k32, h32, s32 = O.solve_ir(H, b, 1e-8)
+    assert s64 == s32 == "ok"
+    assert abs(k64 - k32) <= 1
+    assert np.linalg.norm(b - H.A[0] @ u32) / np.linalg.norm(b) <= 1e-8
+    ue = O.sparse_solve(H.A[0], b)
+    assert np.linalg.norm(u32 - ue) / np.linalg.norm(ue) < 1e-7
+
+
+def test_variable_kappa_solution_matches_direct():
+    n = 16
+    kap = W.kappa_lognormal(3, n, 5)
+    H = O.build_hierarchy(3, n, 4, kappa=kap)
+    b = W.rhs_ones_load(3, n)
+    u, k, hist, st = O.solve(H, b, 1e-10)
+    assert st == "ok"
+    ue = O.sparse_solve(H.A[0], b)
+    assert np.linalg.norm(u - ue) / np.linalg.norm(ue) < 1e-8
+
+
+# ---------------------------------------------------------------- paper facts
+
+def test_paper_dof_counts():
+    with open(os.path.join(GOLDEN, "paper_counts.json")) as f:
+        g = json.load(f)
+    for e in g["dofs_3d"]:
+        assert (e["n"] + 1) ** 3 == e["dofs"]
+        w = W.Workload("x", 3, e["n"], 1, "rbgs", "stencil", "fp64", 1e-8, "uniform", "none")
+        assert w.dofs == e["dofs"]
+    for e in g["tetrahedra_3d"]:
+        assert 6 * e["n"] ** 3 == e["cells"]
+    hh = g["hierarchy"]
+    assert hh["n_fine"] >> (hh["levels"] - 1) == hh["n_coarse"]
+    # one refinement multiplies cells by 8 in 3D
+    assert (2 * 16) ** 3 // 16 ** 3 == g["refinement_cell_factor_3d"]["factor"]
