@@ -1,0 +1,207 @@
+/*
+ * mg.h -- C ABI of the Q1 geometric-multigrid library for MI355X (gfx950).
+ *
+ * The library solves A u = b, where A is the conforming Q1 finite element
+ * stiffness matrix of -div(kappa grad u) on the unit square (dim = 2) or unit
+ * cube (dim = 3), n cells per direction, homogeneous Dirichlet data, with the
+ * multigrid V-cycle of the paper's Algorithm 1 (Sec. 5.3) on a hierarchy of
+ * nested uniformly refined meshes (Sec. 5.1).  One GPU holds the whole
+ * hierarchy.
+ *
+ * Layouts (all arrays x fastest):
+ *   node vectors  (n_l+1)^dim entries, all nodes of level l including the
+ *                 boundary; boundary entries of vectors the library writes
+ *                 are 0, boundary entries of inputs are ignored;
+ *   cell arrays   n^dim entries (coefficient kappa per cell).
+ * Level 0 is the finest mesh (n cells), level l has n_l = n / 2^l cells.
+ *
+ * Memory: "device" pointers are HIP device memory owned by the caller
+ * (allocated by any allocator, e.g. PyTorch); "host" pointers are ordinary
+ * host memory.  The library never frees caller memory.  A context owns one
+ * device allocation (its arena) for the hierarchy.
+ *
+ * Streams: every call that takes `stream` (a hipStream_t, NULL = the null
+ * stream) enqueues its device work on that stream.  Calls that return
+ * results to the host (mg_solve, mg_norm2) synchronise that stream.
+ *
+ * Errors: every call returns an mg_status; on failure mg_last_error()
+ * returns a message for the calling thread.  A context is not thread safe;
+ * distinct contexts are.
+ */
+#ifndef MG_H
+#define MG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mg_ctx mg_ctx;
+
+typedef enum {
+  MG_OK = 0,
+  MG_E_ARG = 1,        /* invalid argument or option */
+  MG_E_NOMEM = 2,      /* device allocation failed / budget exceeded */
+  MG_E_HIP = 3,        /* a HIP runtime call failed */
+  MG_E_NOT_SPD = 4,    /* coarsest matrix has a non-positive Cholesky pivot */
+  MG_E_MAXIT = 5,      /* max_iter cycles done without reaching tol */
+  MG_E_DIVERGED = 6,   /* residual grew above 1e3 ||b|| or became NaN */
+  MG_E_NONFINITE = 7,  /* NaN or Inf in an input */
+  MG_E_STATE = 8       /* call not valid in the current state */
+} mg_status;
+
+typedef enum { MG_OP_STENCIL = 0, MG_OP_CSR = 1 } mg_opfmt;
+typedef enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1 } mg_smoother;
+typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
+
+/* Flags (mg_options.flags). */
+#define MG_FLAG_NO_GRAPH 1   /* launch kernels one by one instead of replaying
+                                one captured HIP graph per cycle */
+
+typedef struct {
+  int dim;          /* 2 or 3 */
+  int n;            /* cells per direction on the finest level, >= 2 */
+  int levels;       /* >= 1; n divisible by 2^(levels-1); n >> (levels-1) >= 2 */
+  int op;           /* mg_opfmt: matrix-free stencil or CSR matrices */
+  int smoother;     /* mg_smoother */
+  int nu_pre;       /* pre-smoothing sweeps per level, >= 0 */
+  int nu_post;      /* post-smoothing sweeps per level, >= 0 */
+  double omega;     /* Jacobi damping, 0 < omega <= 1 (ignored for RBGS) */
+  int precision;    /* mg_precision */
+  int max_iter;     /* maximum number of cycles / refinement steps, >= 1 */
+  int flags;        /* MG_FLAG_* */
+} mg_options;
+
+/* Fill *o with the defaults: 3D, n = 64, levels = 6, stencil, red-black,
+ * V(2,2), omega = 2/3, FP64, max_iter = 100, flags = 0. */
+void mg_options_default(mg_options* o);
+
+/* Device bytes that mg_setup(o, kappa_dev != NULL, ...) allocates for its
+ * arena (an upper bound when kappa_dev is NULL); 0 if the options are
+ * invalid. */
+size_t mg_footprint_bytes(const mg_options* o);
+
+/* Build the level hierarchy (Sec. 5.1): coefficients per level, operators
+ * (stencil data or CSR matrices with rows blocked by colour, Sec. 4.2.6),
+ * and the FP64 Cholesky factor of the coarsest matrix.
+ *   kappa_dev  device, n^dim cell coefficients (kappa > 0, finite), or NULL
+ *              for kappa = 1 (the Poisson problem).  Copied; the caller may
+ *              free it after the call returns.
+ *   stream     hipStream_t used for setup work (synchronised before return).
+ *   out        receives the new context.
+ * Coarse coefficients are the geometric mean of the 2^dim children.
+ * Errors: MG_E_ARG (options, kappa <= 0), MG_E_NONFINITE (kappa), MG_E_NOMEM,
+ * MG_E_NOT_SPD, MG_E_HIP. */
+mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream,
+                   mg_ctx** out);
+
+/* Solve A u = b to a relative residual ||b - A u||_2 / ||b||_2 <= tol
+ * (2-norm over the unknowns), starting from u = 0, one V(nu_pre, nu_post)
+ * cycle per iteration (Sec. 5.5.1).  With MG_PREC_FP32_IR each iteration is
+ * one FP32 V-cycle on the scaled FP64 residual, followed by an FP64 update
+ * and residual.
+ *   b_dev      device, (n+1)^dim doubles; boundary entries ignored.
+ *   u_dev      device, (n+1)^dim doubles, output; boundary entries set to 0.
+ *              Must not alias b_dev.
+ *   tol        > 0.
+ *   iters      host, out: cycles done.
+ *   hist_host  host, out, room for max_iter + 1 doubles (or NULL):
+ *              hist[0] = 1, hist[k] = relative residual after cycle k.
+ * Returns MG_OK, or MG_E_MAXIT / MG_E_DIVERGED with u, iters and hist
+ * holding the last iterate; b = 0 gives u = 0, iters = 0, MG_OK.
+ * MG_E_NONFINITE if b holds NaN/Inf.  Host-synchronous. */
+mg_status mg_solve(mg_ctx* ctx, const double* b_dev, double* u_dev, double tol,
+                   int* iters, double* hist_host, void* stream);
+
+/* Release a context and its device memory (NULL is ignored). */
+void mg_destroy(mg_ctx* ctx);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* mg_last_error(void);
+
+/* Number of levels and the cells per direction of level l. */
+mg_status mg_level_info(const mg_ctx* ctx, int level, int* n_l, size_t* nodes);
+
+/* ---------------------------------------------------------------------
+ * Single steps of the cycle on caller buffers, for testing and profiling.
+ * `prec` selects the element type of every vector argument: MG_PREC_FP64
+ * (double) or MG_PREC_FP32_IR (float; the level's FP32 operator).  FP32
+ * operators exist only in contexts set up with MG_PREC_FP32_IR.  All
+ * vectors are device node vectors of level `level` unless stated otherwise;
+ * outputs must not alias inputs.  Iterate and correction inputs (x, e) are
+ * read on the boundary too and must hold 0 there (the eliminated Dirichlet
+ * values); boundary entries of right-hand sides and residuals are ignored.
+ * Each call is stream-ordered and returns without synchronising.  The
+ * steps use the context's internal buffers, so they must not overlap with
+ * another call on the same context.
+ * ------------------------------------------------------------------- */
+
+/* r = b - A_l x on the unknowns (Sec. 5.3, "restriction" input); r's
+ * boundary entries are set to 0. */
+mg_status mg_apply_residual(mg_ctx* ctx, int level, int prec, const void* x,
+                            const void* b, void* r, void* stream);
+
+/* One smoothing step (Eq. (1), Algorithm 1 pre-/post-smoothing):
+ *   step 0: damped Jacobi sweep      x_out = x + omega D^-1 (b - A x)
+ *   step 1: red-black half-sweep on colour 0 (sum of node coordinates even)
+ *   step 2: red-black half-sweep on colour 1
+ *   step 3: full red-black sweep, colour 0 then 1 (pre-smoothing order)
+ *   step 4: full red-black sweep, colour 1 then 0 (post-smoothing order)
+ * A half-sweep updates every node of its colour from the values of x at the
+ * start of the half-sweep and copies the other colour.  x_in may be NULL to
+ * mean x = 0.  x_out's boundary entries are set to 0. */
+mg_status mg_apply_smooth(mg_ctx* ctx, int level, int prec, int step,
+                          const void* x_in, const void* b, void* x_out,
+                          void* stream);
+
+/* b_coarse = P^T r (level -> level+1, Sec. 5.4): weights 1, 1/2, 1/4, 1/8,
+ * no 2^-dim scaling.  r is a node vector of `level` (boundary entries
+ * ignored), b_coarse a node vector of level+1. */
+mg_status mg_apply_restrict(mg_ctx* ctx, int level, int prec, const void* r,
+                            void* b_coarse, void* stream);
+
+/* b_coarse = P^T (b - A_l x), fused (no fine residual stored). */
+mg_status mg_apply_residual_restrict(mg_ctx* ctx, int level, int prec,
+                                     const void* x, const void* b,
+                                     void* b_coarse, void* stream);
+
+/* x_fine += P e_coarse (multilinear interpolation, level+1 -> level). */
+mg_status mg_apply_prolong_add(mg_ctx* ctx, int level, int prec,
+                               const void* e_coarse, void* x_fine,
+                               void* stream);
+
+/* x_c = A_c^-1 b_c on the coarsest level by the FP64 Cholesky factor
+ * (Algorithm 1, exact coarsest solve); FP32 vectors are cast to FP64 and
+ * back. */
+mg_status mg_apply_coarse_solve(mg_ctx* ctx, int prec, const void* b_c,
+                                void* x_c, void* stream);
+
+/* One V-cycle on level 0: x <- V-cycle(x, b) in place, in precision prec
+ * (FP32 only in FP32_IR contexts). */
+mg_status mg_vcycle(mg_ctx* ctx, int prec, void* x, const void* b,
+                    void* stream);
+
+/* Squared 2-norm over the unknowns of a level node vector, summed in a
+ * fixed order (run-to-run bitwise reproducible).  Host-synchronous. */
+mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
+                   double* out_host, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing: while enabled, mg_solve launches kernels one by one and
+ * brackets every launch of the kernels matching `kernel_id` on level 0 with
+ * HIP events on the launch stream.  mg_profile_read returns the number of
+ * such launches and their summed duration in milliseconds.
+ *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
+ *              1 = residual (+ norm), 2 = residual + restriction,
+ *              3 = prolongation + add
+ * ------------------------------------------------------------------- */
+mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
+mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MG_H */

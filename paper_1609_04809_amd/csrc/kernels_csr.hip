@@ -1,0 +1,220 @@
+// CSR kernels of the Q1 multigrid V-cycle for gfx950: operator build,
+// residual and smoothing sweeps on an assembled matrix.
+//
+// Row kernels stream the nonzeros of a block's rows: a block of 256 threads
+// owns CSR_ROWS consecutive rows, reads their values and column indices
+// contiguously (coalesced), multiplies by the gathered x and stages the
+// products in LDS; four threads then sum each row in a fixed order.
+#include "mg_internal.h"
+
+namespace mg {
+
+namespace {
+
+constexpr int CSR_ROWS = 64;              // rows per block
+constexpr int CSR_MAX_ROW = 27;           // 3^dim entries at most
+constexpr int CSR_MAXNNZ = CSR_ROWS * CSR_MAX_ROW;
+constexpr int COPY_ROWS = 256;            // rows per copy block
+
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
+// Map dispatch order to a logical order in which every XCD owns one
+// contiguous range of blocks, so neighbouring rows share an L2.
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = bid & 7, idx = bid >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
+__device__ __forceinline__ double block_sum_1d(double v) {
+  __shared__ double ws[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) t = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+  return t;
+}
+
+// MODE 0: out = b - A x (residual) with per-block partial sums of out^2.
+// MODE 1: damped Jacobi update of rows [r_begin, r_end).
+// MODE 2: red-black update of the rows of one colour [r_begin, r_end); the
+//         trailing blocks copy the other colour's rows [c_begin, c_end).
+// ZERO: x = 0 (x is not read).
+template <typename T, int MODE, bool ZERO>
+__global__ __launch_bounds__(256) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end, int nbr,
+                                                  const T* __restrict__ xin,
+                                                  const T* __restrict__ b,
+                                                  T* __restrict__ out, T omega,
+                                                  double* __restrict__ partials, int c_begin,
+                                                  int c_end) {
+  __shared__ int rp[CSR_ROWS + 1];
+  __shared__ T prod[CSR_MAXNNZ];
+  const int tid = threadIdx.x;
+  const int blk = xcd_remap(blockIdx.x, gridDim.x);
+  if (blk >= nbr) {
+    const int r = c_begin + (blk - nbr) * COPY_ROWS + tid;
+    if (r < c_end) {
+      const int node = A.rowmap[r];
+      out[node] = ZERO ? T(0) : xin[node];
+    }
+    return;
+  }
+  const int r0 = r_begin + blk * CSR_ROWS;
+  const int nr = min(CSR_ROWS, r_end - r0);
+  if (tid <= nr) rp[tid] = A.rowptr[r0 + tid];
+  __syncthreads();
+  const int base = rp[0];
+  if (!ZERO) {
+    const int cnt = rp[nr] - base;
+    for (int e = tid; e < cnt; e += 256) prod[e] = A.val[base + e] * xin[A.col[base + e]];
+  }
+  __syncthreads();
+  const int lr = tid >> 2, lane = tid & 3;
+  T s = T(0);
+  if (!ZERO && lr < nr) {
+    const int e1 = rp[lr + 1] - base;
+    for (int e = rp[lr] - base + lane; e < e1; e += 4) s += prod[e];
+  }
+  s += __shfl_xor(s, 1);
+  s += __shfl_xor(s, 2);
+  double sq = 0.0;
+  if (lane == 0 && lr < nr) {
+    const int node = A.rowmap[r0 + lr];
+    const T res = b[node] - s;
+    if (MODE == 0) {
+      out[node] = res;
+      sq = (double)res * (double)res;
+    } else {
+      const T q = res / A.val[rp[lr]];
+      const T x0 = ZERO ? T(0) : xin[node];
+      out[node] = MODE == 1 ? x0 + omega * q : x0 + q;
+    }
+  }
+  if (MODE == 0 && partials != nullptr) {
+    const double t = block_sum_1d(sq);
+    if (tid == 0) partials[blk] = t;
+  }
+}
+
+// One thread per row: diagonal first, then the neighbours q = p + d,
+// d in {-1,0,1}^dim \ {0} in lexicographic (z, y, x) order, that are
+// unknowns.  Entry value: sum over the cells containing both p and q of
+// kappa_c * s_elem * f(#nonzero components of d), with the element-matrix
+// classes f = {4, -1, -2} (2D, s_elem = 1/6) and {4, 0, -1, -1}
+// (3D, s_elem = h/12).  kappa == nullptr means kappa = 1.  Values are
+// formed in FP64 and rounded to T.
+template <typename T, int DIM>
+__global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_elem, int rows,
+                            const int* __restrict__ rowmap, const int* __restrict__ rowptr,
+                            int* __restrict__ col, T* __restrict__ val) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int node = rowmap[r];
+  const int n = g.n;
+  const int i = node % g.sy;
+  const int j = (node / g.sy) % g.sy;
+  const int k = DIM == 3 ? (int)(node / g.sz) : 0;
+  const double f3[4] = {4.0, 0.0, -1.0, -1.0};
+  const double f2[3] = {4.0, -1.0, -2.0};
+  auto weight = [&](int dx, int dy, int dz) -> double {
+    const int cls = abs(dx) + abs(dy) + abs(dz);
+    double ks = 0.0;
+    for (int c = 0; c < (DIM == 3 ? 2 : 1); ++c)
+      for (int bb = 0; bb < 2; ++bb)
+        for (int a = 0; a < 2; ++a) {
+          if (dx != 0 && a != (dx > 0)) continue;
+          if (dy != 0 && bb != (dy > 0)) continue;
+          if (DIM == 3 && dz != 0 && c != (dz > 0)) continue;
+          if (kappa == nullptr) {
+            ks += 1.0;
+          } else {
+            const long cell = (long)(i - 1 + a) + (long)n * (j - 1 + bb) +
+                              (DIM == 3 ? (long)n * n * (k - 1 + c) : 0L);
+            ks += kappa[cell];
+          }
+        }
+    return s_elem * (DIM == 3 ? f3[cls] : f2[cls]) * ks;
+  };
+  int pos = rowptr[r];
+  col[pos] = node;
+  val[pos] = (T)weight(0, 0, 0);
+  ++pos;
+  for (int dz = (DIM == 3 ? -1 : 0); dz <= (DIM == 3 ? 1 : 0); ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (dx == 0 && dy == 0 && dz == 0) continue;
+        const int qi = i + dx, qj = j + dy, qk = k + dz;
+        if (qi < 1 || qi > n - 1 || qj < 1 || qj > n - 1) continue;
+        if (DIM == 3 && (qk < 1 || qk > n - 1)) continue;
+        col[pos] = (int)(qi + qj * g.sy + (long)qk * g.sz);
+        val[pos] = (T)weight(dx, dy, dz);
+        ++pos;
+      }
+}
+
+inline int cdiv_i(long a, long b) { return (int)((a + b - 1) / b); }
+
+template <typename T, int MODE>
+void launch_rows(const CsrOp<T>& A, int rb, int re, int cb, int ce, const T* xin, const T* b,
+                 T* out, T omega, double* partials, hipStream_t s) {
+  const int nbr = cdiv_i(re - rb, CSR_ROWS);
+  const int nbc = cdiv_i(ce - cb, COPY_ROWS);
+  const int nb = nbr + nbc;
+  if (nb == 0) return;
+  if (xin == nullptr)
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, true>), dim3(nb), dim3(256), 0, s, A, rb, re, nbr,
+                       xin, b, out, omega, partials, cb, ce);
+  else
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, false>), dim3(nb), dim3(256), 0, s, A, rb, re, nbr,
+                       xin, b, out, omega, partials, cb, ce);
+}
+
+}  // namespace
+
+long csr_residual_blocks(int rows) { return cdiv_i(rows, CSR_ROWS); }
+
+template <typename T>
+void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
+                      const int* rowmap, const int* rowptr, int* col, T* val, hipStream_t s) {
+  const unsigned blocks = (unsigned)cdiv_i(rows, 256);
+  if (blocks == 0) return;
+  if (g.dim == 2)
+    hipLaunchKernelGGL((k_csr_build<T, 2>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
+                       rows, rowmap, rowptr, col, val);
+  else
+    hipLaunchKernelGGL((k_csr_build<T, 3>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
+                       rows, rowmap, rowptr, col, val);
+}
+
+template <typename T>
+void launch_csr_residual(const Geo&, const CsrOp<T>& A, const T* x, const T* b, T* r,
+                         double* partials, hipStream_t s) {
+  launch_rows<T, 0>(A, 0, A.rows, 0, 0, x, b, r, T(0), partials, s);
+}
+
+template <typename T>
+void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, const T* b,
+                       T* xout, T omega, hipStream_t s) {
+  if (kind == SM_JACOBI) {
+    launch_rows<T, 1>(A, 0, A.rows, 0, 0, xin, b, xout, omega, nullptr, s);
+  } else {
+    const int c = kind == SM_RB1 ? 1 : 0;
+    const int o = 1 - c;
+    launch_rows<T, 2>(A, A.coff[c], A.coff[c + 1], A.coff[o], A.coff[o + 1], xin, b, xout,
+                      omega, nullptr, s);
+  }
+}
+
+#define INST(T)                                                                              \
+  template void launch_csr_build<T>(const Geo&, const double*, double, int, const int*,      \
+                                    const int*, int*, T*, hipStream_t);                      \
+  template void launch_csr_residual<T>(const Geo&, const CsrOp<T>&, const T*, const T*, T*,  \
+                                       double*, hipStream_t);                                \
+  template void launch_csr_smooth<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*,   \
+                                     T*, T, hipStream_t);
+INST(float)
+INST(double)
+#undef INST
+
+}  // namespace mg

@@ -1,0 +1,182 @@
+"""Parity of whole GPU solves with the CPU oracle, determinism and edge cases.
+
+Parity bar for the FP64 paths: the same number of cycles as the oracle
+(+-1); after the same number of cycles ||u_gpu - u_oracle|| <= 1e-8
+||u_oracle||; residual histories within 1e-6 relative.  The FP32-inner /
+FP64-outer form must reach the same tolerance (residual recomputed by the
+oracle) with the oracle's refinement-step count +-1.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1609_04809_amd import workloads as W
+from tests.gpu_util import dev_full, host_full, host_int, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dim, n, levels, smoother, op, kappa, rhs, tol
+    (2, 64, 5, "jacobi", "stencil", False, "manufactured", 1e-10),
+    (2, 64, 5, "jacobi", "csr", False, "manufactured", 1e-10),
+    (2, 128, 6, "rbgs", "stencil", True, "uniform", 1e-8),
+    (3, 32, 5, "rbgs", "stencil", False, "uniform", 1e-8),
+    (3, 32, 5, "rbgs", "csr", False, "uniform", 1e-8),
+    (3, 32, 5, "jacobi", "stencil", False, "uniform", 1e-8),
+    (3, 48, 5, "rbgs", "stencil", True, "ones", 1e-8),
+    (3, 48, 5, "rbgs", "csr", True, "ones", 1e-8),
+]
+
+
+def _ids(c):
+    return f"{c[0]}d-n{c[1]}-{c[3]}-{c[4]}-{'kap' if c[5] else 'poi'}"
+
+
+def _inputs(dim, n, kap, rhs):
+    kappa = W.kappa_lognormal(dim, n, 21) if kap else None
+    if rhs == "manufactured":
+        b = W.rhs_manufactured(dim, n)
+    elif rhs == "ones":
+        b = W.rhs_ones_load(dim, n)
+    else:
+        b = W.rhs_uniform(dim, n, 3)
+    return kappa, b
+
+
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_fp64_solve_matches_oracle(case):
+    torch_cuda()
+    from paper_1609_04809_amd.mg import Solver
+    dim, n, levels, sm, op, kap, rhs, tol = case
+    kappa, b = _inputs(dim, n, kap, rhs)
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=sm)
+    u_or, k_or, hist_or, st_or = O.solve(H, b, tol)
+    assert st_or == "ok"
+    bd = dev_full(dim, n, b)
+    with Solver(dim, n, levels, kappa=kappa, op=op, smoother=sm) as S:
+        u, k, hist, st = S.solve(bd, tol)
+        assert st == "ok"
+        assert abs(k - k_or) <= 1, (k, k_or)
+        kk = min(k, k_or)
+        # a residual near the solution is computed with an absolute error of
+        # a few eps * (|A||u| + |b|) ~ 1e-15 ||b||: relative 1e-6 plus that floor
+        np.testing.assert_allclose(hist[1:kk + 1], hist_or[1:kk + 1], rtol=1e-6, atol=1e-14)
+        # same number of cycles: relative solution error
+        if k != k_or:
+            u_or, _, _, _ = O.solve(H, b, 1e-300, max_iter=k)
+        ug = host_int(dim, n, u)
+        assert np.linalg.norm(ug - u_or) <= 1e-8 * np.linalg.norm(u_or)
+        assert not np.any(host_full(u).reshape((n + 1,) * dim)[(0,) * dim])
+        # the reported residual is the oracle's residual of the returned u
+        rho = np.linalg.norm(b - H.A[0] @ ug) / np.linalg.norm(b)
+        assert abs(rho - hist[k]) <= 1e-6 * rho + 1e-14
+        # bitwise determinism run to run
+        u2, k2, hist2, _ = S.solve(bd, tol)
+        assert k2 == k and hist2 == hist
+        assert np.array_equal(host_full(u2), host_full(u))
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c[3] == "rbgs"], ids=_ids)
+def test_fp32_ir_solve_matches_oracle(case):
+    torch_cuda()
+    from paper_1609_04809_amd.mg import Solver
+    dim, n, levels, sm, op, kap, rhs, tol = case
+    kappa, b = _inputs(dim, n, kap, rhs)
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=sm, fp32=True)
+    u_ir, k_ir, _, st_ir = O.solve_ir(H, b, tol)
+    u64, k64, _, _ = O.solve(H, b, tol)
+    assert st_ir == "ok"
+    with Solver(dim, n, levels, kappa=kappa, op=op, smoother=sm, precision="fp32_ir") as S:
+        u, k, hist, st = S.solve(dev_full(dim, n, b), tol)
+    assert st == "ok"
+    assert abs(k - k_ir) <= 1, (k, k_ir)
+    ug = host_int(dim, n, u)
+    rho = np.linalg.norm(b - H.A[0] @ ug) / np.linalg.norm(b)
+    assert rho <= tol * (1 + 1e-6)
+    # error against the FP64 oracle solution (reported; bounded loosely)
+    err = np.linalg.norm(ug - u64) / np.linalg.norm(u64)
+    assert err < 1e-6, err
+
+
+def test_graph_and_eager_agree_bitwise():
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_GRAPH, Solver
+    dim, n = 3, 32
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 9))
+    outs = []
+    for flags in (0, FLAG_NO_GRAPH):
+        for prec in ("fp64", "fp32_ir"):
+            with Solver(dim, n, 5, precision=prec, flags=flags) as S:
+                u, k, hist, st = S.solve(b, 1e-8)
+                outs.append((prec, k, hist, host_full(u)))
+    for a, c in ((0, 2), (1, 3)):
+        assert outs[a][1] == outs[c][1] and outs[a][2] == outs[c][2]
+        assert np.array_equal(outs[a][3], outs[c][3])
+
+
+def test_repeated_solves_with_new_buffers_recapture():
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import Solver
+    dim, n = 2, 64
+    H = O.build_hierarchy(dim, n, 5, smoother="rbgs")
+    with Solver(dim, n, 5) as S:
+        for seed in range(3):
+            b = W.rhs_uniform(dim, n, seed)
+            u, k, hist, st = S.solve(dev_full(dim, n, b), 1e-9)
+            uo, ko, _, _ = O.solve(H, b, 1e-9)
+            assert abs(k - ko) <= 1 and st == "ok"
+            torch.cuda.synchronize()
+
+
+def test_edge_cases():
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import MgError, Solver
+    # one unknown, one level: the cycle is the exact solve
+    with Solver(3, 2, 1) as S:
+        b = dev_full(3, 2, np.array([0.7]))
+        u, k, hist, st = S.solve(b, 1e-12)
+        A = O.assemble(3, 2)
+        assert st == "ok" and k == 1
+        np.testing.assert_allclose(host_int(3, 2, u), [0.7 / A[0, 0]], rtol=1e-15)
+    # 2D single level with 9 unknowns
+    with Solver(2, 4, 1, smoother="jacobi") as S:
+        bb = W.rhs_uniform(2, 4, 0)
+        u, k, hist, st = S.solve(dev_full(2, 4, bb), 1e-12)
+        assert st == "ok" and k == 1
+        np.testing.assert_allclose(host_int(2, 4, u), O.dense_solve(O.assemble(2, 4), bb),
+                                   rtol=1e-13, atol=1e-15)
+    with Solver(3, 16, 4) as S:
+        # b = 0 -> u = 0, no cycles
+        z = torch.zeros(17 ** 3, dtype=torch.float64, device="cuda")
+        u, k, hist, st = S.solve(z, 1e-8)
+        assert st == "ok" and k == 0 and hist == [1.0] and not torch.any(u)
+        # nonzero boundary entries of b are ignored
+        b = W.rhs_uniform(3, 16, 1)
+        bd = dev_full(3, 16, b)
+        u1, k1, h1, _ = S.solve(bd, 1e-8)
+        bd2 = bd.clone().view(17, 17, 17)
+        bd2[0, :, :] = 5.0
+        bd2[:, :, -1] = -3.0
+        u2, k2, h2, _ = S.solve(bd2.reshape(-1), 1e-8)
+        assert k1 == k2 and h1 == h2 and torch.equal(u1, u2)
+        # max_iter reached: status maxit, last iterate returned
+    with Solver(3, 16, 4, max_iter=2) as S:
+        u, k, hist, st = S.solve(bd, 1e-14)
+        assert st == "maxit" and k == 2 and len(hist) == 3
+        # NaN in b
+        bn = bd.clone()
+        bn[5 + 17 * 6 + 289 * 7] = float("nan")          # interior node (5, 6, 7)
+        with pytest.raises(MgError) as e:
+            S.solve(bn, 1e-8)
+        assert e.value.status == 7
+    # invalid coefficient
+    kap = np.ones(16 ** 3)
+    kap[5] = -1.0
+    with pytest.raises(MgError) as e:
+        Solver(3, 16, 4, kappa=kap)
+    assert e.value.status == 1
+    kap[5] = np.inf
+    with pytest.raises(MgError) as e:
+        Solver(3, 16, 4, kappa=kap)
+    assert e.value.status == 7

@@ -1,0 +1,81 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function declared in include/*.h, validates options and sizes its
+arena."""
+
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_1609_04809_amd import mg
+    if not os.path.exists(mg.LIB_PATH):
+        pytest.skip("libmg.so not built")
+    return mg
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(mg_[a-z0-9_]+)\s*\(", text):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("mg_setup", "mg_solve", "mg_destroy", "mg_footprint_bytes",
+                     "mg_last_error", "mg_server_create", "mg_server_submit",
+                     "mg_server_poll", "mg_server_destroy"):
+        assert required in names, required
+
+
+def test_library_exports_every_declared_symbol():
+    mg = _lib()
+    lib = ctypes.CDLL(mg.LIB_PATH)
+    missing = [n for n in sorted(_declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding wraps exactly the declared functions
+    assert set(mg.SIGNATURES) | set(getattr(mg, "SERVER_SIGNATURES", {})) == _declared()
+
+
+def test_options_validation_and_footprint():
+    mg = _lib()
+    L = mg.lib()
+    o = mg.make_options(3, 256, 8)
+    b64 = L.mg_footprint_bytes(ctypes.byref(o))
+    n = 257 ** 3
+    # at least: two full-grid level-0 FP64 vectors plus the coarse levels
+    assert b64 >= 2 * 8 * n
+    o32 = mg.make_options(3, 256, 8, precision="fp32_ir")
+    assert L.mg_footprint_bytes(ctypes.byref(o32)) > b64
+    ocsr = mg.make_options(3, 128, 7, op="csr")
+    nnz = (3 * 128 - 5) ** 3
+    assert L.mg_footprint_bytes(ctypes.byref(ocsr)) >= nnz * 12
+    for bad in (dict(dim=4, n=8, levels=2), dict(dim=3, n=12, levels=4),
+                dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
+                dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
+                dict(dim=3, n=16, levels=3, max_iter=0)):
+        o = mg.make_options(**bad)
+        assert L.mg_footprint_bytes(ctypes.byref(o)) == 0, bad
+        assert L.mg_last_error().decode()
+        ctx = ctypes.c_void_p()
+        st = L.mg_setup(ctypes.byref(o), None, None, ctypes.byref(ctx))
+        assert st == mg.MG_E_ARG and not ctx.value
+
+
+def test_paper_dof_counts_through_the_library():
+    """(n+1)^3 nodes per level, as the paper counts DOFs (Sec. 6.4)."""
+    mg = _lib()
+    L = mg.lib()
+    o = mg.make_options(3, 512, 6)
+    # 513^3 = 135,005,697 nodes; footprint covers at least two such vectors
+    assert L.mg_footprint_bytes(ctypes.byref(o)) >= 2 * 8 * 135005697
