@@ -59,6 +59,26 @@ def time_solves(S, bd, tol, steps, warmup):
     return (t1 - t0) / steps, k, hist, u
 
 
+def reference_copy(mib):
+    """Attainable bandwidth: a plain device-to-device copy of `mib` MiB
+    (read + write bytes / time), 1 warm-up + up to 10 timed copies."""
+    import torch
+    if mib <= 0:
+        return None
+    x = torch.ones(mib * 131072, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    reps = 10 if mib >= 256 else 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    del x, y
+    return round(2 * mib * 1048576 / dt / 1e9, 1)
+
+
 def csr_halfsweep_bytes(n):
     """Algorithmic bytes of one red-black half-sweep on the 3D 27-point CSR
     operator, averaged over the two colours.  Colour-c launch: its rows'
@@ -186,6 +206,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--workload", default="poisson3d_128_csr_rbgs")
+    ap.add_argument("--copy-mib", type=int, default=1024,
+                    help="size of the reference device copy (attainable bandwidth; "
+                         "also the known-size kernel that scales PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -197,6 +220,8 @@ def main():
     torch.cuda.set_device(0)
     name = args.workload
     w = W.WORKLOADS[name]
+    copy_gbs = reference_copy(args.copy_mib)
+    log(f"[bench] reference copy of {args.copy_mib} MiB: {copy_gbs} GB/s (read + write)")
     log(f"[bench] headline {name}: {args.warmup} warmup + {args.steps} timed solves")
     res, roof, (b, kappa, u, k) = run_workload(name, args.steps, args.warmup,
                                                with_roofline=True)
@@ -238,6 +263,7 @@ def main():
                    "cycles": res["cycles"]},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "copy_reference_GBs": copy_gbs,
         "extra": extra,
     }
     print(json.dumps(out), flush=True)

@@ -59,6 +59,9 @@ typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
 /* Flags (mg_options.flags). */
 #define MG_FLAG_NO_GRAPH 1   /* launch kernels one by one instead of replaying
                                 one captured HIP graph per cycle */
+#define MG_FLAG_NO_TAIL 2    /* cycle every level with grid-wide launches, also
+                                the small coarse levels that otherwise run
+                                inside one workgroup */
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -194,11 +197,71 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  * HIP events on the launch stream.  mg_profile_read returns the number of
  * such launches and their summed duration in milliseconds.
  *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
- *              1 = residual (+ norm), 2 = residual + restriction,
+ *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of independent solves on one GPU.
+ *
+ * A server owns a scheduler thread and a HIP stream.  Requests (any
+ * matrix-free options; right-hand side and optional coefficient given in
+ * host memory) queue in arrival order and are admitted while fewer than
+ * max_slots are in flight and their footprint (mg_footprint_bytes plus
+ * their b and u vectors) fits the remaining HBM budget; a context of the
+ * same shape and precision left by a finished Poisson request is reused.
+ * In flight, every request advances one kernel launch of its V-cycle per
+ * scheduler step, and the steps of all requests with the same kernel,
+ * level shape and precision are fused into one batched launch.  Each
+ * request's result is bitwise the same whether it runs alone or fused.
+ * ------------------------------------------------------------------- */
+typedef struct mg_server mg_server;
+
+typedef struct {
+  uint64_t submitted, admitted, completed, failed;
+  uint64_t launches;          /* batched launches issued */
+  uint64_t fused_ops;         /* per-request ops carried by those launches */
+  uint64_t steps;             /* scheduler steps with work */
+  double busy_s;              /* wall time with requests in flight */
+  size_t hbm_in_use, hbm_peak;
+  int in_flight, queued;
+} mg_server_stats;
+
+/* Start a server on the current device.
+ *   hbm_budget  device bytes the in-flight requests may hold (> 0).
+ *   max_slots   requests in flight at most, 1..1024. */
+mg_status mg_server_create(size_t hbm_budget, int max_slots, mg_server** out);
+
+/* Queue one solve.  o: matrix-free options (op = MG_OP_STENCIL);
+ *   b_host     host, (n+1)^dim doubles, copied before the call returns;
+ *   kappa_host host, n^dim cell coefficients, copied, or NULL (Poisson);
+ *   u_host     host, (n+1)^dim doubles, written before the request is
+ *              reported done; must stay valid until then;
+ *   tol        > 0;  id: out, request id (increasing from 1).
+ * MG_E_ARG for invalid options, MG_E_NOMEM if the request can never fit the
+ * budget, MG_E_STATE after the server stopped. */
+mg_status mg_server_submit(mg_server* srv, const mg_options* o, const double* b_host,
+                           const double* kappa_host, double* u_host, double tol,
+                           uint64_t* id);
+
+/* Collect up to `max` finished requests (non-blocking): their ids, cycle
+ * counts, statuses and, if hist is not NULL, final relative residuals, and
+ * (if t_us is not NULL) submit -> done latencies in microseconds.  Returns
+ * the number in *n_done. */
+mg_status mg_server_poll(mg_server* srv, uint64_t* ids, int* iters, int* status,
+                         double* final_rel_residual, double* latency_us, int max,
+                         int* n_done);
+
+/* Block until no request is queued or in flight (or timeout_s elapsed:
+ * MG_E_STATE). */
+mg_status mg_server_drain(mg_server* srv, double timeout_s);
+
+mg_status mg_server_get_stats(mg_server* srv, mg_server_stats* out);
+
+/* Stop the scheduler (finishing in-flight work) and free everything. */
+void mg_server_destroy(mg_server* srv);
 
 #ifdef __cplusplus
 }

@@ -2,19 +2,41 @@
 // residual and smoothing sweeps on an assembled matrix.
 //
 // Row kernels stream the nonzeros of a block's rows: a block of 256 threads
-// owns CSR_ROWS consecutive rows, reads their values and column indices
+// owns ROWS consecutive rows, reads their values and column indices
 // contiguously (coalesced), multiplies by the gathered x and stages the
-// products in LDS; four threads then sum each row in a fixed order.
+// products in LDS; 256 / ROWS threads then sum each row in a fixed order.
+#include <cstdlib>
+
 #include "mg_internal.h"
 
 namespace mg {
 
 namespace {
 
-constexpr int CSR_ROWS = 64;              // rows per block
+constexpr int CSR_THREADS = 256;
 constexpr int CSR_MAX_ROW = 27;           // 3^dim entries at most
-constexpr int CSR_MAXNNZ = CSR_ROWS * CSR_MAX_ROW;
-constexpr int COPY_ROWS = 256;            // rows per copy block
+constexpr int CSR_MIN_ROWS = 32;          // smallest rows-per-block variant
+
+// Launch variants of the row kernel: rows per block and whether the matrix
+// is read with non-temporal loads (it is streamed once per sweep, so it
+// need not stay in the caches that hold x).
+struct CsrVariant {
+  int rows;
+  bool nt;
+  bool remap;
+};
+constexpr CsrVariant kCsrVariants[] = {{64, false, true}, {64, false, false}, {32, false, true},
+                                       {128, false, true}, {64, true, true}};
+constexpr int kNumCsrVariants = sizeof(kCsrVariants) / sizeof(kCsrVariants[0]);
+
+int csr_variant() {
+  static int v = [] {
+    const char* e = getenv("MG_CSR_VARIANT");
+    int k = e ? atoi(e) : 0;
+    return (k >= 0 && k < kNumCsrVariants) ? k : 0;
+  }();
+  return v;
+}
 
 // Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
 // Map dispatch order to a logical order in which every XCD owns one
@@ -26,7 +48,7 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
 }
 
 __device__ __forceinline__ double block_sum_1d(double v) {
-  __shared__ double ws[4];
+  __shared__ double ws[CSR_THREADS / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
@@ -36,48 +58,64 @@ __device__ __forceinline__ double block_sum_1d(double v) {
   return t;
 }
 
+template <bool NT, typename V>
+__device__ __forceinline__ V ld_stream(const V* p) {
+  if (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+
 // MODE 0: out = b - A x (residual) with per-block partial sums of out^2.
 // MODE 1: damped Jacobi update of rows [r_begin, r_end).
 // MODE 2: red-black update of the rows of one colour [r_begin, r_end); the
-//         trailing blocks copy the other colour's rows [c_begin, c_end).
+//         other colour's unknowns are copied alongside (see below).
 // ZERO: x = 0 (x is not read).
-template <typename T, int MODE, bool ZERO>
-__global__ __launch_bounds__(256) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end, int nbr,
-                                                  const T* __restrict__ xin,
-                                                  const T* __restrict__ b,
-                                                  T* __restrict__ out, T omega,
-                                                  double* __restrict__ partials, int c_begin,
-                                                  int c_end) {
-  __shared__ int rp[CSR_ROWS + 1];
-  __shared__ T prod[CSR_MAXNNZ];
+// Phase 1 issues all column and value loads of a thread before any gather,
+// so that about 2 * PER loads per thread are in flight.
+template <typename T, int MODE, bool ZERO, int ROWS, bool NT, bool REMAP>
+__global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end,
+                                                          const T* __restrict__ xin,
+                                                          const T* __restrict__ b,
+                                                          T* __restrict__ out, T omega,
+                                                          double* __restrict__ partials) {
+  constexpr int MAXNNZ = ROWS * CSR_MAX_ROW;
+  constexpr int PER = (MAXNNZ + CSR_THREADS - 1) / CSR_THREADS;
+  constexpr int TPR = CSR_THREADS / ROWS;  // threads summing one row
+  __shared__ int rp[ROWS + 1];
+  __shared__ T prod[MAXNNZ];
   const int tid = threadIdx.x;
-  const int blk = xcd_remap(blockIdx.x, gridDim.x);
-  if (blk >= nbr) {
-    const int r = c_begin + (blk - nbr) * COPY_ROWS + tid;
-    if (r < c_end) {
-      const int node = A.rowmap[r];
-      out[node] = ZERO ? T(0) : xin[node];
-    }
-    return;
-  }
-  const int r0 = r_begin + blk * CSR_ROWS;
-  const int nr = min(CSR_ROWS, r_end - r0);
+  const int blk = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int r0 = r_begin + blk * ROWS;
+  const int nr = min(ROWS, r_end - r0);
   if (tid <= nr) rp[tid] = A.rowptr[r0 + tid];
   __syncthreads();
   const int base = rp[0];
   if (!ZERO) {
     const int cnt = rp[nr] - base;
-    for (int e = tid; e < cnt; e += 256) prod[e] = A.val[base + e] * xin[A.col[base + e]];
+    int cl[PER];
+    T vl[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * CSR_THREADS;
+      if (e < cnt) {
+        cl[q] = ld_stream<NT>(A.col + base + e);
+        vl[q] = ld_stream<NT>(A.val + base + e);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = tid + q * CSR_THREADS;
+      if (e < cnt) prod[e] = vl[q] * xin[cl[q]];
+    }
   }
   __syncthreads();
-  const int lr = tid >> 2, lane = tid & 3;
+  const int lr = tid / TPR, lane = tid % TPR;
   T s = T(0);
   if (!ZERO && lr < nr) {
     const int e1 = rp[lr + 1] - base;
-    for (int e = rp[lr] - base + lane; e < e1; e += 4) s += prod[e];
+    for (int e = rp[lr] - base + lane; e < e1; e += TPR) s += prod[e];
   }
-  s += __shfl_xor(s, 1);
-  s += __shfl_xor(s, 2);
+#pragma unroll
+  for (int off = 1; off < TPR; off <<= 1) s += __shfl_xor(s, off);
   double sq = 0.0;
   if (lane == 0 && lr < nr) {
     const int node = A.rowmap[r0 + lr];
@@ -89,6 +127,15 @@ __global__ __launch_bounds__(256) void k_csr_rows(CsrOp<T> A, int r_begin, int r
       const T q = res / A.val[rp[lr]];
       const T x0 = ZERO ? T(0) : xin[node];
       out[node] = MODE == 1 ? x0 + omega * q : x0 + q;
+      if (MODE == 2) {
+        // Copy the other colour along the grid row: node p+1 (and p-1 for
+        // the colour's first node at x = 2).  Every other-colour unknown of
+        // the row is copied exactly once, by the block that also writes its
+        // neighbour, so each cache line is written by one block.
+        const int ix = (int)(node % A.sy);
+        if (ix + 1 <= A.n - 1) out[node + 1] = ZERO ? T(0) : xin[node + 1];
+        if (ix == 2) out[node - 1] = ZERO ? T(0) : xin[node - 1];
+      }
     }
   }
   if (MODE == 0 && partials != nullptr) {
@@ -155,24 +202,35 @@ __global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_el
 
 inline int cdiv_i(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <typename T, int MODE>
-void launch_rows(const CsrOp<T>& A, int rb, int re, int cb, int ce, const T* xin, const T* b,
-                 T* out, T omega, double* partials, hipStream_t s) {
-  const int nbr = cdiv_i(re - rb, CSR_ROWS);
-  const int nbc = cdiv_i(ce - cb, COPY_ROWS);
-  const int nb = nbr + nbc;
+template <typename T, int MODE, int ROWS, bool NT, bool REMAP>
+void launch_rows_v(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
+                   double* partials, hipStream_t s) {
+  const int nb = cdiv_i(re - rb, ROWS);
   if (nb == 0) return;
   if (xin == nullptr)
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, true>), dim3(nb), dim3(256), 0, s, A, rb, re, nbr,
-                       xin, b, out, omega, partials, cb, ce);
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, true, ROWS, NT, REMAP>), dim3(nb), dim3(CSR_THREADS),
+                       0, s, A, rb, re, xin, b, out, omega, partials);
   else
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, false>), dim3(nb), dim3(256), 0, s, A, rb, re, nbr,
-                       xin, b, out, omega, partials, cb, ce);
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, false, ROWS, NT, REMAP>), dim3(nb),
+                       dim3(CSR_THREADS), 0, s, A, rb, re, xin, b, out, omega, partials);
+}
+
+template <typename T, int MODE>
+void launch_rows(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
+                 double* partials, hipStream_t s) {
+  switch (csr_variant()) {
+    case 1: launch_rows_v<T, MODE, 64, false, false>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 2: launch_rows_v<T, MODE, 32, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 3: launch_rows_v<T, MODE, 128, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 4: launch_rows_v<T, MODE, 64, true, true>(A, rb, re, xin, b, out, omega, partials, s); break;
+    default: launch_rows_v<T, MODE, 64, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
+  }
 }
 
 }  // namespace
 
-long csr_residual_blocks(int rows) { return cdiv_i(rows, CSR_ROWS); }
+long csr_residual_blocks(int rows) { return cdiv_i(rows, kCsrVariants[csr_variant()].rows); }
+long csr_residual_blocks_max(int rows) { return cdiv_i(rows, CSR_MIN_ROWS); }
 
 template <typename T>
 void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
@@ -190,19 +248,17 @@ void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows
 template <typename T>
 void launch_csr_residual(const Geo&, const CsrOp<T>& A, const T* x, const T* b, T* r,
                          double* partials, hipStream_t s) {
-  launch_rows<T, 0>(A, 0, A.rows, 0, 0, x, b, r, T(0), partials, s);
+  launch_rows<T, 0>(A, 0, A.rows, x, b, r, T(0), partials, s);
 }
 
 template <typename T>
 void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s) {
   if (kind == SM_JACOBI) {
-    launch_rows<T, 1>(A, 0, A.rows, 0, 0, xin, b, xout, omega, nullptr, s);
+    launch_rows<T, 1>(A, 0, A.rows, xin, b, xout, omega, nullptr, s);
   } else {
     const int c = kind == SM_RB1 ? 1 : 0;
-    const int o = 1 - c;
-    launch_rows<T, 2>(A, A.coff[c], A.coff[c + 1], A.coff[o], A.coff[o + 1], xin, b, xout,
-                      omega, nullptr, s);
+    launch_rows<T, 2>(A, A.coff[c], A.coff[c + 1], xin, b, xout, omega, nullptr, s);
   }
 }
 

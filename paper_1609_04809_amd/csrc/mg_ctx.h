@@ -1,0 +1,121 @@
+// Internal definitions shared by the solver runtime and the serving
+// scheduler: the context (level hierarchy and its device buffers) and the
+// recorded form of one kernel launch of a V-cycle ("op"), which the
+// scheduler fuses across requests.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mg.h"
+#include "mg_internal.h"
+
+namespace mg {
+
+struct Level {
+  Geo g;
+  // FP64 vectors (x and b of level 0 are the caller's)
+  double *x64 = nullptr, *b64 = nullptr, *t64 = nullptr, *r64 = nullptr;
+  // FP32 vectors (FP32_IR contexts)
+  float *x32 = nullptr, *b32 = nullptr, *t32 = nullptr, *r32 = nullptr;
+  // coefficients per cell
+  double* kap64 = nullptr;
+  float* kap32 = nullptr;
+  // CSR
+  int *rowptr = nullptr, *col = nullptr, *rowmap = nullptr;
+  double* val64 = nullptr;
+  float* val32 = nullptr;
+  int rows = 0;
+  long nnz = 0;
+  int coff[3] = {0, 0, 0};
+  StencilParams<double> st64{};
+  StencilParams<float> st32{};
+  CsrOp<double> csr64{};
+  CsrOp<float> csr32{};
+};
+
+enum OpCode {
+  OC_SMOOTH = 0,
+  OC_RESID,
+  OC_RESTRICT,
+  OC_PROLONG,
+  OC_COARSE,
+  OC_NORM2,
+  OC_REDUCE,
+  OC_SCALE_CAST,
+  OC_IR_UPDATE,
+  OC_TAIL,
+  OC_FILL,
+  OC_COPY,
+  OC_CSR_SMOOTH,
+  OC_CSR_RESID,
+};
+
+// One kernel launch of a cycle for one request.  Ops with equal keys (all
+// fields but `item`, `level` and `csr`) can run as one batched launch.
+struct OpRec {
+  int code = 0;
+  int prec = 0;     // 0 double, 1 float
+  int sub = 0;      // OC_SMOOTH: kind | zero << 4;  OC_RESID: norm
+  int level = 0;    // level index within its context (profiling)
+  Geo g{}, gc{};    // level geometry and the next coarser one
+  int opkind = 0;   // OP_CONST / OP_KAPPA
+  double wc = 0, w1 = 0, w2 = 0, s = 0, omega = 0;
+  int m = 0;        // coarsest unknowns
+  long count = 0;   // OC_REDUCE: partials; OC_FILL / OC_COPY: elements
+  Item item{};
+  const void* csr = nullptr;  // CsrOp<T>* (CSR ops, not batchable)
+};
+
+bool same_key(const OpRec& a, const OpRec& b);
+bool batchable(const OpRec& a);
+// Launch ops[0..n) (equal keys, n <= kMaxBatch) as one batched launch.
+void launch_ops(const OpRec* const* ops, int n, hipStream_t s);
+
+}  // namespace mg
+
+struct mg_ctx {
+  mg_options o{};
+  int L = 0;
+  bool kappa = false;
+  bool ir = false;
+  bool csr = false;
+  int tail0 = -1;  // first level cycled by the one-workgroup tail kernel (-1: none)
+  std::vector<mg::Level> lv;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  double* Lc = nullptr;  // coarsest Cholesky factor, row major
+  int m = 0;
+  double* partials = nullptr;
+  long npart = 0;
+  double* scal = nullptr;       // device scalars: [0] residual norm^2, [1] ||b||^2, [2] scratch
+  int* ibuf = nullptr;          // device ints (setup checks)
+  void* tail64 = nullptr;       // TailDesc<double> (device)
+  void* tail32 = nullptr;       // TailDesc<float> (device)
+  double* pinned = nullptr;     // host pinned scalars
+  hipStream_t cap = nullptr;    // private stream for graph capture
+  hipGraphExec_t gexec = nullptr;
+  const void* gkey[3] = {nullptr, nullptr, nullptr};
+  // profiling
+  int prof_kernel = -1;
+  bool prof_on = false;
+  long prof_launches = 0;
+  double prof_ms = 0.0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+};
+
+namespace mg {
+
+// Ops of one iteration of mg_solve for the context (u, b: level-0 FP64
+// vectors), in launch order.
+void record_iteration(mg_ctx* c, double* u, const double* b, std::vector<OpRec>& out);
+// Ops that prepare a solve: u = 0, ||b||^2 into scal[1], and for FP32-IR
+// r = b with ||r||^2 in scal[0].
+void record_prologue(mg_ctx* c, double* u, const double* b, std::vector<OpRec>& out);
+size_t plan_bytes(const mg_options& o, bool has_kappa);
+
+}  // namespace mg

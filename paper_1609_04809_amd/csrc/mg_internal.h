@@ -1,5 +1,6 @@
 // Internal interfaces of the Q1 multigrid library: level geometry, operator
-// descriptors and the host-side launchers of the HIP kernels.
+// descriptors, batched launch descriptors and the host-side launchers of
+// the HIP kernels.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -31,20 +32,50 @@ inline Geo make_geo(int dim, int n) {
 // Largest coarsest system (unknowns) solved by the one-block Cholesky kernel.
 constexpr int kCoarseMaxUnknowns = 4096;
 
+// Levels with at most this many unknowns are cycled by one workgroup per
+// request (the "tail" of the V-cycle), in one launch.
+constexpr int kTailMaxUnknowns = 4096;
+constexpr int kTailMaxLevels = 12;
+
+// Rows of a 3D CSR colour are ordered by tiles of kCsrTile x kCsrTile grid
+// rows in (y, z).
+constexpr int kCsrTile = 8;
+
+// Requests fused into one batched launch at most.
+constexpr int kMaxBatch = 16;
+
 enum OpKind { OP_CONST = 0, OP_KAPPA = 1 };
 
-// Matrix-free Q1 operator of one level.
+// Launch-wide parameters of the matrix-free Q1 operator of one level; the
+// per-cell coefficients of OP_KAPPA travel per request in Item::kappa.
 //  OP_CONST: kappa = 1, the assembled stencil weights
 //     2D: wc = 8/3, w1 = -1/3 (x/y neighbours), w2 = -1/3 (diagonals)
 //     3D: wc = 8h/3, w1 = -h/6 (edge neighbours), w2 = -h/12 (corners);
 //         face neighbours have weight 0.
-//  OP_KAPPA: kappa per cell; element matrix scale s = 1/6 (2D), h/12 (3D).
+//  OP_KAPPA: element matrix scale s = 1/6 (2D), h/12 (3D).
 template <typename T>
-struct StencilOp {
+struct StencilParams {
   int kind;
-  const T* kappa;  // n^dim cells, x fastest
   T wc, w1, w2;
   T s;
+};
+
+// One request's buffers in a batched launch.  The role of each pointer is
+// given at each launcher below.
+struct Item {
+  const void* a;
+  const void* b;
+  void* c;
+  const void* kappa;
+  double* partials;
+  double* scal;
+  const double* L;
+  int flag;
+};
+
+struct Batch {
+  Item it[kMaxBatch];
+  int count;
 };
 
 // CSR operator of one level.  Rows are the unknowns, blocked by colour
@@ -58,63 +89,95 @@ struct CsrOp {
   const int* rowmap;
   int rows;
   int coff[3];  // colour c rows: [coff[c], coff[c+1])
+  int n;        // cells per direction of the level
+  long sy;      // node stride in y
 };
 
 // Smoothing step kinds (mg_apply_smooth "step" 0..2).
 enum SmoothKind { SM_JACOBI = 0, SM_RB0 = 1, SM_RB1 = 2 };
 
+// Device-resident description of the tail levels l0..L-1 of one request:
+// the V-cycle below level l0 runs inside one workgroup.
+template <typename T>
+struct TailLevel {
+  int n;
+  const T* kappa;  // OP_KAPPA cells or nullptr
+  T* x;            // iterate
+  T* t;            // spare for out-of-place sweeps
+  T* b;            // right-hand side
+  T* r;            // residual scratch
+  T wc, w1, w2, s; // operator parameters of the level
+};
+template <typename T>
+struct TailDesc {
+  int nlev;        // levels in the tail (the last one is the coarsest)
+  int dim;
+  int kind;        // OpKind
+  int smoother;    // 0 Jacobi, 1 red-black
+  int nu_pre, nu_post;
+  T omega;
+  int m;           // coarsest unknowns
+  const double* L; // coarsest Cholesky factor
+  TailLevel<T> lv[kTailMaxLevels];
+};
+
 // ---- grid kernels (kernels_grid.hip) -------------------------------------
 template <typename T> void launch_fill(T* v, long count, T val, hipStream_t s);
 template <typename T> void launch_copy(const T* a, T* b, long count, hipStream_t s);
 
-// Number of per-block partial sums written by the norm-producing launches.
+// Number of per-block partial sums of a norm-producing launch per request.
 long grid_blocks(const Geo& g);
 
+// r = b - A x (+ per-block partial sums of r^2 when `norm`):
+//   a = x, b = b, c = r, kappa, partials.
 template <typename T>
-void launch_residual(const Geo& g, const StencilOp<T>& op, const T* x,
-                     const T* b, T* r, double* partials, hipStream_t s);
-template <typename T>
-void launch_smooth(const Geo& g, const StencilOp<T>& op, int kind,
-                   const T* xin, const T* b, T* xout, T omega, hipStream_t s);
-template <typename T>
-void launch_restrict(const Geo& gf, const Geo& gc, const T* r, T* bc,
+void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
                      hipStream_t s);
+// One smoothing step (SmoothKind); a == nullptr means x = 0 (then for every
+// item):  a = x_in, b = b, c = x_out, kappa.
 template <typename T>
-void launch_resid_restrict(const Geo& gf, const Geo& gc, const StencilOp<T>& op,
-                           const T* x, const T* b, T* bc, hipStream_t s);
+void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
+                   const Batch& B, hipStream_t s);
+// b_c = P^T r:  a = r (fine), c = b_c (coarse).
 template <typename T>
-void launch_prolong_add(const Geo& gf, const Geo& gc, const T* e, T* x,
-                        hipStream_t s);
+void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s);
+// x += P e:  a = e (coarse), c = x (fine).
 template <typename T>
-void launch_coarse_solve(const Geo& gc, const double* L, int m, const T* bc,
-                         T* xc, hipStream_t s);
+void launch_prolong_add(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s);
+// Coarsest solve, one block per request:  b = b_c, c = x_c, L (m x m).
 template <typename T>
-void launch_norm2_partial(const Geo& g, const T* v, double* partials,
-                          hipStream_t s);
-void launch_reduce_final(const double* partials, long count, double* out,
-                         hipStream_t s);
-void launch_scale_cast(const Geo& g, const double* r, const double* norm2,
-                       float* b32, hipStream_t s);
-void launch_ir_update(const Geo& g, double* u, const float* c,
-                      const double* norm2, hipStream_t s);
-void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc,
-                          hipStream_t s);
+void launch_coarse_solve(const Geo& gc, int m, const Batch& B, hipStream_t s);
+// Per-block partial sums of v^2:  a = v, partials.
+template <typename T>
+void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s);
+// scal = sum of partials[0..count), fixed order, one block per request.
+void launch_reduce_final(long count, const Batch& B, hipStream_t s);
+// b32 = float(r / sqrt(scal)):  a = r (double), c = b32 (float), scal.
+void launch_scale_cast(const Geo& g, const Batch& B, hipStream_t s);
+// u += sqrt(scal) * double(c):  a = c (float), c = u (double), scal.
+void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s);
+// The V-cycle on the tail levels, one block per request:  a = TailDesc<T>*
+// (device), b = level-l0 right-hand side, c = level-l0 iterate (updated in
+// place), flag = 1 when the level-l0 iterate starts at 0 (not read).
+template <typename T>
+void launch_tail(int dim, int kind, const Batch& B, hipStream_t s);
+
+void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s);
 void launch_cast_f32(const double* a, float* b, long count, hipStream_t s);
-void launch_count_bad_kappa(const double* k, long count, int* bad_nonpos,
-                            int* bad_nonfinite, hipStream_t s);
+void launch_count_bad_kappa(const double* k, long count, int* bad_nonpos, int* bad_nonfinite,
+                            hipStream_t s);
 
 // ---- CSR kernels (kernels_csr.hip) ----------------------------------------
 template <typename T>
 void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
-                      const int* rowmap, const int* rowptr, int* col, T* val,
-                      hipStream_t s);
+                      const int* rowmap, const int* rowptr, int* col, T* val, hipStream_t s);
 template <typename T>
-void launch_csr_residual(const Geo& g, const CsrOp<T>& A, const T* x,
-                         const T* b, T* r, double* partials, hipStream_t s);
-long csr_residual_blocks(int rows);
+void launch_csr_residual(const Geo& g, const CsrOp<T>& A, const T* x, const T* b, T* r,
+                         double* partials, hipStream_t s);
+long csr_residual_blocks(int rows);      // partial sums of one residual launch
+long csr_residual_blocks_max(int rows);  // upper bound over launch variants
 template <typename T>
-void launch_csr_smooth(const Geo& g, const CsrOp<T>& A, int kind,
-                       const T* xin, const T* b, T* xout, T omega,
-                       hipStream_t s);
+void launch_csr_smooth(const Geo& g, const CsrOp<T>& A, int kind, const T* xin, const T* b,
+                       T* xout, T omega, hipStream_t s);
 
 }  // namespace mg

@@ -2,28 +2,33 @@
 // arena, the level hierarchy (Sec. 5.1), the V-cycle driver (Algorithm 1,
 // Sec. 5.3), the outer cycle iteration (Sec. 5.5.1), the FP32-inner /
 // FP64-outer refinement loop, HIP graph replay of whole cycles and the
-// C ABI declared in mg.h.
+// solver part of the C ABI declared in mg.h.
+//
+// A cycle is produced as a list of recorded kernel launches (OpRec); a
+// single solve launches them one by one (or replays them as one captured
+// graph), the serving scheduler fuses equal ops of different requests into
+// batched launches.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
-#include <cstdlib>
-#include <utility>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
+#include <utility>
 #include <vector>
 
-#include "../../include/mg.h"
-#include "mg_internal.h"
+#include "mg_ctx.h"
 
 using namespace mg;
 
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
-namespace {
+namespace mg {
 thread_local std::string g_err;
 
 mg_status fail(mg_status st, const char* fmt, ...) {
@@ -35,6 +40,7 @@ mg_status fail(mg_status st, const char* fmt, ...) {
   g_err = buf;
   return st;
 }
+}  // namespace mg
 
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
@@ -44,65 +50,9 @@ mg_status fail(mg_status st, const char* fmt, ...) {
                   __FILE__, __LINE__);                                             \
   } while (0)
 
-constexpr int kCoarseMax = kCoarseMaxUnknowns;
-constexpr size_t kAlign = 256;
-
-}  // namespace
-
-// ---------------------------------------------------------------------------
-// context
-// ---------------------------------------------------------------------------
-struct Level {
-  Geo g;
-  // FP64 vectors (x and b of level 0 are the caller's)
-  double *x64 = nullptr, *b64 = nullptr, *t64 = nullptr, *r64 = nullptr;
-  // FP32 vectors (FP32_IR contexts)
-  float *x32 = nullptr, *b32 = nullptr, *t32 = nullptr, *r32 = nullptr;
-  // coefficients per cell
-  double* kap64 = nullptr;
-  float* kap32 = nullptr;
-  // CSR
-  int *rowptr = nullptr, *col = nullptr, *rowmap = nullptr;
-  double* val64 = nullptr;
-  float* val32 = nullptr;
-  int rows = 0;
-  long nnz = 0;
-  int coff[3] = {0, 0, 0};
-  StencilOp<double> st64{};
-  StencilOp<float> st32{};
-  CsrOp<double> csr64{};
-  CsrOp<float> csr32{};
-};
-
-struct mg_ctx {
-  mg_options o{};
-  int L = 0;
-  bool kappa = false;
-  bool ir = false;
-  bool csr = false;
-  std::vector<Level> lv;
-  char* arena = nullptr;
-  size_t arena_bytes = 0;
-  double* Lc = nullptr;  // coarsest Cholesky factor, row major
-  int m = 0;
-  double* partials = nullptr;
-  long npart = 0;
-  double* scal = nullptr;      // device scalars: [0] residual norm^2, [1] ||b||^2
-  int* ibuf = nullptr;         // device ints (setup checks)
-  double* pinned = nullptr;    // host pinned scalars
-  hipStream_t cap = nullptr;   // private stream for graph capture
-  hipGraphExec_t gexec = nullptr;
-  const void* gkey[3] = {nullptr, nullptr, nullptr};
-  // profiling
-  int prof_kernel = -1;
-  bool prof_on = false;
-  long prof_launches = 0;
-  double prof_ms = 0.0;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
-};
-
 namespace {
+
+constexpr size_t kAlign = 256;
 
 // Bump allocator over the arena; with base == nullptr it only measures.
 struct Planner {
@@ -118,6 +68,14 @@ struct Planner {
   }
 };
 
+long ipow(long b, int e) {
+  long r = 1;
+  while (e--) r *= b;
+  return r;
+}
+
+long csr_nnz(int dim, int n) { return ipow(3L * n - 5, dim); }
+
 bool valid_options(const mg_options* o, std::string& why) {
   char buf[256];
   if (!o) { why = "options is NULL"; return false; }
@@ -125,7 +83,8 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->n < 2) { why = "n must be >= 2"; return false; }
   if (o->levels < 1 || o->levels > 30) { why = "levels must be in 1..30"; return false; }
   if (o->n % (1 << (o->levels - 1)) != 0 || (o->n >> (o->levels - 1)) < 2) {
-    snprintf(buf, sizeof buf, "n = %d needs to be divisible by 2^(levels-1) with n >> (levels-1) >= 2", o->n);
+    snprintf(buf, sizeof buf,
+             "n = %d needs to be divisible by 2^(levels-1) with n >> (levels-1) >= 2", o->n);
     why = buf;
     return false;
   }
@@ -136,30 +95,33 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
   const long nc = o->n >> (o->levels - 1);
-  long m = 1;
-  for (int d = 0; d < o->dim; ++d) m *= (nc - 1);
-  if (m > kCoarseMax) {
-    snprintf(buf, sizeof buf, "coarsest level has %ld unknowns (max %d): use more levels", m, kCoarseMax);
+  const long m = ipow(nc - 1, o->dim);
+  if (m > kCoarseMaxUnknowns) {
+    snprintf(buf, sizeof buf, "coarsest level has %ld unknowns (max %d): use more levels", m,
+             kCoarseMaxUnknowns);
     why = buf;
     return false;
   }
-  const long nodes = o->dim == 3 ? (long)(o->n + 1) * (o->n + 1) * (o->n + 1) : (long)(o->n + 1) * (o->n + 1);
+  const long nodes = ipow(o->n + 1L, o->dim);
   if (nodes >= (1L << 31)) { why = "grid too large for 32-bit node indices"; return false; }
-  if (o->op == MG_OP_CSR) {
-    long nnz = 1;
-    for (int d = 0; d < o->dim; ++d) nnz *= (3L * o->n - 5);
-    if (nnz >= (1L << 31)) { why = "CSR matrix too large for 32-bit offsets"; return false; }
+  if (o->op == MG_OP_CSR && csr_nnz(o->dim, o->n) >= (1L << 31)) {
+    why = "CSR matrix too large for 32-bit offsets";
+    return false;
   }
   return true;
 }
 
-long ipow(long b, int e) {
-  long r = 1;
-  while (e--) r *= b;
-  return r;
+// First level handled by the tail kernel: the finest level from which on
+// every level has at most kTailMaxUnknowns unknowns (matrix-free operator
+// only, and at most kTailMaxLevels levels).
+int tail_start(const mg_options& o) {
+  if (o.op != MG_OP_STENCIL || (o.flags & MG_FLAG_NO_TAIL)) return -1;
+  int l0 = o.levels - 1;
+  while (l0 > 0 && ipow((o.n >> (l0 - 1)) - 1, o.dim) <= kTailMaxUnknowns &&
+         o.levels - (l0 - 1) <= kTailMaxLevels)
+    --l0;
+  return l0;
 }
-
-long csr_nnz(int dim, int n) { return ipow(3L * n - 5, dim); }
 
 // Lay out every buffer of a context; with base == nullptr only sizes.
 size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
@@ -190,8 +152,8 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
       L.kap64 = P.take<double>(cells);
       if (ir) L.kap32 = P.take<float>(cells);
     }
-    const long rows = ipow(nl - 1, o.dim);
     if (csr) {
+      const long rows = ipow(nl - 1, o.dim);
       const long nnz = csr_nnz(o.dim, nl);
       L.rows = (int)rows;
       L.nnz = nnz;
@@ -200,7 +162,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
       L.rowmap = P.take<int>(rows);
       L.val64 = P.take<double>(nnz);
       if (ir) L.val32 = P.take<float>(nnz);
-      maxpart = std::max(maxpart, csr_residual_blocks((int)rows));
+      maxpart = std::max(maxpart, csr_residual_blocks_max((int)rows));
     }
     maxpart = std::max(maxpart, grid_blocks(g));
   }
@@ -210,6 +172,8 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
   double* part = P.take<double>(maxpart);
   double* scal = P.take<double>(8);
   int* ibuf = P.take<int>(8);
+  void* t64 = P.take<TailDesc<double>>(1);
+  void* t32 = ir ? (void*)P.take<TailDesc<float>>(1) : nullptr;
   if (c) {
     c->Lc = Lc;
     c->m = m;
@@ -217,6 +181,8 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     c->npart = maxpart;
     c->scal = scal;
     c->ibuf = ibuf;
+    c->tail64 = t64;
+    c->tail32 = t32;
   }
   return (P.off + kAlign - 1) / kAlign * kAlign;
 }
@@ -270,7 +236,8 @@ mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
           if (qi < 1 || qi > mi || qj < 1 || qj > mi) continue;
           if (dim == 3 && (qk < 1 || qk > mi)) continue;
           const int q2 = (qi - 1) + mi * (qj - 1) + (dim == 3 ? mi * mi * (qk - 1) : 0);
-          A[(size_t)q * m + q2] = q1_entry(dim, n, c->kappa ? &kap : nullptr, i, j, k, dx, dy, dz);
+          A[(size_t)q * m + q2] =
+              q1_entry(dim, n, c->kappa ? &kap : nullptr, i, j, k, dx, dy, dz);
         }
   }
   // Cholesky A = L L^T (lower, row major), in place.
@@ -292,8 +259,10 @@ mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
   return MG_OK;
 }
 
-// Rows of level l ordered by colour (colour 0 first), lexicographic within a
-// colour; row lengths from the number of unknown neighbours per direction.
+// Rows of level l ordered by colour (colour 0 first); within a colour, 3D
+// rows run over tiles of kCsrTile x kCsrTile grid rows in (y, z) so that a
+// tile's x neighbours stay in L2, lexicographic inside a tile.  Row lengths
+// follow from the number of unknown neighbours per direction.
 mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   Level& Lv = c->lv[l];
   const int dim = c->o.dim, n = Lv.g.n;
@@ -302,28 +271,35 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   rowptr[0] = 0;
   int idx = 0;
   auto cnt = [&](int i) { return 1 + (i > 1) + (i < n - 1); };
+  const int T = dim == 3 ? kCsrTile : n;
+  const int kmin = dim == 3 ? 1 : 0, kmax = dim == 3 ? n - 1 : 0;
   for (int colour = 0; colour < 2; ++colour) {
     if (colour == 1) Lv.coff[1] = idx;
-    for (int k = (dim == 3 ? 1 : 0); k <= (dim == 3 ? n - 1 : 0); ++k)
-      for (int j = 1; j <= n - 1; ++j)
-        for (int i = 1; i <= n - 1; ++i) {
-          if (((i + j + k) & 1) != colour) continue;
-          rowmap[idx] = (int)(i + j * Lv.g.sy + (long)k * Lv.g.sz);
-          const int len = cnt(i) * cnt(j) * (dim == 3 ? cnt(k) : 1);
-          rowptr[idx + 1] = rowptr[idx] + len;
-          ++idx;
-        }
+    for (int k0 = kmin; k0 <= kmax; k0 += T)
+      for (int j0 = 1; j0 <= n - 1; j0 += T)
+        for (int k = k0; k <= std::min(kmax, k0 + T - 1); ++k)
+          for (int j = j0; j <= std::min(n - 1, j0 + T - 1); ++j)
+            for (int i = 1; i <= n - 1; ++i) {
+              if (((i + j + k) & 1) != colour) continue;
+              rowmap[idx] = (int)(i + j * Lv.g.sy + (long)k * Lv.g.sz);
+              const int len = cnt(i) * cnt(j) * (dim == 3 ? cnt(k) : 1);
+              rowptr[idx + 1] = rowptr[idx] + len;
+              ++idx;
+            }
   }
   Lv.coff[0] = 0;
   Lv.coff[2] = rows;
   if (idx != rows || rowptr[rows] != Lv.nnz)
     return fail(MG_E_ARG, "internal: CSR layout mismatch on level %d", l);
   HIP_TRY(hipMemcpyAsync(Lv.rowmap, rowmap.data(), rows * sizeof(int), hipMemcpyHostToDevice, s));
-  HIP_TRY(hipMemcpyAsync(Lv.rowptr, rowptr.data(), (rows + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(Lv.rowptr, rowptr.data(), (rows + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, s));
   const double selem = dim == 3 ? (1.0 / n) / 12.0 : 1.0 / 6.0;
-  launch_csr_build<double>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col, Lv.val64, s);
+  launch_csr_build<double>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col, Lv.val64,
+                           s);
   if (Lv.val32)
-    launch_csr_build<float>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col, Lv.val32, s);
+    launch_csr_build<float>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col,
+                            Lv.val32, s);
   HIP_TRY(hipGetLastError());
   // the host vectors must stay alive until the copies finish
   HIP_TRY(hipStreamSynchronize(s));
@@ -334,6 +310,8 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
     op.rowmap = Lv.rowmap;
     op.rows = rows;
     for (int q = 0; q < 3; ++q) op.coff[q] = Lv.coff[q];
+    op.n = Lv.g.n;
+    op.sy = Lv.g.sy;
   };
   fill(Lv.csr64, Lv.val64);
   if (Lv.val32) fill(Lv.csr32, Lv.val32);
@@ -356,8 +334,8 @@ void set_stencil(mg_ctx* c, int l) {
     s = h / 12.0;
   }
   const int kind = c->kappa ? OP_KAPPA : OP_CONST;
-  Lv.st64 = StencilOp<double>{kind, Lv.kap64, wc, w1, w2, s};
-  Lv.st32 = StencilOp<float>{kind, Lv.kap32, (float)wc, (float)w1, (float)w2, (float)s};
+  Lv.st64 = StencilParams<double>{kind, wc, w1, w2, s};
+  Lv.st32 = StencilParams<float>{kind, (float)wc, (float)w1, (float)w2, (float)s};
 }
 
 // ---------------------------------------------------------------------------
@@ -365,51 +343,270 @@ void set_stencil(mg_ctx* c, int l) {
 // ---------------------------------------------------------------------------
 template <typename T> struct Bufs;
 template <> struct Bufs<double> {
+  static constexpr int prec = 0;
   static double* x(Level& L) { return L.x64; }
   static double* b(Level& L) { return L.b64; }
   static double* t(Level& L) { return L.t64; }
   static double* r(Level& L) { return L.r64; }
-  static const StencilOp<double>& st(Level& L) { return L.st64; }
-  static const CsrOp<double>& csr(Level& L) { return L.csr64; }
+  static const double* kap(Level& L) { return L.kap64; }
+  static const StencilParams<double>& st(Level& L) { return L.st64; }
+  static const CsrOp<double>* csr(Level& L) { return &L.csr64; }
+  static void* tail(mg_ctx* c) { return c->tail64; }
 };
 template <> struct Bufs<float> {
+  static constexpr int prec = 1;
   static float* x(Level& L) { return L.x32; }
   static float* b(Level& L) { return L.b32; }
   static float* t(Level& L) { return L.t32; }
   static float* r(Level& L) { return L.r32; }
-  static const StencilOp<float>& st(Level& L) { return L.st32; }
-  static const CsrOp<float>& csr(Level& L) { return L.csr32; }
+  static const float* kap(Level& L) { return L.kap32; }
+  static const StencilParams<float>& st(Level& L) { return L.st32; }
+  static const CsrOp<float>* csr(Level& L) { return &L.csr32; }
+  static void* tail(mg_ctx* c) { return c->tail32; }
 };
+
+template <typename T>
+mg_status build_tail(mg_ctx* c, hipStream_t s) {
+  const int l0 = c->tail0;
+  TailDesc<T> D{};
+  if (l0 >= 0) {
+    D.nlev = c->L - l0;
+    D.dim = c->o.dim;
+    D.kind = c->kappa ? OP_KAPPA : OP_CONST;
+    D.smoother = c->o.smoother == MG_SMOOTH_JACOBI ? 0 : 1;
+    D.nu_pre = c->o.nu_pre;
+    D.nu_post = c->o.nu_post;
+    D.omega = (T)c->o.omega;
+    D.m = c->m;
+    D.L = c->Lc;
+    for (int q = 0; q < D.nlev; ++q) {
+      Level& Lv = c->lv[l0 + q];
+      const StencilParams<T>& st = Bufs<T>::st(Lv);
+      D.lv[q] = TailLevel<T>{Lv.g.n, Bufs<T>::kap(Lv), Bufs<T>::x(Lv), Bufs<T>::t(Lv),
+                             Bufs<T>::b(Lv), Bufs<T>::r(Lv), st.wc, st.w1, st.w2, st.s};
+    }
+  }
+  HIP_TRY(hipMemcpyAsync(Bufs<T>::tail(c), &D, sizeof D, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return MG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// recorded ops of one cycle
+// ---------------------------------------------------------------------------
+using Sink = std::function<void(const OpRec&)>;
+
+template <typename T>
+OpRec base_op(mg_ctx* c, int code, int l) {
+  OpRec o;
+  o.code = code;
+  o.prec = Bufs<T>::prec;
+  o.level = l;
+  Level& Lv = c->lv[l];
+  o.g = Lv.g;
+  if (l + 1 < c->L) o.gc = c->lv[l + 1].g;
+  const StencilParams<T>& st = Bufs<T>::st(Lv);
+  o.opkind = st.kind;
+  o.wc = st.wc;
+  o.w1 = st.w1;
+  o.w2 = st.w2;
+  o.s = st.s;
+  o.omega = (T)c->o.omega;
+  o.m = c->m;
+  o.item.kappa = Bufs<T>::kap(Lv);
+  return o;
+}
+
+template <typename T>
+void emit_smooth(mg_ctx* c, const Sink& sink, int l, int kind, const T* xin, const T* b,
+                 T* xout) {
+  OpRec o = base_op<T>(c, c->csr ? OC_CSR_SMOOTH : OC_SMOOTH, l);
+  o.sub = kind | ((xin == nullptr) << 4);
+  o.item.a = xin;
+  o.item.b = b;
+  o.item.c = xout;
+  if (c->csr) o.csr = Bufs<T>::csr(c->lv[l]);
+  sink(o);
+}
+
+template <typename T>
+void emit_residual(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* r,
+                   double* partials) {
+  OpRec o = base_op<T>(c, c->csr ? OC_CSR_RESID : OC_RESID, l);
+  o.sub = partials != nullptr;
+  o.item.a = x;
+  o.item.b = b;
+  o.item.c = r;
+  o.item.partials = partials;
+  if (c->csr) o.csr = Bufs<T>::csr(c->lv[l]);
+  sink(o);
+}
+
+long residual_partials(mg_ctx* c, int l) {
+  return c->csr ? csr_residual_blocks(c->lv[l].rows) : grid_blocks(c->lv[l].g);
+}
+
+void emit_reduce(mg_ctx* c, const Sink& sink, long count, double* out) {
+  OpRec o = base_op<double>(c, OC_REDUCE, 0);
+  o.count = count;
+  o.item.partials = c->partials;
+  o.item.scal = out;
+  sink(o);
+}
+
+template <typename T>
+void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
+  OpRec o = base_op<T>(c, OC_FILL, l);
+  o.count = c->lv[l].g.nodes;
+  o.item.c = v;
+  sink(o);
+}
+
+// Smoothing on level l from *cur (or from 0 if *zero), ping-ponging between
+// *cur and *spare; on return *cur holds the smoothed iterate.
+template <typename T>
+void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
+                  const T* b) {
+  const int nu = pre ? c->o.nu_pre : c->o.nu_post;
+  for (int it = 0; it < nu; ++it) {
+    if (c->o.smoother == MG_SMOOTH_JACOBI) {
+      emit_smooth<T>(c, sink, l, SM_JACOBI, *zero ? nullptr : *cur, b, *spare);
+      std::swap(*cur, *spare);
+      *zero = false;
+    } else {
+      const int first = pre ? SM_RB0 : SM_RB1;
+      const int second = pre ? SM_RB1 : SM_RB0;
+      for (int kind : {first, second}) {
+        emit_smooth<T>(c, sink, l, kind, *zero ? nullptr : *cur, b, *spare);
+        std::swap(*cur, *spare);
+        *zero = false;
+      }
+    }
+  }
+}
+
+// One V-cycle (Algorithm 1) for A_0 x = b starting from x0 (or from 0 when
+// x0_zero); the result is written back to x0.  Levels >= 1 and the spare
+// level-0 buffer are internal.  Levels from c->tail0 on run in one
+// workgroup per request.
+template <typename T>
+void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero) {
+  const int L = c->L;
+  std::vector<T*> cur(L), spare(L);
+  std::vector<const T*> bb(L);
+  cur[0] = x0;
+  spare[0] = spare0;
+  bb[0] = b0;
+  for (int l = 1; l < L; ++l) {
+    cur[l] = Bufs<T>::x(c->lv[l]);
+    spare[l] = Bufs<T>::t(c->lv[l]);
+    bb[l] = Bufs<T>::b(c->lv[l]);
+  }
+  const int lt = c->tail0 >= 0 ? c->tail0 : L - 1;  // first level not cycled level by level
+  for (int l = 0; l < lt; ++l) {
+    bool zero = (l > 0) || x0_zero;
+    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &zero, bb[l]);
+    if (zero) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
+    emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
+    OpRec o = base_op<T>(c, OC_RESTRICT, l);
+    o.item.a = Bufs<T>::r(c->lv[l]);
+    o.item.c = Bufs<T>::b(c->lv[l + 1]);
+    sink(o);
+  }
+  if (c->tail0 >= 0) {
+    OpRec o = base_op<T>(c, OC_TAIL, lt);
+    o.item.a = Bufs<T>::tail(c);
+    o.item.b = bb[lt];
+    o.item.c = cur[lt];
+    // a coarse level's correction starts from 0; level 0 from x0 unless x0_zero
+    o.item.flag = (lt > 0 || x0_zero) ? 1 : 0;
+    sink(o);
+  } else {
+    OpRec o = base_op<T>(c, OC_COARSE, L - 1);
+    o.item.b = bb[L - 1];
+    o.item.c = cur[L - 1];
+    o.item.L = c->Lc;
+    sink(o);
+  }
+  for (int l = lt - 1; l >= 0; --l) {
+    OpRec o = base_op<T>(c, OC_PROLONG, l);
+    o.item.a = cur[l + 1];
+    o.item.c = cur[l];
+    sink(o);
+    bool zero = false;
+    smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &zero, bb[l]);
+  }
+  if (cur[0] != x0) {
+    OpRec o = base_op<T>(c, OC_COPY, 0);
+    o.count = c->lv[0].g.nodes;
+    o.item.a = cur[0];
+    o.item.c = x0;
+    sink(o);
+  }
+}
+
+void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+  Level& L0 = c->lv[0];
+  if (c->ir) {
+    // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c
+    OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+    o.item.a = L0.r64;
+    o.item.c = L0.b32;
+    o.item.scal = c->scal + 0;
+    sink(o);
+    emit_vcycle<float>(c, sink, L0.x32, L0.t32, L0.b32, true);
+    OpRec up = base_op<double>(c, OC_IR_UPDATE, 0);
+    up.item.a = L0.x32;
+    up.item.c = u;
+    up.item.scal = c->scal + 0;
+    sink(up);
+  } else {
+    emit_vcycle<double>(c, sink, u, L0.t64, b, false);
+  }
+  // r = b - A u and ||r||^2 into scal[0]
+  emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
+  emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+}
+
+void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+  Level& L0 = c->lv[0];
+  emit_fill<double>(c, sink, 0, u);
+  OpRec o = base_op<double>(c, OC_NORM2, 0);
+  o.item.a = b;
+  o.item.partials = c->partials;
+  sink(o);
+  emit_reduce(c, sink, grid_blocks(L0.g), c->scal + 1);
+  if (c->ir) {
+    emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
+    emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+  }
+}
 
 // profiling hooks: bracket level-0 launches of the selected kernel class
 enum ProfKind { PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3 };
 
-struct ProfScope {
-  mg_ctx* c;
-  hipStream_t s;
-  bool on;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(mg_ctx* ctx, int kind, int level, hipStream_t st)
-      : c(ctx), s(st), on(ctx->prof_on && level == 0 && kind == ctx->prof_kernel) {
-    if (!on) return;
-    for (int q = 0; q < 2; ++q) {
-      hipEvent_t e;
-      if (!c->ev_pool.empty()) {
-        e = c->ev_pool.back();
-        c->ev_pool.pop_back();
-      } else {
-        hipEventCreate(&e);
-      }
-      (q == 0 ? a : b) = e;
-    }
-    hipEventRecord(a, s);
+int prof_class(int code) {
+  switch (code) {
+    case OC_SMOOTH:
+    case OC_CSR_SMOOTH: return PK_SMOOTH;
+    case OC_RESID:
+    case OC_CSR_RESID: return PK_RESID;
+    case OC_RESTRICT: return PK_RESTRICT;
+    case OC_PROLONG: return PK_PROLONG;
+    default: return -1;
   }
-  ~ProfScope() {
-    if (!on) return;
-    hipEventRecord(b, s);
-    c->ev_pending.emplace_back(a, b);
+}
+
+hipEvent_t take_event(mg_ctx* c) {
+  hipEvent_t e;
+  if (!c->ev_pool.empty()) {
+    e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+  } else {
+    hipEventCreate(&e);
   }
-};
+  return e;
+}
 
 void prof_collect(mg_ctx* c) {
   for (auto& pr : c->ev_pending) {
@@ -424,124 +621,22 @@ void prof_collect(mg_ctx* c) {
   c->ev_pending.clear();
 }
 
-template <typename T>
-void op_smooth(mg_ctx* c, int l, int kind, const T* xin, const T* b, T* xout, hipStream_t s) {
-  Level& Lv = c->lv[l];
-  ProfScope ps(c, PK_SMOOTH, l, s);
-  if (c->csr)
-    launch_csr_smooth<T>(Lv.g, Bufs<T>::csr(Lv), kind, xin, b, xout, (T)c->o.omega, s);
-  else
-    launch_smooth<T>(Lv.g, Bufs<T>::st(Lv), kind, xin, b, xout, (T)c->o.omega, s);
-}
-
-template <typename T>
-void op_residual(mg_ctx* c, int l, const T* x, const T* b, T* r, double* partials,
-                 hipStream_t s) {
-  Level& Lv = c->lv[l];
-  ProfScope ps(c, PK_RESID, l, s);
-  if (c->csr)
-    launch_csr_residual<T>(Lv.g, Bufs<T>::csr(Lv), x, b, r, partials, s);
-  else
-    launch_residual<T>(Lv.g, Bufs<T>::st(Lv), x, b, r, partials, s);
-}
-
-template <typename T>
-long residual_blocks(mg_ctx* c, int l) {
-  return c->csr ? csr_residual_blocks(c->lv[l].rows) : grid_blocks(c->lv[l].g);
-}
-
-template <typename T>
-void op_resid_restrict(mg_ctx* c, int l, const T* x, const T* b, T* bc, hipStream_t s) {
-  Level& Lv = c->lv[l];
-  T* r = Bufs<T>::r(Lv);
-  ProfScope ps(c, PK_RESTRICT, l, s);
-  if (c->csr)
-    launch_csr_residual<T>(Lv.g, Bufs<T>::csr(Lv), x, b, r, nullptr, s);
-  else
-    launch_residual<T>(Lv.g, Bufs<T>::st(Lv), x, b, r, nullptr, s);
-  launch_restrict<T>(Lv.g, c->lv[l + 1].g, r, bc, s);
-}
-
-// Smoothing on level l from *cur (or from 0 if *zero), ping-ponging between
-// *cur and *spare; on return *cur holds the smoothed iterate.
-template <typename T>
-void smooth_level(mg_ctx* c, int l, bool pre, T** cur, T** spare, bool* zero, const T* b,
-                  hipStream_t s) {
-  const int nu = pre ? c->o.nu_pre : c->o.nu_post;
-  for (int it = 0; it < nu; ++it) {
-    if (c->o.smoother == MG_SMOOTH_JACOBI) {
-      op_smooth<T>(c, l, SM_JACOBI, *zero ? nullptr : *cur, b, *spare, s);
-      std::swap(*cur, *spare);
-      *zero = false;
-    } else {
-      const int first = pre ? SM_RB0 : SM_RB1;
-      const int second = pre ? SM_RB1 : SM_RB0;
-      for (int kind : {first, second}) {
-        op_smooth<T>(c, l, kind, *zero ? nullptr : *cur, b, *spare, s);
-        std::swap(*cur, *spare);
-        *zero = false;
-      }
+Sink launch_sink(mg_ctx* c, hipStream_t s) {
+  return [c, s](const OpRec& o) {
+    const bool prof = c->prof_on && o.level == 0 && prof_class(o.code) == c->prof_kernel;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (prof) {
+      a = take_event(c);
+      b = take_event(c);
+      hipEventRecord(a, s);
     }
-  }
-}
-
-// One V-cycle (Algorithm 1) for A_0 x = b starting from x0 (or from 0 when
-// x0_zero); the result is written back to x0.  Levels >= 1 and the spare
-// level-0 buffer are internal.
-template <typename T>
-void enqueue_vcycle(mg_ctx* c, T* x0, T* spare0, const T* b0, bool x0_zero, hipStream_t s) {
-  const int L = c->L;
-  if (L == 1) {
-    launch_coarse_solve<T>(c->lv[0].g, c->Lc, c->m, b0, x0, s);
-    return;
-  }
-  std::vector<T*> cur(L), spare(L);
-  std::vector<const T*> bb(L);
-  cur[0] = x0;
-  spare[0] = spare0;
-  bb[0] = b0;
-  for (int l = 1; l < L; ++l) {
-    cur[l] = Bufs<T>::x(c->lv[l]);
-    spare[l] = Bufs<T>::t(c->lv[l]);
-    bb[l] = Bufs<T>::b(c->lv[l]);
-  }
-  for (int l = 0; l < L - 1; ++l) {
-    bool zero = (l > 0) || x0_zero;
-    smooth_level<T>(c, l, true, &cur[l], &spare[l], &zero, bb[l], s);
-    if (zero) {  // no pre-smoothing: materialise x = 0
-      launch_fill<T>(cur[l], c->lv[l].g.nodes, T(0), s);
+    const OpRec* p = &o;
+    launch_ops(&p, 1, s);
+    if (prof) {
+      hipEventRecord(b, s);
+      c->ev_pending.emplace_back(a, b);
     }
-    op_resid_restrict<T>(c, l, cur[l], bb[l], Bufs<T>::b(c->lv[l + 1]), s);
-  }
-  launch_coarse_solve<T>(c->lv[L - 1].g, c->Lc, c->m, bb[L - 1], cur[L - 1], s);
-  for (int l = L - 2; l >= 0; --l) {
-    {
-      ProfScope ps(c, PK_PROLONG, l, s);
-      launch_prolong_add<T>(c->lv[l].g, c->lv[l + 1].g, cur[l + 1], cur[l], s);
-    }
-    bool zero = false;
-    smooth_level<T>(c, l, false, &cur[l], &spare[l], &zero, bb[l], s);
-  }
-  if (cur[0] != x0) launch_copy<T>(cur[0], x0, c->lv[0].g.nodes, s);
-}
-
-// FP64 iteration body: one V-cycle on u, then r = b - A u and ||r||^2.
-void enqueue_cycle64(mg_ctx* c, double* u, const double* b, hipStream_t s) {
-  Level& L0 = c->lv[0];
-  enqueue_vcycle<double>(c, u, L0.t64, b, false, s);
-  op_residual<double>(c, 0, u, b, L0.r64, c->partials, s);
-  launch_reduce_final(c->partials, residual_blocks<double>(c, 0), c->scal + 0, s);
-}
-
-// FP32-IR iteration body: b32 = float(r/||r||), c = V-cycle32(0, b32),
-// u += ||r|| c, r = b - A u, ||r||^2.
-void enqueue_cycle_ir(mg_ctx* c, double* u, const double* b, hipStream_t s) {
-  Level& L0 = c->lv[0];
-  launch_scale_cast(L0.g, L0.r64, c->scal + 0, L0.b32, s);
-  enqueue_vcycle<float>(c, L0.x32, L0.t32, L0.b32, true, s);
-  launch_ir_update(L0.g, u, L0.x32, c->scal + 0, s);
-  op_residual<double>(c, 0, u, b, L0.r64, c->partials, s);
-  launch_reduce_final(c->partials, residual_blocks<double>(c, 0), c->scal + 0, s);
+  };
 }
 
 void drop_graph(mg_ctx* c) {
@@ -550,18 +645,12 @@ void drop_graph(mg_ctx* c) {
   c->gkey[0] = c->gkey[1] = c->gkey[2] = nullptr;
 }
 
-// Run one iteration body: replay the cached graph (captured on first use
-// for these buffers) or launch eagerly.
+// Run one iteration: replay the cached graph (captured on first use for
+// these buffers) or launch eagerly.
 mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s) {
   const bool eager = (c->o.flags & MG_FLAG_NO_GRAPH) || c->prof_on;
-  auto body = [&](hipStream_t st) {
-    if (c->ir)
-      enqueue_cycle_ir(c, u, b, st);
-    else
-      enqueue_cycle64(c, u, b, st);
-  };
   if (eager) {
-    body(s);
+    emit_iteration(c, launch_sink(c, s), u, b);
     HIP_TRY(hipGetLastError());
     return MG_OK;
   }
@@ -570,7 +659,7 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s) {
     drop_graph(c);
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    body(c->cap);
+    emit_iteration(c, launch_sink(c, c->cap), u, b);
     hipError_t le = hipGetLastError();
     hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -591,7 +680,8 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s) {
 }
 
 mg_status read_scalar(mg_ctx* c, int idx, double* out, hipStream_t s) {
-  HIP_TRY(hipMemcpyAsync(c->pinned + idx, c->scal + idx, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(c->pinned + idx, c->scal + idx, sizeof(double), hipMemcpyDeviceToHost,
+                         s));
   HIP_TRY(hipStreamSynchronize(s));
   *out = c->pinned[idx];
   return MG_OK;
@@ -599,7 +689,86 @@ mg_status read_scalar(mg_ctx* c, int idx, double* out, hipStream_t s) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
+template <typename T>
+StencilParams<T> params_of(const OpRec& o) {
+  return StencilParams<T>{o.opkind, (T)o.wc, (T)o.w1, (T)o.w2, (T)o.s};
+}
+
+template <typename T>
+void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
+  const Item& it = B.it[0];
+  switch (o.code) {
+    case OC_SMOOTH:
+      launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, (T)o.omega, B, s);
+      break;
+    case OC_RESID: launch_residual<T>(o.g, params_of<T>(o), o.sub != 0, B, s); break;
+    case OC_RESTRICT: launch_restrict<T>(o.g, o.gc, B, s); break;
+    case OC_PROLONG: launch_prolong_add<T>(o.g, o.gc, B, s); break;
+    case OC_COARSE: launch_coarse_solve<T>(o.g, o.m, B, s); break;
+    case OC_NORM2: launch_norm2_partial<T>(o.g, B, s); break;
+    case OC_TAIL: launch_tail<T>(o.g.dim, o.opkind, B, s); break;
+    case OC_FILL: launch_fill<T>((T*)it.c, o.count, T(0), s); break;
+    case OC_COPY: launch_copy<T>((const T*)it.a, (T*)it.c, o.count, s); break;
+    case OC_CSR_SMOOTH:
+      launch_csr_smooth<T>(o.g, *(const CsrOp<T>*)o.csr, o.sub & 15,
+                           (o.sub >> 4) ? nullptr : (const T*)it.a, (const T*)it.b, (T*)it.c,
+                           (T)o.omega, s);
+      break;
+    case OC_CSR_RESID:
+      launch_csr_residual<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (const T*)it.b,
+                             (T*)it.c, it.partials, s);
+      break;
+    default: break;
+  }
+}
+
 }  // namespace
+
+// ---------------------------------------------------------------------------
+// op fusion interface (used by the serving scheduler)
+// ---------------------------------------------------------------------------
+namespace mg {
+
+bool batchable(const OpRec& a) {
+  return a.code != OC_FILL && a.code != OC_COPY && a.code != OC_CSR_SMOOTH &&
+         a.code != OC_CSR_RESID;
+}
+
+bool same_key(const OpRec& a, const OpRec& b) {
+  return a.code == b.code && a.prec == b.prec && a.sub == b.sub && a.g.dim == b.g.dim &&
+         a.g.n == b.g.n && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
+         a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.omega == b.omega && a.m == b.m &&
+         a.count == b.count && batchable(a) && batchable(b);
+}
+
+void launch_ops(const OpRec* const* ops, int n, hipStream_t s) {
+  Batch B{};
+  B.count = n;
+  for (int q = 0; q < n; ++q) B.it[q] = ops[q]->item;
+  const OpRec& o = *ops[0];
+  switch (o.code) {
+    case OC_REDUCE: launch_reduce_final(o.count, B, s); return;
+    case OC_SCALE_CAST: launch_scale_cast(o.g, B, s); return;
+    case OC_IR_UPDATE: launch_ir_update(o.g, B, s); return;
+    default: break;
+  }
+  if (o.prec == 0)
+    launch_typed<double>(o, B, s);
+  else
+    launch_typed<float>(o, B, s);
+}
+
+void record_iteration(mg_ctx* c, double* u, const double* b, std::vector<OpRec>& out) {
+  emit_iteration(c, [&out](const OpRec& o) { out.push_back(o); }, u, b);
+}
+
+void record_prologue(mg_ctx* c, double* u, const double* b, std::vector<OpRec>& out) {
+  emit_prologue(c, [&out](const OpRec& o) { out.push_back(o); }, u, b);
+}
+
+size_t plan_bytes(const mg_options& o, bool has_kappa) { return plan(o, has_kappa, nullptr, nullptr); }
+
+}  // namespace mg
 
 // ---------------------------------------------------------------------------
 // C ABI
@@ -629,7 +798,6 @@ size_t mg_footprint_bytes(const mg_options* o) {
     fail(MG_E_ARG, "%s", why.c_str());
     return 0;
   }
-  // the footprint with a coefficient is the larger one
   return plan(*o, true, nullptr, nullptr);
 }
 
@@ -645,6 +813,7 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
   c->kappa = kappa_dev != nullptr;
   c->ir = o->precision == MG_PREC_FP32_IR;
   c->csr = o->op == MG_OP_CSR;
+  c->tail0 = tail_start(*o);
   c->lv.resize(c->L);
   auto bail = [&](mg_status st) {
     mg_destroy(c);
@@ -695,6 +864,9 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
   }
   mg_status st = coarse_factor(c, s);
   if (st != MG_OK) return bail(st);
+  st = build_tail<double>(c, s);
+  if (st == MG_OK && c->ir) st = build_tail<float>(c, s);
+  if (st != MG_OK) return bail(st);
   if (hipStreamSynchronize(s) != hipSuccess || hipGetLastError() != hipSuccess)
     return bail(fail(MG_E_HIP, "setup kernels failed"));
   *out = c;
@@ -733,12 +905,9 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be > 0");
   if ((const void*)b == (const void*)u) return fail(MG_E_ARG, "u must not alias b");
   hipStream_t s = as_stream(stream);
-  Level& L0 = c->lv[0];
   *iters = 0;
   if (hist) hist[0] = 1.0;
-  launch_fill<double>(u, L0.g.nodes, 0.0, s);
-  launch_norm2_partial<double>(L0.g, b, c->partials, s);
-  launch_reduce_final(c->partials, grid_blocks(L0.g), c->scal + 1, s);
+  emit_prologue(c, launch_sink(c, s), u, b);
   HIP_TRY(hipGetLastError());
   double nb2 = 0.0;
   mg_status st = read_scalar(c, 1, &nb2, s);
@@ -746,12 +915,6 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   if (!std::isfinite(nb2)) return fail(MG_E_NONFINITE, "b holds NaN or Inf");
   if (nb2 == 0.0) return MG_OK;
   const double nb = std::sqrt(nb2);
-  if (c->ir) {
-    // r = b - A 0 = b and ||r||^2, the state every refinement step expects
-    op_residual<double>(c, 0, u, b, L0.r64, c->partials, s);
-    launch_reduce_final(c->partials, residual_blocks<double>(c, 0), c->scal + 0, s);
-    HIP_TRY(hipGetLastError());
-  }
   for (int k = 1; k <= c->o.max_iter; ++k) {
     st = run_iteration(c, u, b, s);
     if (st != MG_OK) return st;
@@ -769,6 +932,8 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   return fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, c->o.max_iter);
 }
 
+}  // extern "C"
+
 // ---- single steps -----------------------------------------------------------
 namespace {
 mg_status check_step(mg_ctx* c, int level, int prec, bool need_next) {
@@ -780,23 +945,31 @@ mg_status check_step(mg_ctx* c, int level, int prec, bool need_next) {
     return fail(MG_E_STATE, "FP32 operators exist only in MG_PREC_FP32_IR contexts");
   return MG_OK;
 }
+
+template <typename F>
+mg_status typed(int prec, F f) {
+  if (prec == MG_PREC_FP64)
+    f(double(0));
+  else
+    f(float(0));
+  HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
 }  // namespace
+
+extern "C" {
 
 mg_status mg_apply_residual(mg_ctx* c, int level, int prec, const void* x, const void* b, void* r,
                             void* stream) {
   mg_status st = check_step(c, level, prec, false);
   if (st != MG_OK) return st;
   if (!x || !b || !r) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  if (prec == MG_PREC_FP64) {
-    launch_fill<double>((double*)r, c->lv[level].g.nodes, 0.0, s);
-    op_residual<double>(c, level, (const double*)x, (const double*)b, (double*)r, nullptr, s);
-  } else {
-    launch_fill<float>((float*)r, c->lv[level].g.nodes, 0.f, s);
-    op_residual<float>(c, level, (const float*)x, (const float*)b, (float*)r, nullptr, s);
-  }
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    emit_fill<T>(c, sink, level, (T*)r);
+    emit_residual<T>(c, sink, level, (const T*)x, (const T*)b, (T*)r, nullptr);
+  });
 }
 
 mg_status mg_apply_smooth(mg_ctx* c, int level, int prec, int step, const void* x_in,
@@ -805,27 +978,23 @@ mg_status mg_apply_smooth(mg_ctx* c, int level, int prec, int step, const void* 
   if (st != MG_OK) return st;
   if (!b || !x_out) return fail(MG_E_ARG, "NULL vector");
   if (step < 0 || step > 4) return fail(MG_E_ARG, "step must be 0..4");
-  hipStream_t s = as_stream(stream);
-  Level& Lv = c->lv[level];
-  auto run = [&](auto tag) {
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
     using T = decltype(tag);
     T* out = (T*)x_out;
     const T* in = (const T*)x_in;
     const T* bb = (const T*)b;
-    launch_fill<T>(out, Lv.g.nodes, T(0), s);
+    emit_fill<T>(c, sink, level, out);
     if (step <= 2) {
-      op_smooth<T>(c, level, step, in, bb, out, s);
+      emit_smooth<T>(c, sink, level, step, in, bb, out);
       return;
     }
     // full red-black sweep through the level's spare buffer
-    T* tmp = Bufs<T>::t(Lv);
+    T* tmp = Bufs<T>::t(c->lv[level]);
     const int k1 = step == 3 ? SM_RB0 : SM_RB1, k2 = step == 3 ? SM_RB1 : SM_RB0;
-    op_smooth<T>(c, level, k1, in, bb, tmp, s);
-    op_smooth<T>(c, level, k2, tmp, bb, out, s);
-  };
-  if (prec == MG_PREC_FP64) run(double(0)); else run(float(0));
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+    emit_smooth<T>(c, sink, level, k1, in, bb, tmp);
+    emit_smooth<T>(c, sink, level, k2, tmp, bb, out);
+  });
 }
 
 mg_status mg_apply_restrict(mg_ctx* c, int level, int prec, const void* r, void* bc,
@@ -833,18 +1002,15 @@ mg_status mg_apply_restrict(mg_ctx* c, int level, int prec, const void* r, void*
   mg_status st = check_step(c, level, prec, true);
   if (st != MG_OK) return st;
   if (!r || !bc) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  const Geo& gf = c->lv[level].g;
-  const Geo& gc = c->lv[level + 1].g;
-  if (prec == MG_PREC_FP64) {
-    launch_fill<double>((double*)bc, gc.nodes, 0.0, s);
-    launch_restrict<double>(gf, gc, (const double*)r, (double*)bc, s);
-  } else {
-    launch_fill<float>((float*)bc, gc.nodes, 0.f, s);
-    launch_restrict<float>(gf, gc, (const float*)r, (float*)bc, s);
-  }
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    emit_fill<T>(c, sink, level + 1, (T*)bc);
+    OpRec o = base_op<T>(c, OC_RESTRICT, level);
+    o.item.a = r;
+    o.item.c = bc;
+    sink(o);
+  });
 }
 
 mg_status mg_apply_residual_restrict(mg_ctx* c, int level, int prec, const void* x, const void* b,
@@ -852,17 +1018,17 @@ mg_status mg_apply_residual_restrict(mg_ctx* c, int level, int prec, const void*
   mg_status st = check_step(c, level, prec, true);
   if (st != MG_OK) return st;
   if (!x || !b || !bc) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  const Geo& gc = c->lv[level + 1].g;
-  if (prec == MG_PREC_FP64) {
-    launch_fill<double>((double*)bc, gc.nodes, 0.0, s);
-    op_resid_restrict<double>(c, level, (const double*)x, (const double*)b, (double*)bc, s);
-  } else {
-    launch_fill<float>((float*)bc, gc.nodes, 0.f, s);
-    op_resid_restrict<float>(c, level, (const float*)x, (const float*)b, (float*)bc, s);
-  }
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    T* r = Bufs<T>::r(c->lv[level]);
+    emit_fill<T>(c, sink, level + 1, (T*)bc);
+    emit_residual<T>(c, sink, level, (const T*)x, (const T*)b, r, nullptr);
+    OpRec o = base_op<T>(c, OC_RESTRICT, level);
+    o.item.a = r;
+    o.item.c = bc;
+    sink(o);
+  });
 }
 
 mg_status mg_apply_prolong_add(mg_ctx* c, int level, int prec, const void* e, void* x,
@@ -870,46 +1036,41 @@ mg_status mg_apply_prolong_add(mg_ctx* c, int level, int prec, const void* e, vo
   mg_status st = check_step(c, level, prec, true);
   if (st != MG_OK) return st;
   if (!e || !x) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  const Geo& gf = c->lv[level].g;
-  const Geo& gc = c->lv[level + 1].g;
-  if (prec == MG_PREC_FP64)
-    launch_prolong_add<double>(gf, gc, (const double*)e, (double*)x, s);
-  else
-    launch_prolong_add<float>(gf, gc, (const float*)e, (float*)x, s);
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    OpRec o = base_op<T>(c, OC_PROLONG, level);
+    o.item.a = e;
+    o.item.c = x;
+    sink(o);
+  });
 }
 
 mg_status mg_apply_coarse_solve(mg_ctx* c, int prec, const void* bc, void* xc, void* stream) {
   mg_status st = check_step(c, c ? c->L - 1 : 0, prec, false);
   if (st != MG_OK) return st;
   if (!bc || !xc) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  const Geo& g = c->lv[c->L - 1].g;
-  if (prec == MG_PREC_FP64) {
-    launch_fill<double>((double*)xc, g.nodes, 0.0, s);
-    launch_coarse_solve<double>(g, c->Lc, c->m, (const double*)bc, (double*)xc, s);
-  } else {
-    launch_fill<float>((float*)xc, g.nodes, 0.f, s);
-    launch_coarse_solve<float>(g, c->Lc, c->m, (const float*)bc, (float*)xc, s);
-  }
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    emit_fill<T>(c, sink, c->L - 1, (T*)xc);
+    OpRec o = base_op<T>(c, OC_COARSE, c->L - 1);
+    o.item.b = bc;
+    o.item.c = xc;
+    o.item.L = c->Lc;
+    sink(o);
+  });
 }
 
 mg_status mg_vcycle(mg_ctx* c, int prec, void* x, const void* b, void* stream) {
   mg_status st = check_step(c, 0, prec, false);
   if (st != MG_OK) return st;
   if (!x || !b) return fail(MG_E_ARG, "NULL vector");
-  hipStream_t s = as_stream(stream);
-  Level& L0 = c->lv[0];
-  if (prec == MG_PREC_FP64)
-    enqueue_vcycle<double>(c, (double*)x, L0.t64, (const double*)b, false, s);
-  else
-    enqueue_vcycle<float>(c, (float*)x, L0.t32, (const float*)b, false, s);
-  HIP_TRY(hipGetLastError());
-  return MG_OK;
+  const Sink sink = launch_sink(c, as_stream(stream));
+  return typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    emit_vcycle<T>(c, sink, (T*)x, Bufs<T>::t(c->lv[0]), (const T*)b, false);
+  });
 }
 
 mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, void* stream) {
@@ -917,13 +1078,16 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
   if (st != MG_OK) return st;
   if (!v || !out) return fail(MG_E_ARG, "NULL argument");
   hipStream_t s = as_stream(stream);
-  const Geo& g = c->lv[level].g;
-  if (prec == MG_PREC_FP64)
-    launch_norm2_partial<double>(g, (const double*)v, c->partials, s);
-  else
-    launch_norm2_partial<float>(g, (const float*)v, c->partials, s);
-  launch_reduce_final(c->partials, grid_blocks(g), c->scal + 2, s);
-  HIP_TRY(hipGetLastError());
+  const Sink sink = launch_sink(c, s);
+  st = typed(prec, [&](auto tag) {
+    using T = decltype(tag);
+    OpRec o = base_op<T>(c, OC_NORM2, level);
+    o.item.a = v;
+    o.item.partials = c->partials;
+    sink(o);
+    emit_reduce(c, sink, grid_blocks(c->lv[level].g), c->scal + 2);
+  });
+  if (st != MG_OK) return st;
   return read_scalar(c, 2, out, s);
 }
 

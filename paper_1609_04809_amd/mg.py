@@ -24,11 +24,12 @@ OP = {"stencil": 0, "csr": 1}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 PREC = {"fp64": 0, "fp32_ir": 1}
 FLAG_NO_GRAPH = 1
+FLAG_NO_TAIL = 2
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
 # mg_profile_enable kernel ids
-PROF_SMOOTH, PROF_RESID, PROF_RESID_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
+PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
 
 
 class MgError(RuntimeError):
@@ -72,12 +73,34 @@ SIGNATURES = {
 }
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("launches", ctypes.c_uint64), ("fused_ops", ctypes.c_uint64),
+                ("steps", ctypes.c_uint64), ("busy_s", ctypes.c_double),
+                ("hbm_in_use", ctypes.c_size_t), ("hbm_peak", ctypes.c_size_t),
+                ("in_flight", ctypes.c_int), ("queued", ctypes.c_int)]
+
+
+_DP = ctypes.POINTER(ctypes.c_double)
+SERVER_SIGNATURES = {
+    "mg_server_create": (_I, [ctypes.c_size_t, _I, ctypes.POINTER(_VP)]),
+    "mg_server_submit": (_I, [_VP, ctypes.POINTER(Options), _DP, _DP, _DP, ctypes.c_double,
+                              ctypes.POINTER(ctypes.c_uint64)]),
+    "mg_server_poll": (_I, [_VP, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I),
+                            ctypes.POINTER(_I), _DP, _DP, _I, ctypes.POINTER(_I)]),
+    "mg_server_drain": (_I, [_VP, ctypes.c_double]),
+    "mg_server_get_stats": (_I, [_VP, ctypes.POINTER(ServerStats)]),
+    "mg_server_destroy": (None, [_VP]),
+}
+
+
 def load_library(path=LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(
             f"{path} is missing: build it with `python -m paper_1609_04809_amd.build`")
     lib = ctypes.CDLL(path)
-    for name, (res, args) in SIGNATURES.items():
+    for name, (res, args) in {**SIGNATURES, **SERVER_SIGNATURES}.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
@@ -242,3 +265,75 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib().mg_profile_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+class Server:
+    """Continuous-batching solve server (mg_server_* in the C ABI).
+
+    Requests are host arrays; results land in host arrays owned by this
+    object until they are collected with :meth:`poll`."""
+
+    def __init__(self, hbm_budget_bytes, max_slots=64):
+        srv = ctypes.c_void_p()
+        _check(lib().mg_server_create(int(hbm_budget_bytes), int(max_slots), ctypes.byref(srv)))
+        self._srv = srv
+        self._pending = {}   # id -> (u_host, b_host, kappa_host) kept alive until done
+
+    def submit(self, dim, n, levels, b_full, tol, kappa=None, **kw):
+        """b_full: float64 host array of (n+1)^dim nodes.  Returns the id."""
+        o = make_options(dim, n, levels, **kw)
+        b = np.ascontiguousarray(b_full, dtype=np.float64)
+        if b.size != (n + 1) ** dim:
+            raise ValueError("b has the wrong size")
+        k = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float64)
+        u = np.empty_like(b)
+        rid = ctypes.c_uint64()
+        _check(lib().mg_server_submit(
+            self._srv, ctypes.byref(o), b.ctypes.data_as(_DP),
+            None if k is None else k.ctypes.data_as(_DP), u.ctypes.data_as(_DP),
+            float(tol), ctypes.byref(rid)))
+        self._pending[rid.value] = u
+        return rid.value
+
+    def poll(self, max_items=4096):
+        """Finished requests: list of dicts (id, u, iters, status, rel_residual,
+        latency_us)."""
+        ids = (ctypes.c_uint64 * max_items)()
+        iters = (ctypes.c_int * max_items)()
+        st = (ctypes.c_int * max_items)()
+        rho = (ctypes.c_double * max_items)()
+        lat = (ctypes.c_double * max_items)()
+        n = ctypes.c_int()
+        _check(lib().mg_server_poll(self._srv, ids, iters, st, rho, lat, max_items,
+                                    ctypes.byref(n)))
+        out = []
+        for q in range(n.value):
+            out.append(dict(id=ids[q], u=self._pending.pop(ids[q]), iters=iters[q],
+                            status=STATUS_NAMES.get(st[q], st[q]), rel_residual=rho[q],
+                            latency_us=lat[q]))
+        return out
+
+    def drain(self, timeout_s=600.0):
+        _check(lib().mg_server_drain(self._srv, float(timeout_s)))
+
+    def stats(self):
+        s = ServerStats()
+        _check(lib().mg_server_get_stats(self._srv, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_srv", None) is not None and self._srv.value:
+            lib().mg_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

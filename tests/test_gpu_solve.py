@@ -115,6 +115,29 @@ def test_graph_and_eager_agree_bitwise():
         assert np.array_equal(outs[a][3], outs[c][3])
 
 
+@pytest.mark.parametrize("dim,n,levels,kap,prec", [
+    (2, 64, 5, False, "fp64"),      # the whole cycle fits the one-workgroup tail
+    (2, 256, 7, True, "fp32_ir"),
+    (3, 64, 6, False, "fp64"),
+    (3, 32, 5, True, "fp32_ir"),
+])
+def test_tail_and_grid_levels_agree_bitwise(dim, n, levels, kap, prec):
+    """Coarse levels cycled inside one workgroup compute bitwise what the
+    level-by-level grid launches compute."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_TAIL, Solver
+    kappa = W.kappa_lognormal(dim, n, 4) if kap else None
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 8))
+    outs = []
+    for flags in (0, FLAG_NO_TAIL):
+        with Solver(dim, n, levels, kappa=kappa, precision=prec, flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-8)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
 def test_repeated_solves_with_new_buffers_recapture():
     torch = torch_cuda()
     from paper_1609_04809_amd.mg import Solver
