@@ -205,6 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--workload", default="poisson3d_128_csr_rbgs")
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the reference device copy (attainable bandwidth; "
@@ -236,6 +238,21 @@ def main():
             log(f"[bench] {other}: {r['MDOF_per_s']} MDOF/s, {r['cycles']} cycles, "
                 f"{r['ms_per_solve']} ms/solve")
             extra.append(r)
+    serving = None
+    if not args.no_serve:
+        from paper_1609_04809_amd import serve_load
+        nreq = args.serve_requests
+        trace = W.serving_trace(num=nreq, rate=200.0, seed=0)
+        log(f"[bench] serving: {nreq} requests, Poisson arrivals at 200/s")
+        serving = {"poisson_arrivals_200_per_s": serve_load.run_trace(trace, 64 << 30, 64,
+                                                                       log=log)}
+        log(f"[bench] serving: {serving['poisson_arrivals_200_per_s']}")
+        burst = W.serving_trace(num=nreq, rate=200.0, seed=0, burst=True)
+        serving["burst_all_at_t0"] = serve_load.run_trace(burst, 64 << 30, 64, log=log)
+        log(f"[bench] serving burst: {serving['burst_all_at_t0']}")
+        serving["burst_2GiB_budget"] = serve_load.run_trace(burst[: max(1, nreq // 5)],
+                                                            2 << 30, 64, log=log)
+        log(f"[bench] serving small budget: {serving['burst_2GiB_budget']}")
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
@@ -265,6 +282,7 @@ def main():
         "cpu_baseline": cpu,
         "copy_reference_GBs": copy_gbs,
         "extra": extra,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
