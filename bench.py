@@ -155,10 +155,17 @@ def run_workload(name, steps, warmup, with_roofline=False):
            "cycles": k, "final_rel_residual": hist[-1], "setup_s": round(setup_s, 3),
            "precision": w.precision, "op": w.op}
     roof = None
-    if with_roofline:
-        roof = roofline_csr(S, w, bd) if w.op == "csr" else None
-    elif w.dim == 3 and w.op == "stencil":
-        res["halfsweep"] = roofline_stencil(S, w, bd, 8 if w.precision == "fp64" else 4)
+    if w.op == "csr":
+        if with_roofline:
+            roof = roofline_csr(S, w, bd)
+    elif w.dim == 3:
+        hs = roofline_stencil(S, w, bd, 8 if w.precision == "fp64" else 4)
+        res["halfsweep"] = hs
+        if with_roofline:
+            roof = {"bound": "hbm", "kernel": "k_sweep3 (red-black half-sweep, finest level)",
+                    "achieved": hs["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": hs["frac"], "traffic": None, "avg_us": hs["avg_us"],
+                    "bytes_per_launch": hs["bytes_per_launch"]}
     S.close()
     return res, roof, (b, kappa, u, k)
 

@@ -11,6 +11,8 @@
 // Thread layout of the node kernels: a block of 64 x 4 threads covers 64
 // consecutive x and 4 consecutive y of one z plane of interior nodes, so one
 // wavefront (64 lanes) reads 64 consecutive values of a grid row.
+#include <cstdlib>
+
 #include "mg_internal.h"
 
 namespace mg {
@@ -76,19 +78,90 @@ struct Apply<T, 2, OP_CONST> {
   }
 };
 
-// 3D, kappa = 1: 8h/3 centre, -h/6 on the 12 edge neighbours, -h/12 on the
+// 3D arithmetic on a 3x3x3 neighbourhood v[dz+1][dy+1][dx+1] of node p;
+// shared by every kernel that applies the 3D operator, so that all of them
+// round identically.
+//
+// kappa = 1: 8h/3 centre, -h/6 on the 12 edge neighbours, -h/12 on the
 // 8 corners, 0 on the 6 face neighbours.
+template <typename T, typename V>
+__device__ __forceinline__ T stencil3_const(const StencilParams<T>& op, const V& v) {
+  const T e = ((v[1][0][0] + v[1][0][2]) + (v[1][2][0] + v[1][2][2])) +
+              ((v[0][1][0] + v[0][1][2]) + (v[2][1][0] + v[2][1][2])) +
+              ((v[0][0][1] + v[0][2][1]) + (v[2][0][1] + v[2][2][1]));
+  const T c = ((v[0][0][0] + v[0][0][2]) + (v[0][2][0] + v[0][2][2])) +
+              ((v[2][0][0] + v[2][0][2]) + (v[2][2][0] + v[2][2][2]));
+  return op.wc * v[1][1][1] + op.w1 * e + op.w2 * c;
+}
+
+// kappa per cell: cell (a, b, c) of the eight around p (side sx = 2a-1,
+// sy = 2b-1, sz = 2c-1), coefficient kk[c][b][a], contributes
+//   kappa_abc * h/12 * (4 x_p - x_{p+sx+sy} - x_{p+sx+sz} - x_{p+sy+sz}
+//                       - x_{p+sx+sy+sz});
+// face neighbours have element weight 0.
+template <typename T, typename V, typename K>
+__device__ __forceinline__ T stencil3_kappa(const StencilParams<T>& op, const K& kk, const V& v,
+                                            T& dg) {
+  const T xp = v[1][1][1];
+  T acc = 0, ks = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T kc = kk[c][b][a];
+        const int dx = 2 * a, dy = 2 * b, dz = 2 * c;  // neighbour index (0 or 2) per side
+        acc += kc * (T(4) * xp - v[1][dy][dx] - v[dz][1][dx] - v[dz][dy][1] - v[dz][dy][dx]);
+        ks += kc;
+      }
+    }
+  }
+  dg = op.s * T(4) * ks;
+  return op.s * acc;
+}
+
+template <typename T, typename K>
+__device__ __forceinline__ T kappa_diag3(const StencilParams<T>& op, const K& kk) {
+  T ks = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) ks += kk[c][b][a];
+  return op.s * T(4) * ks;
+}
+
+template <typename T>
+__device__ __forceinline__ void gather27(const T* __restrict__ x, long p, long sy, long sz,
+                                         T (&v)[3][3][3]) {
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = x[p + (dx - 1) + (dy - 1) * sy + (dz - 1) * sz];
+}
+
+template <typename T>
+__device__ __forceinline__ void gather_cells3(const T* __restrict__ kp, long n, T (&kk)[2][2][2]) {
+  const long cz = n * n;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) kk[c][b][a] = kp[a + n * b + cz * c];
+}
+
 template <typename T>
 struct Apply<T, 3, OP_CONST> {
   __device__ static void at(const StencilParams<T>& op, const T*, const DGeo& g,
                             const T* __restrict__ x, long p, int, int, int, T& ax, T& dg) {
-    const long sy = g.sy, sz = g.sz;
-    T e = ((x[p - 1 - sy] + x[p + 1 - sy]) + (x[p - 1 + sy] + x[p + 1 + sy])) +
-          ((x[p - 1 - sz] + x[p + 1 - sz]) + (x[p - 1 + sz] + x[p + 1 + sz])) +
-          ((x[p - sy - sz] + x[p + sy - sz]) + (x[p - sy + sz] + x[p + sy + sz]));
-    T c = ((x[p - 1 - sy - sz] + x[p + 1 - sy - sz]) + (x[p - 1 + sy - sz] + x[p + 1 + sy - sz])) +
-          ((x[p - 1 - sy + sz] + x[p + 1 - sy + sz]) + (x[p - 1 + sy + sz] + x[p + 1 + sy + sz]));
-    ax = op.wc * x[p] + op.w1 * e + op.w2 * c;
+    T v[3][3][3];
+    gather27(x, p, g.sy, g.sz, v);  // face entries are loaded but carry weight 0
+    ax = stencil3_const(op, v);
     dg = op.wc;
   }
   __device__ static T diag(const StencilParams<T>& op, const T*, const DGeo&, int, int, int) {
@@ -136,52 +209,25 @@ struct Apply<T, 2, OP_KAPPA> {
   }
 };
 
-// 3D, kappa per cell.  Cell (a, b, c) of the eight around p (side
-// sx = 2a-1, sy = 2b-1, sz = 2c-1) contributes
-//   kappa_abc * h/12 * (4 x_p - x_{p+sx+sy} - x_{p+sx+sz} - x_{p+sy+sz}
-//                       - x_{p+sx+sy+sz});
-// face neighbours have element weight 0.
+// 3D, kappa per cell (stencil3_kappa).
 template <typename T>
 struct Apply<T, 3, OP_KAPPA> {
   __device__ static void at(const StencilParams<T>& op, const T* __restrict__ kappa,
                             const DGeo& g, const T* __restrict__ x, long p, int i, int j, int k,
                             T& ax, T& dg) {
-    const long sy = g.sy, sz = g.sz;
-    const long n = g.n, cz = (long)g.n * g.n;
-    const T* kp = kappa + (i - 1) + n * (j - 1) + cz * (k - 1);
-    const T xp = x[p];
-    T acc = 0, ks = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const T kc = kp[a + n * b + cz * c];
-          const long dx = a ? 1 : -1;
-          const long dy = b ? sy : -sy;
-          const long dz = c ? sz : -sz;
-          acc += kc * (T(4) * xp - x[p + dx + dy] - x[p + dx + dz] - x[p + dy + dz] -
-                       x[p + dx + dy + dz]);
-          ks += kc;
-        }
-      }
-    }
-    ax = op.s * acc;
-    dg = op.s * T(4) * ks;
+    const long n = g.n;
+    T kk[2][2][2];
+    gather_cells3(kappa + (i - 1) + n * (j - 1) + n * n * (k - 1), n, kk);
+    T v[3][3][3];
+    gather27(x, p, g.sy, g.sz, v);
+    ax = stencil3_kappa(op, kk, v, dg);
   }
   __device__ static T diag(const StencilParams<T>& op, const T* __restrict__ kappa,
                            const DGeo& g, int i, int j, int k) {
-    const long n = g.n, cz = (long)g.n * g.n;
-    const T* kp = kappa + (i - 1) + n * (j - 1) + cz * (k - 1);
-    T ks = 0;
-#pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int a = 0; a < 2; ++a) ks += kp[a + n * b + cz * c];
-    return op.s * T(4) * ks;
+    const long n = g.n;
+    T kk[2][2][2];
+    gather_cells3(kappa + (i - 1) + n * (j - 1) + n * n * (k - 1), n, kk);
+    return kappa_diag3(op, kk);
   }
 };
 
@@ -277,6 +323,258 @@ __device__ __forceinline__ T prolong_node(const DGeo& gc, const T* __restrict__ 
     return (j & 1) ? wj * (line(j0, kk) + line(j1, kk)) : line(j0, kk);
   };
   return (k & 1) ? wk * (plane(k0) + plane(k1)) : plane(k0);
+}
+
+// ---------------------------------------------------------------------------
+// 3D sweep kernel for the large levels: a block of 64 x 4 threads owns a tile
+// of 128 x 4 unknowns in (x, y) and marches over kz planes in z.  Per plane,
+// the block stages the plane's (128+2) x (4+2) tile of x (and the cell layer
+// of kappa) in LDS once; every thread copies its 4 x 3 window of the plane
+// into registers, so it holds planes k-1, k, k+1 for its two unknowns
+// (i, i+1) and reads 6 LDS vectors per plane instead of 2 x 20 global
+// loads.  In a red-black half-sweep exactly one of the two unknowns has the
+// colour being updated, and the whole wavefront agrees on which one.
+//
+// MODE: SM_JACOBI, SM_RB0, SM_RB1 (smoothing; ZERO: x = 0, not read) or
+// SW_RESID (r = b - A x with per-block partial sums of r^2 when NORM).
+// ---------------------------------------------------------------------------
+constexpr int SW_RESID = 3;
+constexpr int SW_TX = 128;  // unknowns per tile in x (2 per thread)
+constexpr int SW_TY = 4;    // unknowns per tile in y (1 per thread row)
+constexpr int SW_LX = SW_TX + 2, SW_LY = SW_TY + 2;
+
+template <typename T> struct Vec2;
+template <> struct Vec2<double> { using type = double2; };
+template <> struct Vec2<float> { using type = float2; };
+
+// sweep3 launch shape: planes per block for a level (MG_SWEEP3_KZ overrides)
+inline int sweep3_kz(int m) {
+  static const int forced = [] {
+    const char* e = getenv("MG_SWEEP3_KZ");
+    return e ? atoi(e) : 0;
+  }();
+  if (forced > 0) return forced;
+  return m >= 255 ? 16 : (m >= 127 ? 8 : 4);
+}
+
+template <typename T, int KIND, int MODE, bool ZERO, bool NORM>
+__global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
+                                                int nzc, Batch B) {
+  using V2 = typename Vec2<T>::type;
+  __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
+  __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
+  const int n = g.n, m = n - 1;
+  const long sy = g.sy, sz = g.sz;
+  const int item = blockIdx.z / nzc, zc = blockIdx.z % nzc;
+  const Item& I = B.it[item];
+  const T* __restrict__ x = (const T*)I.a;
+  const T* __restrict__ b = (const T*)I.b;
+  T* __restrict__ out = (T*)I.c;
+  const T* __restrict__ kap = (const T*)I.kappa;
+  const int i0 = 1 + blockIdx.x * SW_TX, j0 = 1 + blockIdx.y * SW_TY, k0 = 1 + zc * kz;
+  const int k1 = min(k0 + kz - 1, m);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int i = i0 + 2 * tx, j = j0 + ty;
+  const bool row_ok = j <= m;
+  const bool ok0 = row_ok && i <= m, ok1 = row_ok && i + 1 <= m;
+
+  // A plane of x (columns i0-1 .. i0+128, rows j0-1 .. j0+4) is staged by
+  // the block's threads, element e = tid + 256 q; a cell layer (cells
+  // i0-1 .. i0+127, j0-1 .. j0+3) likewise.  Loads go to registers first
+  // (prefetch) and are written to LDS one plane later (commit), so they are
+  // in flight while the previous plane is computed.
+  constexpr int NX = (SW_LX * SW_LY + 255) / 256;
+  constexpr int NK = ((SW_TX + 1) * (SW_TY + 1) + 255) / 256;
+  long xoff[NX];
+  bool xin_ok[NX];
+  T xpf[NX];
+#pragma unroll
+  for (int q = 0; q < NX; ++q) {
+    const int e = tid + 256 * q;
+    const int r = e / SW_LX, c = e - r * SW_LX;
+    const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+    xin_ok[q] = e < SW_LX * SW_LY && gi <= n && gj <= n;
+    xoff[q] = gi + gj * sy;
+  }
+  auto prefetch_x = [&](int z) {
+#pragma unroll
+    for (int q = 0; q < NX; ++q) xpf[q] = (xin_ok[q] && z <= n) ? x[xoff[q] + z * sz] : T(0);
+  };
+  auto commit_x = [&](int s) {
+    T* dst = &sx[s][0][0];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + 256 * q;
+      if (e < SW_LX * SW_LY) dst[e] = xpf[q];
+    }
+  };
+  long koff[NK];
+  bool kin_ok[NK];
+  T kpf[NK];
+  if (KIND == OP_KAPPA) {
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e / (SW_TX + 1), c = e - r * (SW_TX + 1);
+      const int cx = i0 - 1 + c, cy = j0 - 1 + r;
+      kin_ok[q] = e < (SW_TX + 1) * (SW_TY + 1) && cx <= n - 1 && cy <= n - 1;
+      koff[q] = cx + (long)n * cy;
+    }
+  }
+  auto prefetch_k = [&](int cz) {
+#pragma unroll
+    for (int q = 0; q < NK; ++q)
+      kpf[q] = (kin_ok[q] && cz <= n - 1) ? kap[koff[q] + (long)n * n * cz] : T(0);
+  };
+  auto commit_k = [&](int s) {
+    T* dst = &sk[s][0][0];
+#pragma unroll
+    for (int q = 0; q < NK; ++q) {
+      const int e = tid + 256 * q;
+      if (e < (SW_TX + 1) * (SW_TY + 1)) dst[e] = kpf[q];
+    }
+  };
+  // this thread's window of plane slot s: rows j-1..j+1, columns i-1..i+2
+  auto window_x = [&](int s, T (&w)[3][4]) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const V2* row = reinterpret_cast<const V2*>(&sx[s][ty + r][0]);
+      const V2 a = row[tx], c = row[tx + 1];
+      w[r][0] = a.x;
+      w[r][1] = a.y;
+      w[r][2] = c.x;
+      w[r][3] = c.y;
+    }
+  };
+  auto window_k = [&](int s, T (&w)[2][3]) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) w[r][c] = sk[s][ty + r][2 * tx + c];
+  };
+
+  // plane z lives in slot z & 1, cell layer z in slot z & 1
+  T wx[3][3][4];  // planes k-1, k, k+1
+  T wk[2][2][3];  // cell layers k-1, k
+  if (!ZERO) {
+    prefetch_x(k0 - 1);
+    commit_x((k0 - 1) & 1);
+    prefetch_x(k0);
+    commit_x(k0 & 1);
+    prefetch_x(k0 + 1);
+  }
+  if (KIND == OP_KAPPA) {
+    prefetch_k(k0 - 1);
+    commit_k((k0 - 1) & 1);
+    prefetch_k(k0);
+  }
+  __syncthreads();
+  if (!ZERO) {
+    window_x((k0 - 1) & 1, wx[0]);
+    window_x(k0 & 1, wx[1]);
+  }
+  if (KIND == OP_KAPPA) window_k((k0 - 1) & 1, wk[0]);
+  // the first plane committed in the loop reuses the slot of plane k0-1
+  __syncthreads();
+  // right-hand sides of the thread's two unknowns, one plane ahead
+  T bpf[2] = {T(0), T(0)};
+  auto prefetch_b = [&](int k) {
+    const long p = i + j * sy + (long)k * sz;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool ok = (u == 0 ? ok0 : ok1) && k <= k1;
+      const bool need = MODE == SW_RESID || MODE == SM_JACOBI ||
+                        (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
+      bpf[u] = (ok && need) ? b[p + u] : T(0);
+    }
+  };
+  prefetch_b(k0);
+  double sq = 0.0;
+  for (int k = k0; k <= k1; ++k) {
+    const int s = (k + 1) & 1;
+    if (!ZERO) {
+      commit_x(s);        // plane k+1
+      prefetch_x(k + 2);  // in flight while plane k is computed
+    }
+    if (KIND == OP_KAPPA) {
+      commit_k(k & 1);    // cell layer k
+      prefetch_k(k + 1);
+    }
+    const T bcur[2] = {bpf[0], bpf[1]};
+    prefetch_b(k + 1);
+    __syncthreads();
+    if (!ZERO) window_x(s, wx[2]);
+    if (KIND == OP_KAPPA) window_k(k & 1, wk[1]);
+    const long p = i + j * sy + (long)k * sz;
+    // the two unknowns (column 1 = i, column 2 = i+1 of the window)
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const bool ok = u == 0 ? ok0 : ok1;
+      const bool upd = MODE == SW_RESID || MODE == SM_JACOBI ||
+                       (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
+      if (!ok) continue;
+      if (!upd) {
+        out[p + u] = ZERO ? T(0) : wx[1][1][1 + u];
+        continue;
+      }
+      T kk[2][2][2];
+      if (KIND == OP_KAPPA) {
+#pragma unroll
+        for (int c = 0; c < 2; ++c)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int a = 0; a < 2; ++a) kk[c][bb][a] = wk[c][bb][u + a];
+      }
+      if (ZERO) {
+        const T dg = KIND == OP_KAPPA ? kappa_diag3(op, kk) : op.wc;
+        out[p + u] = MODE == SM_JACOBI ? omega * (bcur[u] / dg) : bcur[u] / dg;
+        continue;
+      }
+      T v[3][3][3];
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = wx[dz][dy][u + dx];
+      T ax, dg;
+      if (KIND == OP_KAPPA) {
+        ax = stencil3_kappa(op, kk, v, dg);
+      } else {
+        ax = stencil3_const(op, v);
+        dg = op.wc;
+      }
+      if (MODE == SW_RESID) {
+        const T res = bcur[u] - ax;
+        out[p + u] = res;
+        sq += (double)res * (double)res;
+      } else {
+        const T q = (bcur[u] - ax) / dg;
+        out[p + u] = MODE == SM_JACOBI ? v[1][1][1] + omega * q : v[1][1][1] + q;
+      }
+    }
+    if (!ZERO) {
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          wx[0][r][c] = wx[1][r][c];
+          wx[1][r][c] = wx[2][r][c];
+        }
+    }
+    if (KIND == OP_KAPPA) {
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) wk[0][r][c] = wk[1][r][c];
+    }
+  }
+  if (MODE == SW_RESID && NORM) {
+    const double t = block_sum(sq);
+    if (tid == 0)
+      I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * zc)] = t;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -475,88 +773,126 @@ __device__ __forceinline__ void for_unknowns(int n, const DGeo& g, F f) {
   }
 }
 
-template <typename T, int DIM, int KIND>
-__device__ void tail_smooth(const TailDesc<T>& D, int l, bool pre, T** cur, T** spr,
-                            bool* zero, const T* b) {
-  const TailLevel<T>& Lv = D.lv[l];
-  const DGeo g = dgeo(DIM, Lv.n);
-  const StencilParams<T> op{KIND, Lv.wc, Lv.w1, Lv.w2, Lv.s};
-  const int nu = pre ? D.nu_pre : D.nu_post;
-  for (int it = 0; it < nu; ++it) {
-    const int nsteps = D.smoother == 0 ? 1 : 2;
-    for (int h = 0; h < nsteps; ++h) {
-      const int ks = D.smoother == 0 ? SM_JACOBI : ((h == 0) == pre ? SM_RB0 : SM_RB1);
-      const T* xin = *zero ? nullptr : *cur;
-      T* xout = *spr;
-      for_unknowns<DIM>(Lv.n, g, [&](long p, int i, int j, int k) {
-        xout[p] = smooth_node<T, DIM, KIND>(op, Lv.kappa, g, ks, xin, b, D.omega, p, i, j, k);
-      });
-      __syncthreads();
-      T* tmp = *cur;
-      *cur = *spr;
-      *spr = tmp;
-      *zero = false;
-    }
-  }
-}
-
+// The tail keeps every vector of its levels in the launch's dynamic LDS
+// (element offsets in TailDesc): iterate, spare, right-hand side, residual
+// and, for OP_KAPPA, the cell coefficients.  The region is zeroed first, so
+// boundary entries read 0; the first level's right-hand side and iterate
+// (unless it starts at 0) and the coefficients are copied in, the iterate
+// is copied out at the end.  Bit l of `par` tells whether level l's
+// iterate currently sits in its spare buffer.
 template <typename T, int DIM, int KIND>
 __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
-  __shared__ double ysh[kCoarseMaxUnknowns];
+  extern __shared__ __align__(16) char tail_lds[];
+  __shared__ TailDesc<T> D;
   const Item& I = B.it[blockIdx.x];
-  const TailDesc<T>& D = *(const TailDesc<T>*)I.a;
-  const int nl = D.nlev;
-  T* cur[kTailMaxLevels];
-  T* spr[kTailMaxLevels];
-  const T* bb[kTailMaxLevels];
-  for (int l = 0; l < nl; ++l) {
-    cur[l] = l == 0 ? (T*)I.c : D.lv[l].x;
-    spr[l] = D.lv[l].t;
-    bb[l] = l == 0 ? (const T*)I.b : D.lv[l].b;
+  {
+    const int* src = reinterpret_cast<const int*>(I.a);
+    int* dst = reinterpret_cast<int*>(&D);
+    for (int q = threadIdx.x; q < (int)(sizeof(TailDesc<T>) / sizeof(int)); q += blockDim.x)
+      dst[q] = src[q];
   }
+  __syncthreads();
+  {
+    float4* z = reinterpret_cast<float4*>(tail_lds);
+    for (int q = threadIdx.x; q < D.lds_bytes / 16; q += blockDim.x)
+      z[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  __syncthreads();
+  T* const sm = reinterpret_cast<T*>(tail_lds);
+  const int nl = D.nlev;
+  T* const x0g = (T*)I.c;
+  const T* const b0g = (const T*)I.b;
+  if (KIND == OP_KAPPA) {
+    for (int l = 0; l < nl; ++l) {
+      const int n = D.lv[l].n;
+      const int cells = DIM == 3 ? n * n * n : n * n;
+      T* dst = sm + D.lv[l].ok;
+      const T* src = D.lv[l].kappa;
+      for (int q = threadIdx.x; q < cells; q += blockDim.x) dst[q] = src[q];
+    }
+  }
+  {
+    T* xd = sm + D.lv[0].ox;
+    T* bd = sm + D.lv[0].ob;
+    const bool cx = !I.flag;
+    for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n), [&](long p, int, int, int) {
+      bd[p] = b0g[p];
+      if (cx) xd[p] = x0g[p];
+    });
+  }
+  __syncthreads();
+  int par = 0;
+  auto X = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ot : D.lv[l].ox); };
+  auto S = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ox : D.lv[l].ot); };
+  auto params = [&](int l) {
+    return StencilParams<T>{KIND, D.lv[l].wc, D.lv[l].w1, D.lv[l].w2, D.lv[l].s};
+  };
+  // nu sweeps on level l from X(l) (or from 0 if *zero)
+  auto smooth = [&](int l, bool pre, bool* zero) {
+    const int n = D.lv[l].n;
+    const DGeo g = dgeo(DIM, n);
+    const StencilParams<T> op = params(l);
+    const T* kap = sm + D.lv[l].ok;
+    const T* b = sm + D.lv[l].ob;
+    const T omega = D.omega;
+    const int smoother = D.smoother;
+    const int nu = pre ? D.nu_pre : D.nu_post;
+    for (int it = 0; it < nu; ++it) {
+      for (int h = 0; h < (smoother == 0 ? 1 : 2); ++h) {
+        const int ks = smoother == 0 ? SM_JACOBI : ((h == 0) == pre ? SM_RB0 : SM_RB1);
+        const T* xin = *zero ? nullptr : X(l);
+        T* xout = S(l);
+        for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
+          xout[p] = smooth_node<T, DIM, KIND>(op, kap, g, ks, xin, b, omega, p, i, j, k);
+        });
+        __syncthreads();
+        par ^= 1 << l;
+        *zero = false;
+      }
+    }
+  };
   for (int l = 0; l + 1 < nl; ++l) {
-    const TailLevel<T>& Lv = D.lv[l];
-    const DGeo g = dgeo(DIM, Lv.n);
+    const int n = D.lv[l].n;
+    const DGeo g = dgeo(DIM, n);
     bool zero = (l > 0) || I.flag;
-    tail_smooth<T, DIM, KIND>(D, l, true, &cur[l], &spr[l], &zero, bb[l]);
-    T* x = cur[l];
+    smooth(l, true, &zero);
+    T* x = X(l);
     if (zero) {
-      for_unknowns<DIM>(Lv.n, g, [&](long p, int, int, int) { x[p] = T(0); });
+      for_unknowns<DIM>(n, g, [&](long p, int, int, int) { x[p] = T(0); });
       __syncthreads();
     }
-    const StencilParams<T> op{KIND, Lv.wc, Lv.w1, Lv.w2, Lv.s};
-    T* r = Lv.r;
-    const T* b = bb[l];
-    for_unknowns<DIM>(Lv.n, g, [&](long p, int i, int j, int k) {
-      r[p] = residual_node<T, DIM, KIND>(op, Lv.kappa, g, x, b, p, i, j, k);
+    const StencilParams<T> op = params(l);
+    const T* kap = sm + D.lv[l].ok;
+    const T* b = sm + D.lv[l].ob;
+    T* r = sm + D.lv[l].orr;
+    for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
+      r[p] = residual_node<T, DIM, KIND>(op, kap, g, x, b, p, i, j, k);
     });
     __syncthreads();
-    const DGeo gc = dgeo(DIM, D.lv[l + 1].n);
-    T* bc = D.lv[l + 1].b;
-    for_unknowns<DIM>(D.lv[l + 1].n, gc, [&](long p, int i, int j, int k) {
+    const int nc = D.lv[l + 1].n;
+    T* bc = sm + D.lv[l + 1].ob;
+    for_unknowns<DIM>(nc, dgeo(DIM, nc), [&](long p, int i, int j, int k) {
       bc[p] = restrict_node<T, DIM>(g, r, i, j, k);
     });
     __syncthreads();
   }
-  cholesky_solve_block<T>(DIM, D.lv[nl - 1].n, D.L, D.m, bb[nl - 1], cur[nl - 1], ysh);
+  cholesky_solve_block<T>(DIM, D.lv[nl - 1].n, D.L, D.m, sm + D.lv[nl - 1].ob, X(nl - 1),
+                          reinterpret_cast<double*>(tail_lds + D.oy));
   for (int l = nl - 2; l >= 0; --l) {
-    const DGeo g = dgeo(DIM, D.lv[l].n);
+    const int n = D.lv[l].n;
     const DGeo gc = dgeo(DIM, D.lv[l + 1].n);
-    T* x = cur[l];
-    const T* e = cur[l + 1];
-    for_unknowns<DIM>(D.lv[l].n, g, [&](long p, int i, int j, int k) {
+    T* x = X(l);
+    const T* e = X(l + 1);
+    for_unknowns<DIM>(n, dgeo(DIM, n), [&](long p, int i, int j, int k) {
       x[p] += prolong_node<T, DIM>(gc, e, i, j, k);
     });
     __syncthreads();
     bool zero = false;
-    tail_smooth<T, DIM, KIND>(D, l, false, &cur[l], &spr[l], &zero, bb[l]);
+    smooth(l, false, &zero);
   }
-  if (cur[0] != (T*)I.c) {
-    T* out = (T*)I.c;
-    const T* src = cur[0];
-    const DGeo g = dgeo(DIM, D.lv[0].n);
-    for_unknowns<DIM>(D.lv[0].n, g, [&](long p, int, int, int) { out[p] = src[p]; });
-  }
+  const T* src = X(0);
+  for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n),
+                    [&](long p, int, int, int) { x0g[p] = src[p]; });
 }
 
 // ---------------------------------------------------------------------------
@@ -612,7 +948,38 @@ inline unsigned flat_blocks(long count) {
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+namespace {
+// 3D levels with at least 31 unknowns per direction use k_sweep3.
+inline bool use_sweep3(const Geo& g) { return g.dim == 3 && g.n >= 32; }
+
+inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc) {
+  const int m = g.n - 1;
+  *kz = sweep3_kz(m);
+  *nzc = (int)cdiv(m, *kz);
+  return dim3(cdiv(m, SW_TX), cdiv(m, SW_TY), (unsigned)(*nzc * count));
+}
+
+template <typename T, int K, int MODE, bool ZERO, bool NORM>
+void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batch& B,
+                   hipStream_t s) {
+  int kz, nzc;
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM>), gr, dim3(64, SW_TY), 0, s, g, op, omega,
+                     kz, nzc, B);
+}
+}  // namespace
+
+long norm2_blocks(const Geo& g) {
+  dim3 gr = node_grid(g, 1);
+  return (long)gr.x * gr.y * gr.z;
+}
+
 long grid_blocks(const Geo& g) {
+  if (use_sweep3(g)) {
+    int kz, nzc;
+    const dim3 gr = sweep3_grid(g, 1, &kz, &nzc);
+    return (long)gr.x * gr.y * gr.z;
+  }
   dim3 gr = node_grid(g, 1);
   return (long)gr.x * gr.y * gr.z;
 }
@@ -638,6 +1005,17 @@ void launch_copy(const T* a, T* b, long count, hipStream_t s) {
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
                      hipStream_t s) {
+  if (use_sweep3(g)) {
+    const bool kap = op.kind == OP_KAPPA;
+    if (norm) {
+      if (kap) launch_sweep3<T, OP_KAPPA, SW_RESID, false, true>(g, op, T(0), B, s);
+      else launch_sweep3<T, OP_CONST, SW_RESID, false, true>(g, op, T(0), B, s);
+    } else {
+      if (kap) launch_sweep3<T, OP_KAPPA, SW_RESID, false, false>(g, op, T(0), B, s);
+      else launch_sweep3<T, OP_CONST, SW_RESID, false, false>(g, op, T(0), B, s);
+    }
+    return;
+  }
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
 #define L_RES(D, K)                                                                   \
   do {                                                                                \
@@ -662,9 +1040,30 @@ static void launch_smooth_k(const Geo& g, const StencilParams<T>& op, int kind, 
     hipLaunchKernelGGL((k_smooth<T, D, K, SM_RB1, Z>), gr, bl, 0, s, g, op, omega, B);
 }
 
+template <typename T, int K, bool Z>
+static void launch_sweep3_smooth(const Geo& g, const StencilParams<T>& op, int kind, T omega,
+                                 const Batch& B, hipStream_t s) {
+  if (kind == SM_JACOBI)
+    launch_sweep3<T, K, SM_JACOBI, Z, false>(g, op, omega, B, s);
+  else if (kind == SM_RB0)
+    launch_sweep3<T, K, SM_RB0, Z, false>(g, op, omega, B, s);
+  else
+    launch_sweep3<T, K, SM_RB1, Z, false>(g, op, omega, B, s);
+}
+
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s) {
+  if (use_sweep3(g)) {
+    if (op.kind == OP_KAPPA) {
+      if (zero) launch_sweep3_smooth<T, OP_KAPPA, true>(g, op, kind, omega, B, s);
+      else launch_sweep3_smooth<T, OP_KAPPA, false>(g, op, kind, omega, B, s);
+    } else {
+      if (zero) launch_sweep3_smooth<T, OP_CONST, true>(g, op, kind, omega, B, s);
+      else launch_sweep3_smooth<T, OP_CONST, false>(g, op, kind, omega, B, s);
+    }
+    return;
+  }
 #define L_SM(D, K)                                                       \
   do {                                                                   \
     if (zero)                                                            \
@@ -728,10 +1127,20 @@ void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s) {
     hipLaunchKernelGGL(k_ir_update<3>, gr, bl, 0, s, g, B);
 }
 
+template <typename T, int D, int K>
+static void launch_tail_k(int lds_bytes, const Batch& B, hipStream_t s) {
+  static const bool attr = [] {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail<T, D, K>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kTailLdsBytes) == hipSuccess;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((k_tail<T, D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B);
+}
+
 template <typename T>
-void launch_tail(int dim, int kind, const Batch& B, hipStream_t s) {
-#define L_TAIL(D, K) \
-  hipLaunchKernelGGL((k_tail<T, D, K>), dim3(B.count), dim3(TAIL_THREADS), 0, s, B)
+void launch_tail(int dim, int kind, int lds_bytes, const Batch& B, hipStream_t s) {
+#define L_TAIL(D, K) launch_tail_k<T, D, K>(lds_bytes, B, s)
   DISPATCH_DIM_KIND(dim, kind, L_TAIL);
 #undef L_TAIL
 }
@@ -767,7 +1176,7 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_prolong_add<T>(const Geo&, const Geo&, const Batch&, hipStream_t);   \
   template void launch_coarse_solve<T>(const Geo&, int, const Batch&, hipStream_t);         \
   template void launch_norm2_partial<T>(const Geo&, const Batch&, hipStream_t);             \
-  template void launch_tail<T>(int, int, const Batch&, hipStream_t);
+  template void launch_tail<T>(int, int, int, const Batch&, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -95,6 +95,7 @@ struct mg_ctx {
   int* ibuf = nullptr;          // device ints (setup checks)
   void* tail64 = nullptr;       // TailDesc<double> (device)
   void* tail32 = nullptr;       // TailDesc<float> (device)
+  int tail_lds[2] = {0, 0};     // dynamic LDS bytes of the tail launch (FP64, FP32)
   double* pinned = nullptr;     // host pinned scalars
   hipStream_t cap = nullptr;    // private stream for graph capture
   hipGraphExec_t gexec = nullptr;

@@ -97,16 +97,16 @@ struct CsrOp {
 enum SmoothKind { SM_JACOBI = 0, SM_RB0 = 1, SM_RB1 = 2 };
 
 // Device-resident description of the tail levels l0..L-1 of one request:
-// the V-cycle below level l0 runs inside one workgroup.
+// the V-cycle below level l0 runs inside one workgroup, with every vector
+// of these levels in the launch's dynamic LDS.  Offsets are in elements of
+// T from the start of that LDS region.
 template <typename T>
 struct TailLevel {
   int n;
-  const T* kappa;  // OP_KAPPA cells or nullptr
-  T* x;            // iterate
-  T* t;            // spare for out-of-place sweeps
-  T* b;            // right-hand side
-  T* r;            // residual scratch
-  T wc, w1, w2, s; // operator parameters of the level
+  int ox, ot, ob, orr;  // iterate, spare, right-hand side, residual
+  int ok;               // cell coefficients (OP_KAPPA)
+  const T* kappa;       // device copy of the level's coefficients (OP_KAPPA)
+  T wc, w1, w2, s;      // operator parameters of the level
 };
 template <typename T>
 struct TailDesc {
@@ -117,16 +117,41 @@ struct TailDesc {
   int nu_pre, nu_post;
   T omega;
   int m;           // coarsest unknowns
-  const double* L; // coarsest Cholesky factor
+  const double* L; // coarsest Cholesky factor (device memory)
+  int oy;          // byte offset of the coarsest solve's m doubles
+  int lds_bytes;   // dynamic LDS of the launch
   TailLevel<T> lv[kTailMaxLevels];
 };
+
+// LDS a tail launch may use (gfx950 has 160 KB per workgroup).
+constexpr int kTailLdsBytes = 150 * 1024;
+
+// LDS bytes the tail needs for levels l0..levels-1 of a hierarchy.
+inline long tail_lds_bytes(int dim, int n, int levels, int l0, bool kappa, int elem) {
+  long bytes = 0;
+  for (int l = l0; l < levels; ++l) {
+    const long nl = n >> l;
+    long nodes = (nl + 1) * (nl + 1), cells = nl * nl;
+    if (dim == 3) {
+      nodes *= nl + 1;
+      cells *= nl;
+    }
+    bytes += 4 * ((nodes * elem + 15) / 16 * 16);
+    if (kappa) bytes += (cells * elem + 15) / 16 * 16;
+  }
+  long nc = n >> (levels - 1), m = 1;
+  for (int d = 0; d < dim; ++d) m *= nc - 1;
+  return bytes + (m * 8 + 15) / 16 * 16;
+}
 
 // ---- grid kernels (kernels_grid.hip) -------------------------------------
 template <typename T> void launch_fill(T* v, long count, T val, hipStream_t s);
 template <typename T> void launch_copy(const T* a, T* b, long count, hipStream_t s);
 
-// Number of per-block partial sums of a norm-producing launch per request.
+// Number of per-block partial sums per request written by a residual
+// launch (grid_blocks) and by a norm launch (norm2_blocks).
 long grid_blocks(const Geo& g);
+long norm2_blocks(const Geo& g);
 
 // r = b - A x (+ per-block partial sums of r^2 when `norm`):
 //   a = x, b = b, c = r, kappa, partials.
@@ -160,7 +185,7 @@ void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s);
 // (device), b = level-l0 right-hand side, c = level-l0 iterate (updated in
 // place), flag = 1 when the level-l0 iterate starts at 0 (not read).
 template <typename T>
-void launch_tail(int dim, int kind, const Batch& B, hipStream_t s);
+void launch_tail(int dim, int kind, int lds_bytes, const Batch& B, hipStream_t s);
 
 void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s);
 void launch_cast_f32(const double* a, float* b, long count, hipStream_t s);

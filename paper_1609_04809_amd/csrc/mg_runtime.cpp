@@ -112,13 +112,16 @@ bool valid_options(const mg_options* o, std::string& why) {
 }
 
 // First level handled by the tail kernel: the finest level from which on
-// every level has at most kTailMaxUnknowns unknowns (matrix-free operator
-// only, and at most kTailMaxLevels levels).
-int tail_start(const mg_options& o) {
+// every level has at most kTailMaxUnknowns unknowns and all their vectors
+// (FP64) fit the tail's LDS (matrix-free operator only, at most
+// kTailMaxLevels levels); -1 if not even the coarsest level fits.
+int tail_start(const mg_options& o, bool kappa) {
   if (o.op != MG_OP_STENCIL || (o.flags & MG_FLAG_NO_TAIL)) return -1;
   int l0 = o.levels - 1;
+  if (tail_lds_bytes(o.dim, o.n, o.levels, l0, kappa, 8) > kTailLdsBytes) return -1;
   while (l0 > 0 && ipow((o.n >> (l0 - 1)) - 1, o.dim) <= kTailMaxUnknowns &&
-         o.levels - (l0 - 1) <= kTailMaxLevels)
+         o.levels - (l0 - 1) <= kTailMaxLevels &&
+         tail_lds_bytes(o.dim, o.n, o.levels, l0 - 1, kappa, 8) <= kTailLdsBytes)
     --l0;
   return l0;
 }
@@ -164,7 +167,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
       if (ir) L.val32 = P.take<float>(nnz);
       maxpart = std::max(maxpart, csr_residual_blocks_max((int)rows));
     }
-    maxpart = std::max(maxpart, grid_blocks(g));
+    maxpart = std::max(maxpart, std::max(grid_blocks(g), norm2_blocks(g)));
   }
   const long nc = o.n >> (o.levels - 1);
   const int m = (int)ipow(nc - 1, o.dim);
@@ -379,13 +382,37 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
     D.omega = (T)c->o.omega;
     D.m = c->m;
     D.L = c->Lc;
+    // LDS layout (16-byte aligned pieces): per level iterate, spare,
+    // right-hand side, residual (and cells), then the coarsest solve's
+    // work vector; offsets of level vectors in elements of T
+    long off = 0;
+    auto take = [&](long bytes) {
+      const long at = off;
+      off += (bytes + 15) / 16 * 16;
+      return at;
+    };
     for (int q = 0; q < D.nlev; ++q) {
       Level& Lv = c->lv[l0 + q];
       const StencilParams<T>& st = Bufs<T>::st(Lv);
-      D.lv[q] = TailLevel<T>{Lv.g.n, Bufs<T>::kap(Lv), Bufs<T>::x(Lv), Bufs<T>::t(Lv),
-                             Bufs<T>::b(Lv), Bufs<T>::r(Lv), st.wc, st.w1, st.w2, st.s};
+      const long vb = Lv.g.nodes * (long)sizeof(T);
+      TailLevel<T>& tl = D.lv[q];
+      tl.n = Lv.g.n;
+      tl.ox = (int)(take(vb) / sizeof(T));
+      tl.ot = (int)(take(vb) / sizeof(T));
+      tl.ob = (int)(take(vb) / sizeof(T));
+      tl.orr = (int)(take(vb) / sizeof(T));
+      tl.ok = c->kappa ? (int)(take(ipow(Lv.g.n, c->o.dim) * (long)sizeof(T)) / sizeof(T)) : 0;
+      tl.kappa = Bufs<T>::kap(Lv);
+      tl.wc = st.wc;
+      tl.w1 = st.w1;
+      tl.w2 = st.w2;
+      tl.s = st.s;
     }
+    D.oy = (int)take((long)c->m * sizeof(double));
+    if (off > kTailLdsBytes) return fail(MG_E_ARG, "internal: tail levels exceed the LDS budget");
+    D.lds_bytes = (int)off;
   }
+  c->tail_lds[Bufs<T>::prec] = D.lds_bytes;
   HIP_TRY(hipMemcpyAsync(Bufs<T>::tail(c), &D, sizeof D, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MG_OK;
@@ -515,6 +542,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
   }
   if (c->tail0 >= 0) {
     OpRec o = base_op<T>(c, OC_TAIL, lt);
+    o.count = c->tail_lds[Bufs<T>::prec];
     o.item.a = Bufs<T>::tail(c);
     o.item.b = bb[lt];
     o.item.c = cur[lt];
@@ -575,7 +603,7 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
   o.item.a = b;
   o.item.partials = c->partials;
   sink(o);
-  emit_reduce(c, sink, grid_blocks(L0.g), c->scal + 1);
+  emit_reduce(c, sink, norm2_blocks(L0.g), c->scal + 1);
   if (c->ir) {
     emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
     emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
@@ -706,7 +734,7 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
     case OC_PROLONG: launch_prolong_add<T>(o.g, o.gc, B, s); break;
     case OC_COARSE: launch_coarse_solve<T>(o.g, o.m, B, s); break;
     case OC_NORM2: launch_norm2_partial<T>(o.g, B, s); break;
-    case OC_TAIL: launch_tail<T>(o.g.dim, o.opkind, B, s); break;
+    case OC_TAIL: launch_tail<T>(o.g.dim, o.opkind, (int)o.count, B, s); break;
     case OC_FILL: launch_fill<T>((T*)it.c, o.count, T(0), s); break;
     case OC_COPY: launch_copy<T>((const T*)it.a, (T*)it.c, o.count, s); break;
     case OC_CSR_SMOOTH:
@@ -813,7 +841,7 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
   c->kappa = kappa_dev != nullptr;
   c->ir = o->precision == MG_PREC_FP32_IR;
   c->csr = o->op == MG_OP_CSR;
-  c->tail0 = tail_start(*o);
+  c->tail0 = tail_start(*o, c->kappa);
   c->lv.resize(c->L);
   auto bail = [&](mg_status st) {
     mg_destroy(c);
@@ -1085,7 +1113,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
     o.item.a = v;
     o.item.partials = c->partials;
     sink(o);
-    emit_reduce(c, sink, grid_blocks(c->lv[level].g), c->scal + 2);
+    emit_reduce(c, sink, norm2_blocks(c->lv[level].g), c->scal + 2);
   });
   if (st != MG_OK) return st;
   return read_scalar(c, 2, out, s);
