@@ -113,10 +113,12 @@ bool valid_options(const mg_options* o, std::string& why) {
 
 // First level handled by the tail kernel: the finest level from which on
 // every level has at most kTailMaxUnknowns unknowns and all their vectors
-// (FP64) fit the tail's LDS (matrix-free operator only, at most
-// kTailMaxLevels levels); -1 if not even the coarsest level fits.
+// (FP64) fit the tail's LDS (at most kTailMaxLevels levels); -1 if not even
+// the coarsest level fits.  The tail applies each level's operator
+// matrix-free, also in a CSR hierarchy: the CSR matrices hold the same
+// rediscretised entries (up to the rounding of each entry).
 int tail_start(const mg_options& o, bool kappa) {
-  if (o.op != MG_OP_STENCIL || (o.flags & MG_FLAG_NO_TAIL)) return -1;
+  if (o.flags & MG_FLAG_NO_TAIL) return -1;
   int l0 = o.levels - 1;
   if (tail_lds_bytes(o.dim, o.n, o.levels, l0, kappa, 8) > kTailLdsBytes) return -1;
   while (l0 > 0 && ipow((o.n >> (l0 - 1)) - 1, o.dim) <= kTailMaxUnknowns &&
