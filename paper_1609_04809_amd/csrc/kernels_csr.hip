@@ -68,6 +68,9 @@ __device__ __forceinline__ V ld_stream(const V* p) {
 // MODE 1: damped Jacobi update of rows [r_begin, r_end).
 // MODE 2: red-black update of the rows of one colour [r_begin, r_end); the
 //         other colour's unknowns are copied alongside (see below).
+// MODE 3: over all rows, the residual partial sums of MODE 0 and, written to
+//         out, the colour-0 red-black update with colour-1 unknowns copied.
+// MODE 4: over all rows, the residual partial sums and the Jacobi update.
 // ZERO: x = 0 (x is not read).
 // Phase 1 issues all column and value loads of a thread before any gather,
 // so that about 2 * PER loads per thread are in flight.
@@ -86,9 +89,31 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begi
   const int blk = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int r0 = r_begin + blk * ROWS;
   const int nr = min(ROWS, r_end - r0);
+  // The owner thread of each row (lane 0 of its group) fetches the row's
+  // node, right-hand side, current value, diagonal and (red-black) the
+  // other-colour neighbours to copy, early: these loads are in flight
+  // together with the row pointers and the matrix stream below.
+  const int lr = tid / TPR, lane = tid % TPR;
+  const bool owner = lane == 0 && lr < nr;
+  int node = 0;
+  if (owner) node = A.rowmap[r0 + lr];
   if (tid <= nr) rp[tid] = A.rowptr[r0 + tid];
   __syncthreads();
   const int base = rp[0];
+  T bv = T(0), x0 = T(0), dg = T(1), xr = T(0), xl = T(0);
+  bool copy_r = false, copy_l = false;
+  if (owner) {
+    bv = b[node];
+    if (!ZERO && MODE != 0) x0 = xin[node];
+    if (MODE != 0) dg = A.val[rp[lr]];
+    if (MODE == 2) {
+      const int ix = (int)(node % A.sy);
+      copy_r = ix + 1 <= A.n - 1;
+      copy_l = ix == 2;
+      if (!ZERO && copy_r) xr = xin[node + 1];
+      if (!ZERO && copy_l) xl = xin[node - 1];
+    }
+  }
   if (!ZERO) {
     const int cnt = rp[nr] - base;
     int cl[PER];
@@ -108,7 +133,6 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begi
     }
   }
   __syncthreads();
-  const int lr = tid / TPR, lane = tid % TPR;
   T s = T(0);
   if (!ZERO && lr < nr) {
     const int e1 = rp[lr + 1] - base;
@@ -117,28 +141,32 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begi
 #pragma unroll
   for (int off = 1; off < TPR; off <<= 1) s += __shfl_xor(s, off);
   double sq = 0.0;
-  if (lane == 0 && lr < nr) {
-    const int node = A.rowmap[r0 + lr];
-    const T res = b[node] - s;
+  if (owner) {
+    const T res = bv - s;
     if (MODE == 0) {
       out[node] = res;
       sq = (double)res * (double)res;
+    } else if (MODE >= 3) {
+      // residual of every row plus the first smoothing step: Jacobi (4)
+      // updates every row, red-black (3) the colour-0 rows, which come first
+      sq = (double)res * (double)res;
+      const bool upd = MODE == 4 || r0 + lr < A.coff[1];
+      const T q = res / dg;
+      out[node] = upd ? (MODE == 4 ? x0 + omega * q : x0 + q) : x0;
     } else {
-      const T q = res / A.val[rp[lr]];
-      const T x0 = ZERO ? T(0) : xin[node];
+      const T q = res / dg;
       out[node] = MODE == 1 ? x0 + omega * q : x0 + q;
       if (MODE == 2) {
         // Copy the other colour along the grid row: node p+1 (and p-1 for
         // the colour's first node at x = 2).  Every other-colour unknown of
         // the row is copied exactly once, by the block that also writes its
         // neighbour, so each cache line is written by one block.
-        const int ix = (int)(node % A.sy);
-        if (ix + 1 <= A.n - 1) out[node + 1] = ZERO ? T(0) : xin[node + 1];
-        if (ix == 2) out[node - 1] = ZERO ? T(0) : xin[node - 1];
+        if (copy_r) out[node + 1] = xr;
+        if (copy_l) out[node - 1] = xl;
       }
     }
   }
-  if (MODE == 0 && partials != nullptr) {
+  if ((MODE == 0 || MODE >= 3) && partials != nullptr) {
     const double t = block_sum_1d(sq);
     if (tid == 0) partials[blk] = t;
   }

@@ -864,17 +864,22 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
     const StencilParams<T> op = params(l);
     const T* kap = sm + D.lv[l].ok;
     const T* b = sm + D.lv[l].ob;
-    T* r = sm + D.lv[l].orr;
-    for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
-      r[p] = residual_node<T, DIM, KIND>(op, kap, g, x, b, p, i, j, k);
-    });
-    __syncthreads();
     const int nc = D.lv[l + 1].n;
     T* bc = sm + D.lv[l + 1].ob;
-    for_unknowns<DIM>(nc, dgeo(DIM, nc), [&](long p, int i, int j, int k) {
-      bc[p] = restrict_node<T, DIM>(g, r, i, j, k);
-    });
-    __syncthreads();
+    auto resid_restrict = [&](T* r) {
+      for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
+        r[p] = residual_node<T, DIM, KIND>(op, kap, g, x, b, p, i, j, k);
+      });
+      __syncthreads();
+      for_unknowns<DIM>(nc, dgeo(DIM, nc), [&](long p, int i, int j, int k) {
+        bc[p] = restrict_node<T, DIM>(g, r, i, j, k);
+      });
+      __syncthreads();
+    };
+    if (l == 0 && D.r0 != nullptr)
+      resid_restrict(D.r0);  // device memory
+    else
+      resid_restrict(sm + D.lv[l].orr);
   }
   cholesky_solve_block<T>(DIM, D.lv[nl - 1].n, D.L, D.m, sm + D.lv[nl - 1].ob, X(nl - 1),
                           reinterpret_cast<double*>(tail_lds + D.oy));

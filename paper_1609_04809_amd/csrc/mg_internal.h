@@ -120,14 +120,17 @@ struct TailDesc {
   const double* L; // coarsest Cholesky factor (device memory)
   int oy;          // byte offset of the coarsest solve's m doubles
   int lds_bytes;   // dynamic LDS of the launch
+  T* r0;           // first level's residual in device memory (nullptr: in LDS)
   TailLevel<T> lv[kTailMaxLevels];
 };
 
 // LDS a tail launch may use (gfx950 has 160 KB per workgroup).
 constexpr int kTailLdsBytes = 150 * 1024;
 
-// LDS bytes the tail needs for levels l0..levels-1 of a hierarchy.
-inline long tail_lds_bytes(int dim, int n, int levels, int l0, bool kappa, int elem) {
+// LDS bytes the tail needs for levels l0..levels-1 of a hierarchy (with the
+// first level's residual in device memory when r0_global).
+inline long tail_lds_bytes(int dim, int n, int levels, int l0, bool kappa, int elem,
+                           bool r0_global) {
   long bytes = 0;
   for (int l = l0; l < levels; ++l) {
     const long nl = n >> l;
@@ -136,7 +139,7 @@ inline long tail_lds_bytes(int dim, int n, int levels, int l0, bool kappa, int e
       nodes *= nl + 1;
       cells *= nl;
     }
-    bytes += 4 * ((nodes * elem + 15) / 16 * 16);
+    bytes += (l == l0 && r0_global ? 3 : 4) * ((nodes * elem + 15) / 16 * 16);
     if (kappa) bytes += (cells * elem + 15) / 16 * 16;
   }
   long nc = n >> (levels - 1), m = 1;

@@ -119,11 +119,13 @@ bool valid_options(const mg_options* o, std::string& why) {
 // rediscretised entries (up to the rounding of each entry).
 int tail_start(const mg_options& o, bool kappa) {
   if (o.flags & MG_FLAG_NO_TAIL) return -1;
+  auto fits = [&](int l) {
+    return tail_lds_bytes(o.dim, o.n, o.levels, l, kappa, 8, true) <= kTailLdsBytes;
+  };
   int l0 = o.levels - 1;
-  if (tail_lds_bytes(o.dim, o.n, o.levels, l0, kappa, 8) > kTailLdsBytes) return -1;
+  if (!fits(l0)) return -1;
   while (l0 > 0 && ipow((o.n >> (l0 - 1)) - 1, o.dim) <= kTailMaxUnknowns &&
-         o.levels - (l0 - 1) <= kTailMaxLevels &&
-         tail_lds_bytes(o.dim, o.n, o.levels, l0 - 1, kappa, 8) <= kTailLdsBytes)
+         o.levels - (l0 - 1) <= kTailMaxLevels && fits(l0 - 1))
     --l0;
   return l0;
 }
@@ -276,7 +278,12 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   rowptr[0] = 0;
   int idx = 0;
   auto cnt = [&](int i) { return 1 + (i > 1) + (i < n - 1); };
-  const int T = dim == 3 ? kCsrTile : n;
+  static const int tile = [] {  // MG_CSR_TILE overrides the tile edge
+    const char* e = getenv("MG_CSR_TILE");
+    const int t = e ? atoi(e) : 0;
+    return t > 0 ? t : kCsrTile;
+  }();
+  const int T = dim == 3 ? tile : n;
   const int kmin = dim == 3 ? 1 : 0, kmax = dim == 3 ? n - 1 : 0;
   for (int colour = 0; colour < 2; ++colour) {
     if (colour == 1) Lv.coff[1] = idx;
@@ -393,6 +400,11 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
       off += (bytes + 15) / 16 * 16;
       return at;
     };
+    // the first level's residual goes to device memory when all else fits
+    // the LDS only without it
+    const bool r0_global = tail_lds_bytes(c->o.dim, c->o.n, c->L, l0, c->kappa,
+                                          (int)sizeof(T), false) > kTailLdsBytes;
+    D.r0 = r0_global ? Bufs<T>::r(c->lv[l0]) : nullptr;
     for (int q = 0; q < D.nlev; ++q) {
       Level& Lv = c->lv[l0 + q];
       const StencilParams<T>& st = Bufs<T>::st(Lv);
@@ -402,7 +414,7 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
       tl.ox = (int)(take(vb) / sizeof(T));
       tl.ot = (int)(take(vb) / sizeof(T));
       tl.ob = (int)(take(vb) / sizeof(T));
-      tl.orr = (int)(take(vb) / sizeof(T));
+      tl.orr = (q == 0 && r0_global) ? 0 : (int)(take(vb) / sizeof(T));
       tl.ok = c->kappa ? (int)(take(ipow(Lv.g.n, c->o.dim) * (long)sizeof(T)) / sizeof(T)) : 0;
       tl.kappa = Bufs<T>::kap(Lv);
       tl.wc = st.wc;
