@@ -62,6 +62,10 @@ typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
 #define MG_FLAG_NO_TAIL 2    /* cycle every level with grid-wide launches, also
                                 the small coarse levels that otherwise run
                                 inside one workgroup */
+#define MG_FLAG_NO_FUSE 4    /* FP64 solves: compute the stopping residual of
+                                each cycle in a launch of its own instead of
+                                in one pass with the next cycle's first
+                                pre-smoothing step (same results bitwise) */
 
 typedef struct {
   int dim;          /* 2 or 3 */

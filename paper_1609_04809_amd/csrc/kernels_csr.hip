@@ -280,6 +280,15 @@ void launch_csr_residual(const Geo&, const CsrOp<T>& A, const T* x, const T* b, 
 }
 
 template <typename T>
+void launch_csr_head(const Geo&, const CsrOp<T>& A, int kind, const T* x, const T* b, T* xout,
+                     T omega, double* partials, hipStream_t s) {
+  if (kind == SM_JACOBI)
+    launch_rows<T, 4>(A, 0, A.rows, x, b, xout, omega, partials, s);
+  else
+    launch_rows<T, 3>(A, 0, A.rows, x, b, xout, omega, partials, s);
+}
+
+template <typename T>
 void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s) {
   if (kind == SM_JACOBI) {
@@ -296,7 +305,9 @@ void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, co
   template void launch_csr_residual<T>(const Geo&, const CsrOp<T>&, const T*, const T*, T*,  \
                                        double*, hipStream_t);                                \
   template void launch_csr_smooth<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*,   \
-                                     T*, T, hipStream_t);
+                                     T*, T, hipStream_t);                                    \
+  template void launch_csr_head<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*, T*, \
+                                   T, double*, hipStream_t);
 INST(float)
 INST(double)
 #undef INST

@@ -12,6 +12,7 @@
 // consecutive x and 4 consecutive y of one z plane of interior nodes, so one
 // wavefront (64 lanes) reads 64 consecutive values of a grid row.
 #include <cstdlib>
+#include <type_traits>
 
 #include "mg_internal.h"
 
@@ -335,10 +336,14 @@ __device__ __forceinline__ T prolong_node(const DGeo& gc, const T* __restrict__ 
 // loads.  In a red-black half-sweep exactly one of the two unknowns has the
 // colour being updated, and the whole wavefront agrees on which one.
 //
-// MODE: SM_JACOBI, SM_RB0, SM_RB1 (smoothing; ZERO: x = 0, not read) or
-// SW_RESID (r = b - A x with per-block partial sums of r^2 when NORM).
+// MODE: SM_JACOBI, SM_RB0, SM_RB1 (smoothing; ZERO: x = 0, not read),
+// SW_RESID (r = b - A x with per-block partial sums of r^2 when NORM) or
+// SW_HEAD_RB0 / SW_HEAD_JAC: the partial sums of (b - A x)^2 together with
+// the red-black colour-0 (Jacobi) smoothing step of x, written to out.
 // ---------------------------------------------------------------------------
 constexpr int SW_RESID = 3;
+constexpr int SW_HEAD_RB0 = 4;
+constexpr int SW_HEAD_JAC = 5;
 constexpr int SW_TX = 128;  // unknowns per tile in x (2 per thread)
 constexpr int SW_TY = 4;    // unknowns per tile in y (1 per thread row)
 constexpr int SW_LX = SW_TX + 2, SW_LY = SW_TY + 2;
@@ -361,6 +366,7 @@ template <typename T, int KIND, int MODE, bool ZERO, bool NORM>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
                                                 int nzc, Batch B) {
   using V2 = typename Vec2<T>::type;
+  constexpr bool HEAD = MODE == SW_HEAD_RB0 || MODE == SW_HEAD_JAC;
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
@@ -483,7 +489,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const bool ok = (u == 0 ? ok0 : ok1) && k <= k1;
-      const bool need = MODE == SW_RESID || MODE == SM_JACOBI ||
+      const bool need = MODE == SW_RESID || MODE == SM_JACOBI || HEAD ||
                         (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
       bpf[u] = (ok && need) ? b[p + u] : T(0);
     }
@@ -510,7 +516,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const bool ok = u == 0 ? ok0 : ok1;
-      const bool upd = MODE == SW_RESID || MODE == SM_JACOBI ||
+      const bool upd = MODE == SW_RESID || MODE == SM_JACOBI || HEAD ||
                        (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
       if (!ok) continue;
       if (!upd) {
@@ -549,6 +555,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         const T res = bcur[u] - ax;
         out[p + u] = res;
         sq += (double)res * (double)res;
+      } else if (HEAD) {
+        const T res = bcur[u] - ax;
+        sq += (double)res * (double)res;
+        const T q = res / dg;
+        const bool c0 = ((i + u + j + k) & 1) == 0;
+        out[p + u] = MODE == SW_HEAD_JAC ? v[1][1][1] + omega * q : (c0 ? v[1][1][1] + q : v[1][1][1]);
       } else {
         const T q = (bcur[u] - ax) / dg;
         out[p + u] = MODE == SM_JACOBI ? v[1][1][1] + omega * q : v[1][1][1] + q;
@@ -570,7 +582,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         for (int c = 0; c < 3; ++c) wk[0][r][c] = wk[1][r][c];
     }
   }
-  if (MODE == SW_RESID && NORM) {
+  if ((MODE == SW_RESID && NORM) || HEAD) {
     const double t = block_sum(sq);
     if (tid == 0)
       I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * zc)] = t;
@@ -631,6 +643,27 @@ __global__ __launch_bounds__(256) void k_smooth(Geo g, StencilParams<T> op, T om
   ((T*)I.c)[p] = smooth_node<T, DIM, KIND>(op, (const T*)I.kappa, dgeo(g), KS,
                                            ZERO ? nullptr : (const T*)I.a, (const T*)I.b,
                                            omega, p, i, j, k);
+}
+
+// Partial sums of (b - A x)^2 and, written to c, the first smoothing step
+// of x: KS = SM_JACOBI updates every unknown, SM_RB0 those of colour 0.
+template <typename T, int DIM, int KIND, int KS>
+__global__ __launch_bounds__(256) void k_head(Geo g, StencilParams<T> op, T omega, Batch B) {
+  NODE_INDEX(DIM, g)
+  double sq = 0.0;
+  if (inside) {
+    const T* __restrict__ x = (const T*)I.a;
+    T ax, dg;
+    Apply<T, DIM, KIND>::at(op, (const T*)I.kappa, dgeo(g), x, p, i, j, k, ax, dg);
+    const T res = ((const T*)I.b)[p] - ax;
+    sq = (double)res * (double)res;
+    const T q = res / dg;
+    const bool upd = KS == SM_JACOBI || ((i + j + k) & 1) == 0;
+    ((T*)I.c)[p] = upd ? (KS == SM_JACOBI ? x[p] + omega * q : x[p] + q) : x[p];
+  }
+  const double t = block_sum(sq);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * plane)] = t;
 }
 
 template <typename T, int DIM>
@@ -842,9 +875,20 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
         const int ks = smoother == 0 ? SM_JACOBI : ((h == 0) == pre ? SM_RB0 : SM_RB1);
         const T* xin = *zero ? nullptr : X(l);
         T* xout = S(l);
-        for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
-          xout[p] = smooth_node<T, DIM, KIND>(op, kap, g, ks, xin, b, omega, p, i, j, k);
-        });
+        // the step kind is a constant in each instance, as in the grid
+        // kernels, so both contract the update the same way
+        auto sweep = [&](auto kind) {
+          for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
+            xout[p] = smooth_node<T, DIM, KIND>(op, kap, g, decltype(kind)::value, xin, b, omega,
+                                                p, i, j, k);
+          });
+        };
+        if (ks == SM_JACOBI)
+          sweep(std::integral_constant<int, SM_JACOBI>{});
+        else if (ks == SM_RB0)
+          sweep(std::integral_constant<int, SM_RB0>{});
+        else
+          sweep(std::integral_constant<int, SM_RB1>{});
         __syncthreads();
         par ^= 1 << l;
         *zero = false;
@@ -1081,6 +1125,32 @@ void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero
 }
 
 template <typename T>
+void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
+                 hipStream_t s) {
+  const bool jac = kind == SM_JACOBI;
+  if (use_sweep3(g)) {
+    if (op.kind == OP_KAPPA) {
+      if (jac) launch_sweep3<T, OP_KAPPA, SW_HEAD_JAC, false, true>(g, op, omega, B, s);
+      else launch_sweep3<T, OP_KAPPA, SW_HEAD_RB0, false, true>(g, op, omega, B, s);
+    } else {
+      if (jac) launch_sweep3<T, OP_CONST, SW_HEAD_JAC, false, true>(g, op, omega, B, s);
+      else launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true>(g, op, omega, B, s);
+    }
+    return;
+  }
+  const dim3 gr = node_grid(g, B.count), bl(BX, BY);
+#define L_HEAD(D, K)                                                                        \
+  do {                                                                                      \
+    if (jac)                                                                                \
+      hipLaunchKernelGGL((k_head<T, D, K, SM_JACOBI>), gr, bl, 0, s, g, op, omega, B);      \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_head<T, D, K, SM_RB0>), gr, bl, 0, s, g, op, omega, B);         \
+  } while (0)
+  DISPATCH_DIM_KIND(g.dim, op.kind, L_HEAD);
+#undef L_HEAD
+}
+
+template <typename T>
 void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(gc, B.count), bl(BX, BY);
   if (gf.dim == 2)
@@ -1177,6 +1247,8 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
                                    hipStream_t);                                            \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
                                  const Batch&, hipStream_t);                                \
+  template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \
+                               hipStream_t);                                                \
   template void launch_restrict<T>(const Geo&, const Geo&, const Batch&, hipStream_t);      \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const Batch&, hipStream_t);   \
   template void launch_coarse_solve<T>(const Geo&, int, const Batch&, hipStream_t);         \

@@ -52,6 +52,8 @@ enum OpCode {
   OC_COPY,
   OC_CSR_SMOOTH,
   OC_CSR_RESID,
+  OC_HEAD,      // residual partial sums + first smoothing step (sub: kind)
+  OC_CSR_HEAD,
 };
 
 // One kernel launch of a cycle for one request.  Ops with equal keys (all
@@ -98,8 +100,10 @@ struct mg_ctx {
   int tail_lds[2] = {0, 0};     // dynamic LDS bytes of the tail launch (FP64, FP32)
   double* pinned = nullptr;     // host pinned scalars
   hipStream_t cap = nullptr;    // private stream for graph capture
-  hipGraphExec_t gexec = nullptr;
-  const void* gkey[3] = {nullptr, nullptr, nullptr};
+  // one cached graph per iteration kind (plain, first fused, steady fused),
+  // valid for the (u, b) it was captured with
+  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
+  const void* gkey[3][2] = {};
   // profiling
   int prof_kernel = -1;
   bool prof_on = false;

@@ -175,6 +175,12 @@ void launch_prolong_add(const Geo& gf, const Geo& gc, const Batch& B, hipStream_
 // Coarsest solve, one block per request:  b = b_c, c = x_c, L (m x m).
 template <typename T>
 void launch_coarse_solve(const Geo& gc, int m, const Batch& B, hipStream_t s);
+// In one pass over x: per-block partial sums of (b - A x)^2 (as the residual
+// launch writes them) and the first smoothing step of the next cycle, kind
+// SM_JACOBI or SM_RB0:  a = x, b = b, c = x_out, kappa, partials.
+template <typename T>
+void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
+                 hipStream_t s);
 // Per-block partial sums of v^2:  a = v, partials.
 template <typename T>
 void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s);
@@ -204,6 +210,11 @@ void launch_csr_residual(const Geo& g, const CsrOp<T>& A, const T* x, const T* b
                          double* partials, hipStream_t s);
 long csr_residual_blocks(int rows);      // partial sums of one residual launch
 long csr_residual_blocks_max(int rows);  // upper bound over launch variants
+// Residual partial sums of x (as launch_csr_residual) and the smoothing
+// step SM_JACOBI / SM_RB0 from x into xout, over all rows in one pass.
+template <typename T>
+void launch_csr_head(const Geo& g, const CsrOp<T>& A, int kind, const T* x, const T* b, T* xout,
+                     T omega, double* partials, hipStream_t s);
 template <typename T>
 void launch_csr_smooth(const Geo& g, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s);

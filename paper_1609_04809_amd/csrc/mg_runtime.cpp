@@ -94,6 +94,7 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
+  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE)) { why = "unknown flags"; return false; }
   const long nc = o->n >> (o->levels - 1);
   const long m = ipow(nc - 1, o->dim);
   if (m > kCoarseMaxUnknowns) {
@@ -483,6 +484,21 @@ void emit_residual(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T
   sink(o);
 }
 
+// Partial sums of ||b - A x||^2 on level l and, into xout, the first
+// pre-smoothing step of the next cycle from x.
+template <typename T>
+void emit_head(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* xout,
+               double* partials) {
+  OpRec o = base_op<T>(c, c->csr ? OC_CSR_HEAD : OC_HEAD, l);
+  o.sub = c->o.smoother == MG_SMOOTH_JACOBI ? SM_JACOBI : SM_RB0;
+  o.item.a = x;
+  o.item.b = b;
+  o.item.c = xout;
+  o.item.partials = partials;
+  if (c->csr) o.csr = Bufs<T>::csr(c->lv[l]);
+  sink(o);
+}
+
 long residual_partials(mg_ctx* c, int l) {
   return c->csr ? csr_residual_blocks(c->lv[l].rows) : grid_blocks(c->lv[l].g);
 }
@@ -504,24 +520,28 @@ void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
 }
 
 // Smoothing on level l from *cur (or from 0 if *zero), ping-ponging between
-// *cur and *spare; on return *cur holds the smoothed iterate.
+// *cur and *spare; on return *cur holds the smoothed iterate.  With
+// `skip`, the first step is not emitted: it has already been done, from
+// *spare into *cur.
 template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
-                  const T* b) {
+                  const T* b, bool skip = false) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
+  auto step = [&](int kind) {
+    if (skip) {
+      skip = false;
+      return;
+    }
+    emit_smooth<T>(c, sink, l, kind, *zero ? nullptr : *cur, b, *spare);
+    std::swap(*cur, *spare);
+    *zero = false;
+  };
   for (int it = 0; it < nu; ++it) {
     if (c->o.smoother == MG_SMOOTH_JACOBI) {
-      emit_smooth<T>(c, sink, l, SM_JACOBI, *zero ? nullptr : *cur, b, *spare);
-      std::swap(*cur, *spare);
-      *zero = false;
+      step(SM_JACOBI);
     } else {
-      const int first = pre ? SM_RB0 : SM_RB1;
-      const int second = pre ? SM_RB1 : SM_RB0;
-      for (int kind : {first, second}) {
-        emit_smooth<T>(c, sink, l, kind, *zero ? nullptr : *cur, b, *spare);
-        std::swap(*cur, *spare);
-        *zero = false;
-      }
+      step(pre ? SM_RB0 : SM_RB1);
+      step(pre ? SM_RB1 : SM_RB0);
     }
   }
 }
@@ -529,9 +549,11 @@ void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spa
 // One V-cycle (Algorithm 1) for A_0 x = b starting from x0 (or from 0 when
 // x0_zero); the result is written back to x0.  Levels >= 1 and the spare
 // level-0 buffer are internal.  Levels from c->tail0 on run in one
-// workgroup per request.
+// workgroup per request.  head_done: the first level-0 pre-smoothing step
+// has already been applied to x0, its result is in spare0.
 template <typename T>
-void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero) {
+void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero,
+                 bool head_done = false) {
   const int L = c->L;
   std::vector<T*> cur(L), spare(L);
   std::vector<const T*> bb(L);
@@ -544,9 +566,10 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     bb[l] = Bufs<T>::b(c->lv[l]);
   }
   const int lt = c->tail0 >= 0 ? c->tail0 : L - 1;  // first level not cycled level by level
+  if (head_done) std::swap(cur[0], spare[0]);
   for (int l = 0; l < lt; ++l) {
     bool zero = (l > 0) || x0_zero;
-    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &zero, bb[l]);
+    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &zero, bb[l], l == 0 && head_done);
     if (zero) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, l);
@@ -587,8 +610,30 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
   }
 }
 
-void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+// Whether FP64 solves fuse the stopping residual of cycle k with the first
+// pre-smoothing step of cycle k+1 (both read A and u_k once): needs a
+// level-0 pre-smoothing step outside the tail.
+bool head_fusion(const mg_ctx* c) {
+  return !c->ir && c->o.nu_pre >= 1 && c->L >= 2 && c->tail0 != 0 &&
+         !(c->o.flags & MG_FLAG_NO_FUSE);
+}
+
+// Iteration kinds: IT_PLAIN = V-cycle, then residual norm;  IT_FUSED_FIRST =
+// V-cycle, then the fused residual norm + next head (into the level-0
+// spare);  IT_FUSED = the V-cycle without its head (taken from the spare),
+// then the fused residual norm + next head.  In every kind u holds the new
+// iterate and scal[0] its squared residual norm at the end.
+enum IterKind { IT_PLAIN = 0, IT_FUSED_FIRST = 1, IT_FUSED = 2 };
+
+void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
+                    int kind = IT_PLAIN) {
   Level& L0 = c->lv[0];
+  if (kind != IT_PLAIN) {
+    emit_vcycle<double>(c, sink, u, L0.t64, b, false, kind == IT_FUSED);
+    emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
+    emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+    return;
+  }
   if (c->ir) {
     // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c
     OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
@@ -632,7 +677,9 @@ int prof_class(int code) {
     case OC_SMOOTH:
     case OC_CSR_SMOOTH: return PK_SMOOTH;
     case OC_RESID:
-    case OC_CSR_RESID: return PK_RESID;
+    case OC_CSR_RESID:
+    case OC_HEAD:
+    case OC_CSR_HEAD: return PK_RESID;
     case OC_RESTRICT: return PK_RESTRICT;
     case OC_PROLONG: return PK_PROLONG;
     default: return -1;
@@ -681,27 +728,31 @@ Sink launch_sink(mg_ctx* c, hipStream_t s) {
   };
 }
 
-void drop_graph(mg_ctx* c) {
-  if (c->gexec) hipGraphExecDestroy(c->gexec);
-  c->gexec = nullptr;
-  c->gkey[0] = c->gkey[1] = c->gkey[2] = nullptr;
+void drop_graph(mg_ctx* c, int kind) {
+  if (c->gexec[kind]) hipGraphExecDestroy(c->gexec[kind]);
+  c->gexec[kind] = nullptr;
+  c->gkey[kind][0] = c->gkey[kind][1] = nullptr;
 }
 
-// Run one iteration: replay the cached graph (captured on first use for
-// these buffers) or launch eagerly.
-mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s) {
+void drop_graphs(mg_ctx* c) {
+  for (int k = 0; k < 3; ++k) drop_graph(c, k);
+}
+
+// Run one iteration of the given kind: replay the cached graph (captured on
+// first use for these buffers) or launch eagerly.
+mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s, int kind) {
   const bool eager = (c->o.flags & MG_FLAG_NO_GRAPH) || c->prof_on;
   if (eager) {
-    emit_iteration(c, launch_sink(c, s), u, b);
+    emit_iteration(c, launch_sink(c, s), u, b, kind);
     HIP_TRY(hipGetLastError());
     return MG_OK;
   }
-  const void* key[3] = {u, b, (const void*)(long)c->ir};
-  if (!c->gexec || memcmp(key, c->gkey, sizeof key) != 0) {
-    drop_graph(c);
+  const void* key[2] = {u, b};
+  if (!c->gexec[kind] || memcmp(key, c->gkey[kind], sizeof key) != 0) {
+    drop_graph(c, kind);
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    emit_iteration(c, launch_sink(c, c->cap), u, b);
+    emit_iteration(c, launch_sink(c, c->cap), u, b, kind);
     hipError_t le = hipGetLastError();
     hipError_t ee = hipStreamEndCapture(c->cap, &graph);
     if (le != hipSuccess || ee != hipSuccess) {
@@ -709,15 +760,15 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s) {
       return fail(MG_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
                   hipGetErrorString(ee));
     }
-    hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+    hipError_t ie = hipGraphInstantiate(&c->gexec[kind], graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (ie != hipSuccess) {
-      c->gexec = nullptr;
+      c->gexec[kind] = nullptr;
       return fail(MG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
     }
-    memcpy(c->gkey, key, sizeof key);
+    memcpy(c->gkey[kind], key, sizeof key);
   }
-  HIP_TRY(hipGraphLaunch(c->gexec, s));
+  HIP_TRY(hipGraphLaunch(c->gexec[kind], s));
   return MG_OK;
 }
 
@@ -760,6 +811,11 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
       launch_csr_residual<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (const T*)it.b,
                              (T*)it.c, it.partials, s);
       break;
+    case OC_HEAD: launch_head<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
+    case OC_CSR_HEAD:
+      launch_csr_head<T>(o.g, *(const CsrOp<T>*)o.csr, o.sub, (const T*)it.a, (const T*)it.b,
+                         (T*)it.c, (T)o.omega, it.partials, s);
+      break;
     default: break;
   }
 }
@@ -773,7 +829,7 @@ namespace mg {
 
 bool batchable(const OpRec& a) {
   return a.code != OC_FILL && a.code != OC_COPY && a.code != OC_CSR_SMOOTH &&
-         a.code != OC_CSR_RESID;
+         a.code != OC_CSR_RESID && a.code != OC_CSR_HEAD;
 }
 
 bool same_key(const OpRec& a, const OpRec& b) {
@@ -918,7 +974,7 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
 void mg_destroy(mg_ctx* c) {
   if (!c) return;
   if (c->cap) hipStreamSynchronize(c->cap);
-  drop_graph(c);
+  drop_graphs(c);
   for (auto& pr : c->ev_pending) {
     c->ev_pool.push_back(pr.first);
     c->ev_pool.push_back(pr.second);
@@ -957,8 +1013,9 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   if (!std::isfinite(nb2)) return fail(MG_E_NONFINITE, "b holds NaN or Inf");
   if (nb2 == 0.0) return MG_OK;
   const double nb = std::sqrt(nb2);
+  const bool fuse = head_fusion(c);
   for (int k = 1; k <= c->o.max_iter; ++k) {
-    st = run_iteration(c, u, b, s);
+    st = run_iteration(c, u, b, s, !fuse ? IT_PLAIN : (k == 1 ? IT_FUSED_FIRST : IT_FUSED));
     if (st != MG_OK) return st;
     double n2 = 0.0;
     st = read_scalar(c, 0, &n2, s);

@@ -63,7 +63,8 @@ def test_options_validation_and_footprint():
     for bad in (dict(dim=4, n=8, levels=2), dict(dim=3, n=12, levels=4),
                 dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
                 dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
-                dict(dim=3, n=16, levels=3, max_iter=0)):
+                dict(dim=3, n=16, levels=3, max_iter=0),
+                dict(dim=3, n=16, levels=3, flags=8)):
         o = mg.make_options(**bad)
         assert L.mg_footprint_bytes(ctypes.byref(o)) == 0, bad
         assert L.mg_last_error().decode()
