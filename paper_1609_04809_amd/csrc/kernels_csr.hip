@@ -1,10 +1,10 @@
 // CSR kernels of the Q1 multigrid V-cycle for gfx950: operator build,
 // residual and smoothing sweeps on an assembled matrix.
 //
-// Row kernels stream the nonzeros of a block's rows: a block of 256 threads
+// Row kernels stream the nonzeros of a block's rows: a block of NTH threads
 // owns ROWS consecutive rows, reads their values and column indices
 // contiguously (coalesced), multiplies by the gathered x and stages the
-// products in LDS; 256 / ROWS threads then sum each row in a fixed order.
+// products in LDS; NTH / ROWS threads then sum each row in a fixed order.
 #include <cstdlib>
 
 #include "mg_internal.h"
@@ -13,20 +13,23 @@ namespace mg {
 
 namespace {
 
-constexpr int CSR_THREADS = 256;
 constexpr int CSR_MAX_ROW = 27;           // 3^dim entries at most
-constexpr int CSR_MIN_ROWS = 32;          // smallest rows-per-block variant
+constexpr int CSR_MIN_ROWS = 16;          // smallest rows-per-block variant
 
 // Launch variants of the row kernel: rows per block and whether the matrix
 // is read with non-temporal loads (it is streamed once per sweep, so it
 // need not stay in the caches that hold x).
 struct CsrVariant {
   int rows;
+  int threads;
   bool nt;
   bool remap;
 };
-constexpr CsrVariant kCsrVariants[] = {{64, false, true}, {64, false, false}, {32, false, true},
-                                       {128, false, true}, {64, true, true}};
+constexpr CsrVariant kCsrVariants[] = {
+    {64, 256, false, false}, {64, 256, false, true}, {32, 256, false, true},
+    {128, 256, false, true}, {64, 256, true, true},  {16, 64, false, true},
+    {32, 128, false, true}, {16, 64, true, true},   {32, 128, true, true},
+    {128, 512, false, true}};
 constexpr int kNumCsrVariants = sizeof(kCsrVariants) / sizeof(kCsrVariants[0]);
 
 int csr_variant() {
@@ -47,14 +50,22 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Sum of v over the NTH threads of a block; result valid in thread 0.
+// Wave-level butterfly, then the wave sums in a fixed order.
+template <int NTH>
 __device__ __forceinline__ double block_sum_1d(double v) {
-  __shared__ double ws[CSR_THREADS / 64];
+  __shared__ double ws[NTH / 64];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if (NTH == 64) return v;
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
   __syncthreads();
   double t = 0.0;
-  if (threadIdx.x == 0) t = ((ws[0] + ws[1]) + ws[2]) + ws[3];
+  if (threadIdx.x == 0) {
+    t = ws[0];
+#pragma unroll
+    for (int w = 1; w < NTH / 64; ++w) t += ws[w];
+  }
   return t;
 }
 
@@ -73,71 +84,70 @@ __device__ __forceinline__ V ld_stream(const V* p) {
 // MODE 4: over all rows, the residual partial sums and the Jacobi update.
 // ZERO: x = 0 (x is not read).
 // Phase 1 issues all column and value loads of a thread before any gather,
-// so that about 2 * PER loads per thread are in flight.
-template <typename T, int MODE, bool ZERO, int ROWS, bool NT, bool REMAP>
-__global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end,
+// so that about 2 * PER loads per thread are in flight.  The loads carry no
+// branches: a thread past the block's last nonzero re-reads that nonzero
+// and writes its product to a slot beyond the rows (the LDS array has
+// PER * NTH slots), so all loads of a phase are issued before the
+// first wait.
+template <typename T, int MODE, bool ZERO, int ROWS, bool NT, bool REMAP, int NTH>
+__global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end,
                                                           const T* __restrict__ xin,
                                                           const T* __restrict__ b,
                                                           T* __restrict__ out, T omega,
                                                           double* __restrict__ partials) {
   constexpr int MAXNNZ = ROWS * CSR_MAX_ROW;
-  constexpr int PER = (MAXNNZ + CSR_THREADS - 1) / CSR_THREADS;
-  constexpr int TPR = CSR_THREADS / ROWS;  // threads summing one row
-  __shared__ int rp[ROWS + 1];
-  __shared__ T prod[MAXNNZ];
+  constexpr int PER = (MAXNNZ + NTH - 1) / NTH;
+  constexpr int TPR = NTH / ROWS;  // threads summing one row
+  __shared__ T prod[PER * NTH];
   const int tid = threadIdx.x;
   const int blk = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int r0 = r_begin + blk * ROWS;
   const int nr = min(ROWS, r_end - r0);
-  // The owner thread of each row (lane 0 of its group) fetches the row's
-  // node, right-hand side, current value, diagonal and (red-black) the
-  // other-colour neighbours to copy, early: these loads are in flight
-  // together with the row pointers and the matrix stream below.
+  // The block's nonzero range comes from two uniform (scalar) loads, so the
+  // matrix stream starts after one round trip.  Every thread loads at
+  // clamped indices (no branch around a load), so the loads of a phase are
+  // all in flight before the first wait: its row's bounds and node, then,
+  // with the matrix, the row's operands -- right-hand side, current value,
+  // diagonal and (red-black) the other-colour neighbours to copy (all TPR
+  // threads of a row read the same addresses; the row's owner, lane 0 of
+  // its group, uses them).
   const int lr = tid / TPR, lane = tid % TPR;
   const bool owner = lane == 0 && lr < nr;
-  int node = 0;
-  if (owner) node = A.rowmap[r0 + lr];
-  if (tid <= nr) rp[tid] = A.rowptr[r0 + tid];
-  __syncthreads();
-  const int base = rp[0];
-  T bv = T(0), x0 = T(0), dg = T(1), xr = T(0), xl = T(0);
-  bool copy_r = false, copy_l = false;
-  if (owner) {
-    bv = b[node];
-    if (!ZERO && MODE != 0) x0 = xin[node];
-    if (MODE != 0) dg = A.val[rp[lr]];
-    if (MODE == 2) {
-      const int ix = (int)(node % A.sy);
-      copy_r = ix + 1 <= A.n - 1;
-      copy_l = ix == 2;
-      if (!ZERO && copy_r) xr = xin[node + 1];
-      if (!ZERO && copy_l) xl = xin[node - 1];
-    }
+  const int lrc = min(lr, nr - 1);
+  const int base = A.rowptr[r0];
+  const int last = A.rowptr[r0 + nr] - base - 1;  // every row holds its diagonal
+  const int rb = A.rowptr[r0 + lrc] - base, re = A.rowptr[r0 + lrc + 1] - base;
+  const int node = A.rowmap[r0 + lrc];
+  const T bv = b[node];
+  T x0 = T(0), dg = T(1), xr = T(0), xl = T(0);
+  if (!ZERO && MODE != 0) x0 = xin[node];
+  if (MODE != 0) dg = A.val[base + rb];
+  const int ix = node % (int)A.sy;
+  const bool copy_r = MODE == 2 && ix + 1 <= A.n - 1;
+  const bool copy_l = MODE == 2 && ix == 2;
+  if (MODE == 2 && !ZERO) {
+    xr = xin[node + 1];  // interior node: both neighbours lie in the grid
+    xl = xin[node - 1];
   }
   if (!ZERO) {
-    const int cnt = rp[nr] - base;
     int cl[PER];
     T vl[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * CSR_THREADS;
-      if (e < cnt) {
-        cl[q] = ld_stream<NT>(A.col + base + e);
-        vl[q] = ld_stream<NT>(A.val + base + e);
-      }
+      const int e = min(tid + q * NTH, last);
+      cl[q] = ld_stream<NT>(A.col + base + e);
+      vl[q] = ld_stream<NT>(A.val + base + e);
     }
+    T xg[PER];
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = tid + q * CSR_THREADS;
-      if (e < cnt) prod[e] = vl[q] * xin[cl[q]];
-    }
+    for (int q = 0; q < PER; ++q) xg[q] = xin[cl[q]];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) prod[tid + q * NTH] = vl[q] * xg[q];
   }
   __syncthreads();
   T s = T(0);
-  if (!ZERO && lr < nr) {
-    const int e1 = rp[lr + 1] - base;
-    for (int e = rp[lr] - base + lane; e < e1; e += TPR) s += prod[e];
-  }
+  if (!ZERO && lr < nr)
+    for (int e = rb + lane; e < re; e += TPR) s += prod[e];
 #pragma unroll
   for (int off = 1; off < TPR; off <<= 1) s += __shfl_xor(s, off);
   double sq = 0.0;
@@ -167,7 +177,7 @@ __global__ __launch_bounds__(CSR_THREADS) void k_csr_rows(CsrOp<T> A, int r_begi
     }
   }
   if ((MODE == 0 || MODE >= 3) && partials != nullptr) {
-    const double t = block_sum_1d(sq);
+    const double t = block_sum_1d<NTH>(sq);
     if (tid == 0) partials[blk] = t;
   }
 }
@@ -230,28 +240,33 @@ __global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_el
 
 inline int cdiv_i(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <typename T, int MODE, int ROWS, bool NT, bool REMAP>
+template <typename T, int MODE, int ROWS, bool NT, bool REMAP, int NTH = 256>
 void launch_rows_v(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
                    double* partials, hipStream_t s) {
   const int nb = cdiv_i(re - rb, ROWS);
   if (nb == 0) return;
   if (xin == nullptr)
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, true, ROWS, NT, REMAP>), dim3(nb), dim3(CSR_THREADS),
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, true, ROWS, NT, REMAP, NTH>), dim3(nb), dim3(NTH),
                        0, s, A, rb, re, xin, b, out, omega, partials);
   else
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, false, ROWS, NT, REMAP>), dim3(nb),
-                       dim3(CSR_THREADS), 0, s, A, rb, re, xin, b, out, omega, partials);
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, false, ROWS, NT, REMAP, NTH>), dim3(nb), dim3(NTH),
+                       0, s, A, rb, re, xin, b, out, omega, partials);
 }
 
 template <typename T, int MODE>
 void launch_rows(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
                  double* partials, hipStream_t s) {
   switch (csr_variant()) {
-    case 1: launch_rows_v<T, MODE, 64, false, false>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 1: launch_rows_v<T, MODE, 64, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
     case 2: launch_rows_v<T, MODE, 32, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
     case 3: launch_rows_v<T, MODE, 128, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
     case 4: launch_rows_v<T, MODE, 64, true, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    default: launch_rows_v<T, MODE, 64, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 5: launch_rows_v<T, MODE, 16, false, true, 64>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 6: launch_rows_v<T, MODE, 32, false, true, 128>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 7: launch_rows_v<T, MODE, 16, true, true, 64>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 8: launch_rows_v<T, MODE, 32, true, true, 128>(A, rb, re, xin, b, out, omega, partials, s); break;
+    case 9: launch_rows_v<T, MODE, 128, false, true, 512>(A, rb, re, xin, b, out, omega, partials, s); break;
+    default: launch_rows_v<T, MODE, 64, false, false>(A, rb, re, xin, b, out, omega, partials, s); break;
   }
 }
 
