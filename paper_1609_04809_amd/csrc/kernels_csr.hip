@@ -41,15 +41,6 @@ int csr_variant() {
   return v;
 }
 
-// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2).
-// Map dispatch order to a logical order in which every XCD owns one
-// contiguous range of blocks, so neighbouring rows share an L2.
-__device__ __forceinline__ int xcd_remap(int bid, int nb) {
-  const int q = nb >> 3, r = nb & 7;
-  const int xcd = bid & 7, idx = bid >> 3;
-  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
-}
-
 // Sum of v over the NTH threads of a block; result valid in thread 0.
 // Wave-level butterfly, then the wave sums in a fixed order.
 template <int NTH>

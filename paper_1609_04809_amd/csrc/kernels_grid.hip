@@ -364,20 +364,31 @@ inline int sweep3_kz(int m) {
 
 template <typename T, int KIND, int MODE, bool ZERO, bool NORM>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
-                                                int nzc, Batch B) {
+                                                int nzc, int remap, Batch B) {
   using V2 = typename Vec2<T>::type;
   constexpr bool HEAD = MODE == SW_HEAD_RB0 || MODE == SW_HEAD_JAC;
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
   const long sy = g.sy, sz = g.sz;
-  const int item = blockIdx.z / nzc, zc = blockIdx.z % nzc;
+  // tile (bx, by, bz): with `remap`, tiles that are neighbours in y and z
+  // run on one XCD, so the halo rows they share are read once into its L2
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if (remap) {
+    const int gxy = gridDim.x * gridDim.y;
+    const int nb = gxy * gridDim.z;
+    const int L = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+    bx = L % gridDim.x;
+    by = (L / gridDim.x) % gridDim.y;
+    bz = L / gxy;
+  }
+  const int item = bz / nzc, zc = bz % nzc;
   const Item& I = B.it[item];
   const T* __restrict__ x = (const T*)I.a;
   const T* __restrict__ b = (const T*)I.b;
   T* __restrict__ out = (T*)I.c;
   const T* __restrict__ kap = (const T*)I.kappa;
-  const int i0 = 1 + blockIdx.x * SW_TX, j0 = 1 + blockIdx.y * SW_TY, k0 = 1 + zc * kz;
+  const int i0 = 1 + bx * SW_TX, j0 = 1 + by * SW_TY, k0 = 1 + zc * kz;
   const int k1 = min(k0 + kz - 1, m);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
   const int i = i0 + 2 * tx, j = j0 + ty;
@@ -392,19 +403,24 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   constexpr int NX = (SW_LX * SW_LY + 255) / 256;
   constexpr int NK = ((SW_TX + 1) * (SW_TY + 1) + 255) / 256;
   long xoff[NX];
-  bool xin_ok[NX];
   T xpf[NX];
 #pragma unroll
   for (int q = 0; q < NX; ++q) {
     const int e = tid + 256 * q;
     const int r = e / SW_LX, c = e - r * SW_LX;
     const int gi = i0 - 1 + c, gj = j0 - 1 + r;
-    xin_ok[q] = e < SW_LX * SW_LY && gi <= n && gj <= n;
-    xoff[q] = gi + gj * sy;
+    xoff[q] = min(gi, n) + min(gj, n) * sy;  // always inside the grid
   }
+  // Loads sit behind no branch or select, so the compiler keeps a plane's
+  // loads in flight across the computation of the previous plane instead of
+  // waiting at each one: a staged position off the grid (x or y beyond n,
+  // z beyond n, or past the tile) reads some node of the grid instead, and
+  // only the stencils of unknowns beyond m, which are never written, see
+  // such a value.  The same holds for b and the cell coefficients below.
   auto prefetch_x = [&](int z) {
+    const long zo = (long)min(z, n) * sz;
 #pragma unroll
-    for (int q = 0; q < NX; ++q) xpf[q] = (xin_ok[q] && z <= n) ? x[xoff[q] + z * sz] : T(0);
+    for (int q = 0; q < NX; ++q) xpf[q] = x[xoff[q] + zo];
   };
   auto commit_x = [&](int s) {
     T* dst = &sx[s][0][0];
@@ -415,7 +431,6 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     }
   };
   long koff[NK];
-  bool kin_ok[NK];
   T kpf[NK];
   if (KIND == OP_KAPPA) {
 #pragma unroll
@@ -423,14 +438,13 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       const int e = tid + 256 * q;
       const int r = e / (SW_TX + 1), c = e - r * (SW_TX + 1);
       const int cx = i0 - 1 + c, cy = j0 - 1 + r;
-      kin_ok[q] = e < (SW_TX + 1) * (SW_TY + 1) && cx <= n - 1 && cy <= n - 1;
-      koff[q] = cx + (long)n * cy;
+      koff[q] = min(cx, n - 1) + (long)n * min(cy, n - 1);
     }
   }
   auto prefetch_k = [&](int cz) {
+    const long zo = (long)n * n * min(cz, n - 1);
 #pragma unroll
-    for (int q = 0; q < NK; ++q)
-      kpf[q] = (kin_ok[q] && cz <= n - 1) ? kap[koff[q] + (long)n * n * cz] : T(0);
+    for (int q = 0; q < NK; ++q) kpf[q] = kap[koff[q] + zo];
   };
   auto commit_k = [&](int s) {
     T* dst = &sk[s][0][0];
@@ -484,15 +498,11 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   __syncthreads();
   // right-hand sides of the thread's two unknowns, one plane ahead
   T bpf[2] = {T(0), T(0)};
+  const long pb0 = min(i, n - 1) + min(j, n) * sy;  // clamped into the grid
   auto prefetch_b = [&](int k) {
-    const long p = i + j * sy + (long)k * sz;
+    const long p = pb0 + (long)min(k, n) * sz;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool ok = (u == 0 ? ok0 : ok1) && k <= k1;
-      const bool need = MODE == SW_RESID || MODE == SM_JACOBI || HEAD ||
-                        (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
-      bpf[u] = (ok && need) ? b[p + u] : T(0);
-    }
+    for (int u = 0; u < 2; ++u) bpf[u] = b[p + u];
   };
   prefetch_b(k0);
   double sq = 0.0;
@@ -585,7 +595,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   if ((MODE == SW_RESID && NORM) || HEAD) {
     const double t = block_sum(sq);
     if (tid == 0)
-      I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * zc)] = t;
+      I.partials[bx + (long)gridDim.x * (by + (long)gridDim.y * zc)] = t;
   }
 }
 
@@ -1008,13 +1018,22 @@ inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc) {
   return dim3(cdiv(m, SW_TX), cdiv(m, SW_TY), (unsigned)(*nzc * count));
 }
 
+// Whether sweep3 launches map tiles to XCDs (MG_SWEEP3_REMAP=0 turns it off).
+inline int sweep3_remap() {
+  static const int v = [] {
+    const char* e = getenv("MG_SWEEP3_REMAP");
+    return e ? (atoi(e) != 0) : 1;
+  }();
+  return v;
+}
+
 template <typename T, int K, int MODE, bool ZERO, bool NORM>
 void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batch& B,
                    hipStream_t s) {
   int kz, nzc;
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
   hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM>), gr, dim3(64, SW_TY), 0, s, g, op, omega,
-                     kz, nzc, B);
+                     kz, nzc, sweep3_remap(), B);
 }
 }  // namespace
 

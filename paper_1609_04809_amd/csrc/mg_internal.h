@@ -29,6 +29,16 @@ inline Geo make_geo(int dim, int n) {
   return g;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip (each
+// with its own L2) in linear order.  xcd_remap maps a dispatch index to a
+// logical one such that every XCD owns one contiguous range of logical
+// indices, so neighbouring tiles share an L2.  A bijection of [0, nb).
+__device__ __forceinline__ int xcd_remap(int bid, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = bid & 7, idx = bid >> 3;
+  return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
+}
+
 // Largest coarsest system (unknowns) solved by the one-block Cholesky kernel.
 constexpr int kCoarseMaxUnknowns = 4096;
 
