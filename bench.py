@@ -109,6 +109,30 @@ def stencil_halfsweep_bytes(n, s, kappa=False):
     return b
 
 
+def measured_traffic(name):
+    """HBM bytes per launch of the workload's finest-level half-sweep from the
+    committed FETCH_SIZE / WRITE_SIZE record (profiles/traffic.md), scaled by
+    the copy-kernel factors; None when the record is missing or the kernel
+    sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    try:
+        text = open(path).read()
+        rec = json.loads(re.search(r"```json\n(.*?)```", text, re.S).group(1)).get(name)
+    except (OSError, AttributeError, ValueError):
+        return None
+    if rec is None:
+        return None
+    for src, digest in rec["sources"].items():
+        try:
+            if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != digest:
+                return None
+        except OSError:
+            return None
+    return int(rec["bytes_per_launch"])
+
+
 def roofline_csr(S, w, bd):
     from paper_1609_04809_amd.mg import PROF_SMOOTH
     S.profile(PROF_SMOOTH, True)
@@ -120,7 +144,7 @@ def roofline_csr(S, w, bd):
     achieved = per_launch / avg_s / 1e9
     return {"bound": "hbm", "kernel": "k_csr_rows (red-black half-sweep, finest level)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(w.name),
             "launches": launches, "avg_us": round(avg_s * 1e6, 2),
             "bytes_per_launch": int(per_launch)}
 
@@ -164,9 +188,21 @@ def run_workload(name, steps, warmup, with_roofline=False):
         if with_roofline:
             roof = {"bound": "hbm", "kernel": "k_sweep3 (red-black half-sweep, finest level)",
                     "achieved": hs["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": hs["frac"], "traffic": None, "avg_us": hs["avg_us"],
+                    "frac": hs["frac"], "traffic": measured_traffic(w.name),
+                    "avg_us": hs["avg_us"],
                     "bytes_per_launch": hs["bytes_per_launch"]}
     S.close()
+    if w.precision == "fp32_ir":
+        # error of the FP32-inner / FP64-outer result against the FP64 V-cycle
+        # solution of the same system (the FP64 path is the one the tests hold
+        # to the oracle)
+        S64 = Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=w.smoother,
+                     nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision="fp64")
+        u64, k64, _, st = S64.solve(bd, w.tol)
+        S64.close()
+        res["err_vs_fp64"] = float(torch.linalg.vector_norm(u - u64) /
+                                   torch.linalg.vector_norm(u64))
+        res["fp64_cycles"] = k64
     return res, roof, (b, kappa, u, k)
 
 
