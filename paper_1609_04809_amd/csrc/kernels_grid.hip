@@ -79,59 +79,110 @@ struct Apply<T, 2, OP_CONST> {
   }
 };
 
-// 3D arithmetic on a 3x3x3 neighbourhood v[dz+1][dy+1][dx+1] of node p;
-// shared by every kernel that applies the 3D operator, so that all of them
-// round identically.
+// 3D arithmetic; shared by every kernel that applies the 3D operator (the
+// node kernels and the tail on a 3x3x3 neighbourhood v[dz+1][dy+1][dx+1],
+// the plane-marching sweep kernel on per-plane windows), so that all of
+// them round identically.  The operator is written as a sum of per-plane
+// parts so that a kernel marching in z can form each part when its plane is
+// at hand.
 //
 // kappa = 1: 8h/3 centre, -h/6 on the 12 edge neighbours, -h/12 on the
-// 8 corners, 0 on the 6 face neighbours.
+// 8 corners, 0 on the 6 face neighbours.  Parts of one plane, in a window
+// w[dy+1][c] whose node column is c = u+1:
+//   xe = x-edge pair of the centre row, ye = y-edge pair of the centre
+//   column, q = the four corners (for the node's own plane: its in-plane
+//   edge neighbours).
+template <typename T, typename W>
+__device__ __forceinline__ void plane_parts(const W& w, int u, T& xe, T& ye, T& q) {
+  xe = w[1][u] + w[1][u + 2];
+  ye = w[0][u + 1] + w[2][u + 1];
+  q = (w[0][u] + w[0][u + 2]) + (w[2][u] + w[2][u + 2]);
+}
+
+// A x at a node from the parts: xc its value, g the corners of its own
+// plane, (a0, b0, c0) / (a1, b1, c1) the parts of the planes below / above.
+template <typename T>
+__device__ __forceinline__ T stencil3_const_sum(const StencilParams<T>& op, T xc, T g, T a0, T a1,
+                                                T b0, T b1, T c0, T c1) {
+  const T e = (g + (a0 + a1)) + (b0 + b1);
+  const T c = c0 + c1;
+  return op.wc * xc + op.w1 * e + op.w2 * c;
+}
+
 template <typename T, typename V>
 __device__ __forceinline__ T stencil3_const(const StencilParams<T>& op, const V& v) {
-  const T e = ((v[1][0][0] + v[1][0][2]) + (v[1][2][0] + v[1][2][2])) +
-              ((v[0][1][0] + v[0][1][2]) + (v[2][1][0] + v[2][1][2])) +
-              ((v[0][0][1] + v[0][2][1]) + (v[2][0][1] + v[2][2][1]));
-  const T c = ((v[0][0][0] + v[0][0][2]) + (v[0][2][0] + v[0][2][2])) +
-              ((v[2][0][0] + v[2][0][2]) + (v[2][2][0] + v[2][2][2]));
-  return op.wc * v[1][1][1] + op.w1 * e + op.w2 * c;
+  T a0, b0, c0, a1, b1, c1, ea, eb, g;
+  plane_parts<T>(v[0], 0, a0, b0, c0);
+  plane_parts<T>(v[2], 0, a1, b1, c1);
+  plane_parts<T>(v[1], 0, ea, eb, g);
+  return stencil3_const_sum(op, v[1][1][1], g, a0, a1, b0, b1, c0, c1);
 }
 
-// kappa per cell: cell (a, b, c) of the eight around p (side sx = 2a-1,
-// sy = 2b-1, sz = 2c-1), coefficient kk[c][b][a], contributes
+// kappa per cell: cell (c, b, a) of the eight around p (sides sx = 2a-1,
+// sy = 2b-1, sz = 2c-1) with coefficient kappa_abc contributes
 //   kappa_abc * h/12 * (4 x_p - x_{p+sx+sy} - x_{p+sx+sz} - x_{p+sy+sz}
 //                       - x_{p+sx+sy+sz});
-// face neighbours have element weight 0.
-template <typename T, typename V, typename K>
-__device__ __forceinline__ T stencil3_kappa(const StencilParams<T>& op, const K& kk, const V& v,
-                                            T& dg) {
-  const T xp = v[1][1][1];
-  T acc = 0, ks = 0;
+// face neighbours have element weight 0.  Summed by planes:
+//   A x = h/12 (P - (Q + R)),  P = sum_cells kappa (4 x_p - x_{p+sx+sy}),
+//   Q = sum over the 4 cells below of kappa (x_{p+sx+sz} + x_{p+sy+sz} +
+//   x_{p+sx+sy+sz}), R = the same over the 4 cells above; diagonal
+//   h/12 * 4 * sum_cells kappa.  A cell layer window kw[b][c] holds the
+//   cells on the node's y sides b, x side c - u (node column u+1 of w).
+template <typename T, typename KW, typename W>
+__device__ __forceinline__ T kappa_side(const KW& kw, const W& w, int u) {
+  T q = 0;
 #pragma unroll
-  for (int c = 0; c < 2; ++c) {
+  for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const T kc = kk[c][b][a];
-        const int dx = 2 * a, dy = 2 * b, dz = 2 * c;  // neighbour index (0 or 2) per side
-        acc += kc * (T(4) * xp - v[1][dy][dx] - v[dz][1][dx] - v[dz][dy][1] - v[dz][dy][dx]);
-        ks += kc;
-      }
-    }
-  }
-  dg = op.s * T(4) * ks;
-  return op.s * acc;
+    for (int a = 0; a < 2; ++a)
+      q += kw[bb][u + a] * ((w[1][u + 2 * a] + w[2 * bb][u + 1]) + w[2 * bb][u + 2 * a]);
+  return q;
 }
 
-template <typename T, typename K>
-__device__ __forceinline__ T kappa_diag3(const StencilParams<T>& op, const K& kk) {
+template <typename T, typename KW, typename W>
+__device__ __forceinline__ void kappa_plane(const KW& kwlo, const KW& kwhi, const W& w, int u,
+                                            T& P, T& ks) {
+  const T xp = w[1][u + 1];
+  P = 0;
+  ks = 0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const T kc = c ? kwhi[bb][u + a] : kwlo[bb][u + a];
+        P += kc * (T(4) * xp - w[2 * bb][u + 2 * a]);
+        ks += kc;
+      }
+}
+
+template <typename T, typename KW>
+__device__ __forceinline__ T kappa_cell_sum(const KW& kwlo, const KW& kwhi, int u) {
   T ks = 0;
 #pragma unroll
   for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
-      for (int a = 0; a < 2; ++a) ks += kk[c][b][a];
-  return op.s * T(4) * ks;
+      for (int a = 0; a < 2; ++a) ks += c ? kwhi[bb][u + a] : kwlo[bb][u + a];
+  return ks;
+}
+
+template <typename T, typename V, typename K>
+__device__ __forceinline__ T stencil3_kappa(const StencilParams<T>& op, const K& kk, const V& v,
+                                            T& dg) {
+  T P, ks;
+  kappa_plane<T>(kk[0], kk[1], v[1], 0, P, ks);
+  const T Q = kappa_side<T>(kk[0], v[0], 0);
+  const T R = kappa_side<T>(kk[1], v[2], 0);
+  dg = op.s * T(4) * ks;
+  return op.s * (P - (Q + R));
+}
+
+template <typename T, typename K>
+__device__ __forceinline__ T kappa_diag3(const StencilParams<T>& op, const K& kk) {
+  return op.s * T(4) * kappa_cell_sum<T>(kk[0], kk[1], 0);
 }
 
 template <typename T>
@@ -402,14 +453,14 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   // in flight while the previous plane is computed.
   constexpr int NX = (SW_LX * SW_LY + 255) / 256;
   constexpr int NK = ((SW_TX + 1) * (SW_TY + 1) + 255) / 256;
-  long xoff[NX];
+  int xoff[NX];  // node offsets within a plane (grids have < 2^31 nodes)
   T xpf[NX];
 #pragma unroll
   for (int q = 0; q < NX; ++q) {
     const int e = tid + 256 * q;
     const int r = e / SW_LX, c = e - r * SW_LX;
     const int gi = i0 - 1 + c, gj = j0 - 1 + r;
-    xoff[q] = min(gi, n) + min(gj, n) * sy;  // always inside the grid
+    xoff[q] = min(gi, n) + min(gj, n) * (int)sy;  // always inside the grid
   }
   // Loads sit behind no branch or select, so the compiler keeps a plane's
   // loads in flight across the computation of the previous plane instead of
@@ -418,9 +469,9 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   // only the stencils of unknowns beyond m, which are never written, see
   // such a value.  The same holds for b and the cell coefficients below.
   auto prefetch_x = [&](int z) {
-    const long zo = (long)min(z, n) * sz;
+    const T* __restrict__ xz = x + (long)min(z, n) * sz;
 #pragma unroll
-    for (int q = 0; q < NX; ++q) xpf[q] = x[xoff[q] + zo];
+    for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
   };
   auto commit_x = [&](int s) {
     T* dst = &sx[s][0][0];
@@ -430,7 +481,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       if (e < SW_LX * SW_LY) dst[e] = xpf[q];
     }
   };
-  long koff[NK];
+  int koff[NK];
   T kpf[NK];
   if (KIND == OP_KAPPA) {
 #pragma unroll
@@ -438,13 +489,13 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       const int e = tid + 256 * q;
       const int r = e / (SW_TX + 1), c = e - r * (SW_TX + 1);
       const int cx = i0 - 1 + c, cy = j0 - 1 + r;
-      koff[q] = min(cx, n - 1) + (long)n * min(cy, n - 1);
+      koff[q] = min(cx, n - 1) + n * min(cy, n - 1);
     }
   }
   auto prefetch_k = [&](int cz) {
-    const long zo = (long)n * n * min(cz, n - 1);
+    const T* __restrict__ kz_ = kap + (long)n * n * min(cz, n - 1);
 #pragma unroll
-    for (int q = 0; q < NK; ++q) kpf[q] = kap[koff[q] + zo];
+    for (int q = 0; q < NK; ++q) kpf[q] = kz_[koff[q]];
   };
   auto commit_k = [&](int s) {
     T* dst = &sk[s][0][0];
@@ -473,123 +524,187 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       for (int c = 0; c < 3; ++c) w[r][c] = sk[s][ty + r][2 * tx + c];
   };
 
-  // plane z lives in slot z & 1, cell layer z in slot z & 1
-  T wx[3][3][4];  // planes k-1, k, k+1
-  T wk[2][2][3];  // cell layers k-1, k
-  if (!ZERO) {
-    prefetch_x(k0 - 1);
-    commit_x((k0 - 1) & 1);
-    prefetch_x(k0);
-    commit_x(k0 & 1);
-    prefetch_x(k0 + 1);
-  }
-  if (KIND == OP_KAPPA) {
-    prefetch_k(k0 - 1);
-    commit_k((k0 - 1) & 1);
-    prefetch_k(k0);
-  }
-  __syncthreads();
-  if (!ZERO) {
-    window_x((k0 - 1) & 1, wx[0]);
-    window_x(k0 & 1, wx[1]);
-  }
-  if (KIND == OP_KAPPA) window_k((k0 - 1) & 1, wk[0]);
-  // the first plane committed in the loop reuses the slot of plane k0-1
-  __syncthreads();
-  // right-hand sides of the thread's two unknowns, one plane ahead
-  T bpf[2] = {T(0), T(0)};
+  // Planes are processed in order p = k0-1 .. k1+1; plane p and cell layer
+  // p go to LDS slot p & 1.  At plane p each thread reads its window once
+  // and reduces it to the sums the stencils need (the operator is a sum of
+  // per-plane parts, see stencil3_const_sum / the kappa parts): the parts of
+  // plane p for the unknowns of planes p-1 and p+1 (x/y edges and corners,
+  // or the kappa Q/R sums) and for the unknown of plane p itself (in-plane
+  // corners and centre, or P and the coefficient sum).  The unknowns of
+  // plane p-1 are then complete and are written.  Only these sums are
+  // carried between planes, not the windows, which keeps the register
+  // count low.  In a red-black half-sweep a thread updates one of its two
+  // unknowns per plane, alternately i and i+1, so one set of sums suffices.
+  constexpr bool RB = MODE == SM_RB0 || MODE == SM_RB1;
+  constexpr bool KAP = KIND == OP_KAPPA;
+  constexpr int NC = RB ? 1 : 2;  // unknowns computed per thread and plane
+  const int colour = MODE == SM_RB1 ? 1 : 0;
   const long pb0 = min(i, n - 1) + min(j, n) * sy;  // clamped into the grid
+  T bpf[2] = {T(0), T(0)};
   auto prefetch_b = [&](int k) {
     const long p = pb0 + (long)min(k, n) * sz;
 #pragma unroll
     for (int u = 0; u < 2; ++u) bpf[u] = b[p + u];
   };
-  prefetch_b(k0);
+  auto store = [&](int k, int u, T v) { out[i + u + j * sy + (long)k * sz] = v; };
   double sq = 0.0;
-  for (int k = k0; k <= k1; ++k) {
-    const int s = (k + 1) & 1;
-    if (!ZERO) {
-      commit_x(s);        // plane k+1
-      prefetch_x(k + 2);  // in flight while plane k is computed
+  T kwp[2][3];  // cell window of layer p-1
+#pragma unroll
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) kwp[r][c] = T(0);
+
+  if (ZERO) {
+    // x = 0: an updated unknown gets (omega) b / a_pp, the others 0
+    if (KAP) {
+      prefetch_k(k0 - 1);
+      commit_k((k0 - 1) & 1);
+      prefetch_k(k0);
+      __syncthreads();
+      window_k((k0 - 1) & 1, kwp);
     }
-    if (KIND == OP_KAPPA) {
-      commit_k(k & 1);    // cell layer k
-      prefetch_k(k + 1);
+    for (int k = k0; k <= k1; ++k) {
+      if (KAP) {
+        commit_k(k & 1);
+        prefetch_k(k + 1);
+      }
+      prefetch_b(k);
+      __syncthreads();
+      T kwc[2][3];
+      if (KAP) window_k(k & 1, kwc);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const bool ok = u == 0 ? ok0 : ok1;
+        const bool upd = MODE == SM_JACOBI || (((i + u + j + k) & 1) == colour);
+        if (!ok) continue;
+        T dg = op.wc;
+        if (KAP) dg = op.s * T(4) * kappa_cell_sum<T>(kwp, kwc, u);
+        store(k, u, !upd ? T(0) : (MODE == SM_JACOBI ? omega * (bpf[u] / dg) : bpf[u] / dg));
+      }
+      if (KAP) {
+#pragma unroll
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) kwp[r][c] = kwc[r][c];
+      }
     }
-    const T bcur[2] = {bpf[0], bpf[1]};
-    prefetch_b(k + 1);
+    return;
+  }
+
+  // sums carried per computed unknown q (see above):
+  //   s2 / s1: side parts of planes p-2 / p-1 for the unknowns two / one
+  //            plane(s) up: {x-edges, y-edges, corners} (kappa: {Q, -, -})
+  //   g1, x1, k1s: plane-(p-1) parts of its own unknown: in-plane corners
+  //            (kappa: P), centre value, coefficient sum (kappa)
+  T s2[NC][3], s1[NC][3], g1[NC], x1[NC], k1s[NC];
+  T xo1 = T(0);  // red-black: old value of the other unknown at plane p-1
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    g1[q] = x1[q] = k1s[q] = T(0);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) s2[q][t] = s1[q][t] = T(0);
+  }
+  prefetch_x(k0 - 1);
+  if (KAP) prefetch_k(k0 - 1);
+  for (int p = k0 - 1; p <= k1 + 1; ++p) {
+    commit_x(p & 1);
+    prefetch_x(p + 1);
+    if (KAP) {
+      commit_k(p & 1);
+      prefetch_k(p + 1);
+    }
+    const T bcur[2] = {bpf[0], bpf[1]};  // b of plane p-1 (red-black: [0], its updated unknown)
+    if (!RB) prefetch_b(p);
     __syncthreads();
-    if (!ZERO) window_x(s, wx[2]);
-    if (KIND == OP_KAPPA) window_k(k & 1, wk[1]);
-    const long p = i + j * sy + (long)k * sz;
-    // the two unknowns (column 1 = i, column 2 = i+1 of the window)
+    T w[3][4];
+    window_x(p & 1, w);
+    T kwc[2][3];
+    if (KAP) window_k(p & 1, kwc);
+    // red-black: column updated at plane p (the unknowns at p-1, p+1 use
+    // the other one); the same for a whole wavefront (one row j), so the
+    // branch below does not diverge, and inside it every window index is a
+    // constant (runtime indices into register arrays become select chains)
+    T sn[NC][3], gn[NC], xn[NC], kn[NC], xon;
+    const int k = p - 1;
+    auto step = [&](auto upc) {
+      constexpr int up = decltype(upc)::value;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const bool ok = u == 0 ? ok0 : ok1;
-      const bool upd = MODE == SW_RESID || MODE == SM_JACOBI || HEAD ||
-                       (((i + u + j + k) & 1) == (MODE == SM_RB1 ? 1 : 0));
-      if (!ok) continue;
-      if (!upd) {
-        out[p + u] = ZERO ? T(0) : wx[1][1][1 + u];
-        continue;
-      }
-      T kk[2][2][2];
-      if (KIND == OP_KAPPA) {
-#pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int a = 0; a < 2; ++a) kk[c][bb][a] = wk[c][bb][u + a];
-      }
-      if (ZERO) {
-        const T dg = KIND == OP_KAPPA ? kappa_diag3(op, kk) : op.wc;
-        out[p + u] = MODE == SM_JACOBI ? omega * (bcur[u] / dg) : bcur[u] / dg;
-        continue;
-      }
-      T v[3][3][3];
-#pragma unroll
-      for (int dz = 0; dz < 3; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 3; ++dy)
-#pragma unroll
-          for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = wx[dz][dy][u + dx];
-      T ax, dg;
-      if (KIND == OP_KAPPA) {
-        ax = stencil3_kappa(op, kk, v, dg);
-      } else {
-        ax = stencil3_const(op, v);
-        dg = op.wc;
-      }
-      if (MODE == SW_RESID) {
-        const T res = bcur[u] - ax;
-        out[p + u] = res;
-        sq += (double)res * (double)res;
-      } else if (HEAD) {
-        const T res = bcur[u] - ax;
-        sq += (double)res * (double)res;
-        const T q = res / dg;
-        const bool c0 = ((i + u + j + k) & 1) == 0;
-        out[p + u] = MODE == SW_HEAD_JAC ? v[1][1][1] + omega * q : (c0 ? v[1][1][1] + q : v[1][1][1]);
-      } else {
-        const T q = (bcur[u] - ax) / dg;
-        out[p + u] = MODE == SM_JACOBI ? v[1][1][1] + omega * q : v[1][1][1] + q;
-      }
-    }
-    if (!ZERO) {
-#pragma unroll
-      for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          wx[0][r][c] = wx[1][r][c];
-          wx[1][r][c] = wx[2][r][c];
+      for (int q = 0; q < NC; ++q) {
+        const int cs = RB ? 1 - up : q;  // column of the unknowns at p-1 and p+1
+        const int cc = RB ? up : q;      // column of the unknown at p
+        if (KAP) {
+          sn[q][0] = kappa_side<T>(kwc, w, cs);  // Q of the unknown at p+1 (layer p)
+          sn[q][1] = kappa_side<T>(kwp, w, cs);  // R of the unknown at p-1 (layer p-1)
+          sn[q][2] = T(0);
+          kappa_plane<T>(kwp, kwc, w, cc, gn[q], kn[q]);
+        } else {
+          plane_parts<T>(w, cs, sn[q][0], sn[q][1], sn[q][2]);
+          T ea, eb;
+          plane_parts<T>(w, cc, ea, eb, gn[q]);
+          kn[q] = T(0);
         }
+        xn[q] = w[1][cc + 1];
+      }
+      xon = w[1][(1 - up) + 1];
+      if (k < k0) return;
+      // complete the unknowns of plane k
+#pragma unroll
+      for (int q = 0; q < NC; ++q) {
+        const int u = RB ? 1 - up : q;
+        const bool ok = u == 0 ? ok0 : ok1;
+        if (!ok) continue;
+        T ax, dg;
+        if (KAP) {
+          ax = op.s * (g1[q] - (s2[q][0] + sn[q][1]));
+          dg = op.s * T(4) * k1s[q];
+        } else {
+          ax = stencil3_const_sum(op, x1[q], g1[q], s2[q][0], sn[q][0], s2[q][1], sn[q][1],
+                                  s2[q][2], sn[q][2]);
+          dg = op.wc;
+        }
+        const T res = (RB ? bcur[0] : bcur[u]) - ax;
+        if (MODE == SW_RESID) {
+          store(k, u, res);
+          sq += (double)res * (double)res;
+        } else if (HEAD) {
+          sq += (double)res * (double)res;
+          const T d = res / dg;
+          const bool c0 = ((i + u + j + k) & 1) == 0;
+          store(k, u, MODE == SW_HEAD_JAC ? x1[q] + omega * d : (c0 ? x1[q] + d : x1[q]));
+        } else {
+          const T d = res / dg;
+          store(k, u, MODE == SM_JACOBI ? x1[q] + omega * d : x1[q] + d);
+        }
+      }
+      if (RB && (up == 0 ? ok0 : ok1)) store(k, up, xo1);  // the other unknown keeps its value
+    };
+    // red-black: b of the unknown updated at plane p, for the next plane
+    auto prefetch_b1 = [&](int up) { bpf[0] = b[pb0 + (long)min(p, n) * sz + up]; };
+    if (!RB || ((colour + 1 + j + p) & 1) == 0) {  // i is odd
+      if (RB) prefetch_b1(0);
+      step(std::integral_constant<int, 0>{});
+    } else {
+      prefetch_b1(1);
+      step(std::integral_constant<int, 1>{});
     }
-    if (KIND == OP_KAPPA) {
+    // shift
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        s2[q][t] = s1[q][t];
+        s1[q][t] = sn[q][t];
+      }
+      g1[q] = gn[q];
+      x1[q] = xn[q];
+      k1s[q] = kn[q];
+    }
+    xo1 = xon;
+    if (KAP) {
 #pragma unroll
       for (int r = 0; r < 2; ++r)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) wk[0][r][c] = wk[1][r][c];
+        for (int c = 0; c < 3; ++c) kwp[r][c] = kwc[r][c];
     }
   }
   if ((MODE == SW_RESID && NORM) || HEAD) {
