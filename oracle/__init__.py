@@ -18,6 +18,9 @@ What it computes, and where the paper defines it:
   adjoint R = P^T (Sec. 5.4, read for nested conforming Q1 spaces);
 * the outer fixed-point iteration of cycles (Sec. 5.5.1);
 * an FP32-inner / FP64-outer iterative-refinement wrapper of that iteration;
+* conjugate gradients preconditioned by one V-cycle per iteration
+  (multigrid as a Krylov preconditioner, Sec. 1), in FP64 or with the
+  cycle in FP32;
 * independent exact references (dense Cholesky, DST-I diagonalisation,
   sparse LU) used only to pin the rest.
 
@@ -49,6 +52,8 @@ from .mg import (
     vcycle,
     solve,
     solve_ir,
+    solve_pcg,
+    precondition,
     colour_mask,
 )
 from .exact import (

@@ -208,3 +208,69 @@ def solve_ir(H, b, tol, max_iter=100, diverge=1e3):
         if rho <= tol:
             return u, k, hist, "ok"
     return u, max_iter, hist, "maxit"
+
+
+def precondition(H, r, fp32=False):
+    """The multigrid preconditioner: z = one V-cycle from a zero guess on
+    A z = r.  With fp32, the cycle runs in float32 on r / ||r|| and is
+    scaled back: z = ||r|| * float64(cycle32(float32(r / ||r||))).  The
+    cycle is symmetric (post-smoothing reverses the colour order of the
+    pre-smoothing, nu_pre = nu_post), so in exact arithmetic z = B r with
+    B symmetric positive definite."""
+    if not fp32:
+        return vcycle(H, 0, np.zeros_like(r), r)
+    s = np.linalg.norm(r)
+    if s == 0.0:
+        return np.zeros_like(r)
+    r32 = (r / s).astype(np.float32)
+    return s * vcycle(H, 0, np.zeros_like(r32), r32, fp32=True).astype(np.float64)
+
+
+def solve_pcg(H, b, tol, max_iter=100, diverge=1e3, fp32=False, precond=None):
+    """Conjugate gradients on A u = b preconditioned by one V-cycle per
+    iteration.  The paper names multigrid as a preconditioner for Krylov
+    solvers (Sec. 1, with GMRES); A is symmetric positive definite and the
+    V-cycle symmetric, so CG is the Krylov method used here.
+
+    Steps per iteration k (u_0 = 0, r_0 = b, z_0 = B r_0, p_0 = z_0):
+      q = A p;  alpha = (r, z) / (p, q);  u += alpha p;  r' = r - alpha q;
+      stop if ||r'|| / ||b|| <= tol;
+      z' = B r';  beta = (z', r' - r) / (r, z);  p = z' + beta p.
+    beta is the flexible (Polak-Ribiere) form: for a fixed SPD B it equals
+    the classical (z', r') / (z, r) because (z', r) = 0, and it keeps the
+    iteration robust when B is applied in float32.  The stopping test uses
+    the recursively updated residual r'.
+
+    precond: optional replacement for the V-cycle (a function r -> z), for
+    the special cases that pin this routine.  Returns (u, iters, hist,
+    status) like :func:`solve`.
+    """
+    b = np.asarray(b, dtype=np.float64)
+    A = H.A[0]
+    M = precond if precond is not None else (lambda v: precondition(H, v, fp32))
+    nb = np.linalg.norm(b)
+    u = np.zeros_like(b)
+    hist = [1.0]
+    if nb == 0.0:
+        return u, 0, hist, "ok"
+    r = b.copy()
+    z = M(r)
+    p = z.copy()
+    rz = r @ z
+    for k in range(1, max_iter + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        u = u + alpha * p
+        r_new = r - alpha * q
+        rho = np.linalg.norm(r_new) / nb
+        hist.append(rho)
+        if not np.isfinite(rho) or rho > diverge:
+            return u, k, hist, "diverged"
+        if rho <= tol:
+            return u, k, hist, "ok"
+        z = M(r_new)
+        beta = (z @ r_new - z @ r) / rz
+        rz = z @ r_new
+        p = z + beta * p
+        r = r_new
+    return u, max_iter, hist, "maxit"

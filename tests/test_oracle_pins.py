@@ -397,3 +397,77 @@ def test_paper_dof_counts():
     assert hh["n_fine"] >> (hh["levels"] - 1) == hh["n_coarse"]
     # one refinement multiplies cells by 8 in 3D
     assert (2 * 16) ** 3 // 16 ** 3 == g["refinement_cell_factor_3d"]["factor"]
+
+
+# ---- multigrid-preconditioned conjugate gradients -------------------------
+
+@pytest.mark.parametrize("dim,n,levels,smoother", [(2, 16, 3, "rbgs"), (2, 16, 3, "jacobi"),
+                                                   (3, 8, 3, "rbgs")])
+def test_vcycle_preconditioner_is_symmetric_positive_definite(dim, n, levels, smoother, rng):
+    """z = V-cycle(0, r) is B r with B = (I - E) A^-1 (E the cycle's error
+    propagation matrix, built from the smoother matrices); the symmetric
+    cycle makes B SPD, which CG needs."""
+    H = O.build_hierarchy(dim, n, levels, smoother=smoother)
+    N = (n - 1) ** dim
+    A = H.A[0].toarray()
+    Bm = (np.eye(N) - _cycle_matrix(H, 0)) @ np.linalg.inv(A)
+    r = rng.uniform(-1, 1, N)
+    np.testing.assert_allclose(O.precondition(H, r), Bm @ r, rtol=0, atol=1e-12)
+    assert np.abs(Bm - Bm.T).max() <= 1e-10 * np.abs(Bm).max()
+    assert np.linalg.eigvalsh(0.5 * (Bm + Bm.T)).min() > 0
+
+
+def test_pcg_with_identity_preconditioner_is_scipy_cg(rng):
+    from scipy.sparse.linalg import cg
+    H = O.build_hierarchy(3, 8, 2)
+    A = H.A[0]
+    b = rng.uniform(-1, 1, A.shape[0])
+    xs = []
+    cg(A, b, rtol=1e-14, maxiter=10, callback=lambda xk: xs.append(xk.copy()))
+    assert len(xs) >= 6
+    for k, xk in enumerate(xs, start=1):
+        uk = O.solve_pcg(H, b, 1e-300, max_iter=k, precond=lambda r: r.copy())[0]
+        assert np.linalg.norm(uk - xk) <= 1e-10 * np.linalg.norm(xk), k
+
+
+def test_pcg_with_exact_preconditioner_converges_in_one_iteration(rng):
+    # one level: the "cycle" is the exact coarsest Cholesky solve
+    H = O.build_hierarchy(2, 8, 1)
+    b = rng.uniform(-1, 1, 49)
+    u, k, hist, st = O.solve_pcg(H, b, 1e-12)
+    assert st == "ok" and k == 1
+    np.testing.assert_allclose(u, O.dense_solve(H.A[0], b), rtol=1e-12, atol=1e-14)
+
+
+def test_pcg_iterates_minimise_the_energy_error_over_the_krylov_space():
+    """The k-th PCG iterate minimises ||u* - u||_A over the span of
+    B r0, (B A) B r0, ..., (B A)^(k-1) B r0 (textbook optimality)."""
+    H = O.build_hierarchy(2, 16, 3, smoother="rbgs")
+    A = H.A[0].toarray()
+    N = A.shape[0]
+    Bm = (np.eye(N) - _cycle_matrix(H, 0)) @ np.linalg.inv(A)
+    b = W.rhs_uniform(2, 16, 5)
+    for k in (1, 2, 3):
+        uk = O.solve_pcg(H, b, 1e-300, max_iter=k)[0]
+        vecs = [Bm @ b]
+        for _ in range(k - 1):
+            vecs.append(Bm @ (A @ vecs[-1]))
+        V = np.linalg.qr(np.array(vecs).T)[0]
+        y = np.linalg.solve(V.T @ A @ V, V.T @ b)
+        assert np.linalg.norm(uk - V @ y) <= 1e-9 * np.linalg.norm(V @ y), k
+
+
+def test_pcg_beats_the_stationary_cycle_and_fp32_cycle_matches():
+    dim, n = 3, 32
+    kappa = W.kappa_lognormal(dim, n, 0)
+    b = W.rhs_uniform(dim, n, 3)
+    H = O.build_hierarchy(dim, n, 5, kappa=kappa, fp32=True)
+    _, ks, _, _ = O.solve(H, b, 1e-8)
+    u, k, hist, st = O.solve_pcg(H, b, 1e-8)
+    assert st == "ok" and k < ks
+    r = b - H.A[0] @ u
+    # the recursive residual tracks the true one
+    assert abs(np.linalg.norm(r) / np.linalg.norm(b) - hist[k]) <= 1e-10
+    u32, k32, hist32, st32 = O.solve_pcg(H, b, 1e-8, fp32=True)
+    assert st32 == "ok" and abs(k32 - k) <= 1
+    assert np.linalg.norm(u32 - u) <= 1e-6 * np.linalg.norm(u)
