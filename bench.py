@@ -162,24 +162,29 @@ def roofline_stencil(S, w, bd, s):
             "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(per)}
 
 
-def run_workload(name, steps, warmup, with_roofline=False):
+def run_workload(name, steps, warmup, with_roofline=False, pcg=False):
+    """Time `steps` solves of a workload: the plain cycle iteration, or with
+    pcg conjugate gradients preconditioned by one cycle per iteration."""
     import torch
     from paper_1609_04809_amd import workloads as W
-    from paper_1609_04809_amd.mg import Solver
+    from paper_1609_04809_amd.mg import FLAG_PCG, Solver
     w = W.WORKLOADS[name]
     b, kappa, bd = _device_rhs(w)
     t0 = time.perf_counter()
     S = Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=w.smoother,
-               nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision=w.precision)
+               nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision=w.precision,
+               flags=FLAG_PCG if pcg else 0)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     t, k, hist, u = time_solves(S, bd, w.tol, steps, warmup)
     res = {"workload": name, "dofs": w.dofs, "unknowns": w.unknowns,
            "MDOF_per_s": round(w.dofs / t / 1e6, 1), "ms_per_solve": round(t * 1e3, 3),
            "cycles": k, "final_rel_residual": hist[-1], "setup_s": round(setup_s, 3),
-           "precision": w.precision, "op": w.op}
+           "precision": w.precision, "op": w.op, "method": "pcg" if pcg else "cycle"}
     roof = None
-    if w.op == "csr":
+    if pcg:
+        pass
+    elif w.op == "csr":
         if with_roofline:
             roof = roofline_csr(S, w, bd)
     elif w.dim == 3:
@@ -279,6 +284,15 @@ def main():
                 continue
             r, _, _ = run_workload(other, max(3, args.steps // 4), 1)
             log(f"[bench] {other}: {r['MDOF_per_s']} MDOF/s, {r['cycles']} cycles, "
+                f"{r['ms_per_solve']} ms/solve")
+            extra.append(r)
+        # the next row of the method: CG preconditioned by one cycle per
+        # iteration, on the 3D workloads
+        for other in W.WORKLOADS:
+            if W.WORKLOADS[other].dim != 3:
+                continue
+            r, _, _ = run_workload(other, max(3, args.steps // 4), 1, pcg=True)
+            log(f"[bench] {other} (pcg): {r['MDOF_per_s']} MDOF/s, {r['cycles']} iterations, "
                 f"{r['ms_per_solve']} ms/solve")
             extra.append(r)
     serving = None

@@ -66,6 +66,16 @@ typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
                                 each cycle in a launch of its own instead of
                                 in one pass with the next cycle's first
                                 pre-smoothing step (same results bitwise) */
+#define MG_FLAG_PCG 8        /* mg_solve runs conjugate gradients
+                                preconditioned by one V-cycle per iteration
+                                (multigrid as a Krylov preconditioner,
+                                Sec. 1) instead of the plain cycle iteration
+                                (Sec. 5.5.1); needs a symmetric cycle
+                                (nu_pre == nu_post).  In FP32_IR contexts the
+                                preconditioning cycle runs in FP32 on
+                                r / ||r||.  Iterations and the history then
+                                count CG iterations, with the recursively
+                                updated residual.  Not for the server. */
 
 typedef struct {
   int dim;          /* 2 or 3 */

@@ -18,7 +18,8 @@ OUTDIR = os.path.join(PKG, "lib")
 BUILDDIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(OUTDIR, "libmg.so")
 
-SOURCES = ["kernels_grid.hip", "kernels_csr.hip", "mg_runtime.cpp", "mg_server.cpp"]
+SOURCES = ["kernels_grid.hip", "kernels_csr.hip", "kernels_pcg.hip", "mg_runtime.cpp",
+           "mg_server.cpp"]
 
 ARCH = os.environ.get("MG_OFFLOAD_ARCH", "gfx950")
 

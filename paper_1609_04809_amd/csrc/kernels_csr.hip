@@ -73,6 +73,7 @@ __device__ __forceinline__ V ld_stream(const V* p) {
 // MODE 3: over all rows, the residual partial sums of MODE 0 and, written to
 //         out, the colour-0 red-black update with colour-1 unknowns copied.
 // MODE 4: over all rows, the residual partial sums and the Jacobi update.
+// MODE 5: out = A x over all rows with partial sums of x.(A x).
 // ZERO: x = 0 (x is not read).
 // Phase 1 issues all column and value loads of a thread before any gather,
 // so that about 2 * PER loads per thread are in flight.  The loads carry no
@@ -147,11 +148,14 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
     if (MODE == 0) {
       out[node] = res;
       sq = (double)res * (double)res;
+    } else if (MODE == 5) {
+      out[node] = s;
+      sq = (double)x0 * (double)s;
     } else if (MODE >= 3) {
       // residual of every row plus the first smoothing step: Jacobi (4)
       // updates every row, red-black (3) the colour-0 rows, which come first
       sq = (double)res * (double)res;
-      const bool upd = MODE == 4 || r0 + lr < A.coff[1];
+      const bool upd = MODE == 4 || r0 + lr < A.coff[1];  // MODE 3 or 4
       const T q = res / dg;
       out[node] = upd ? (MODE == 4 ? x0 + omega * q : x0 + q) : x0;
     } else {
@@ -295,6 +299,13 @@ void launch_csr_head(const Geo&, const CsrOp<T>& A, int kind, const T* x, const 
 }
 
 template <typename T>
+void launch_csr_apply_dot(const Geo&, const CsrOp<T>& A, const T* x, T* q, double* partials,
+                          hipStream_t s) {
+  // b is not used by MODE 5; x stands in for it so that every load is valid
+  launch_rows<T, 5>(A, 0, A.rows, x, x, q, T(0), partials, s);
+}
+
+template <typename T>
 void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s) {
   if (kind == SM_JACOBI) {
@@ -313,7 +324,9 @@ void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, co
   template void launch_csr_smooth<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*,   \
                                      T*, T, hipStream_t);                                    \
   template void launch_csr_head<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*, T*, \
-                                   T, double*, hipStream_t);
+                                   T, double*, hipStream_t);                                 \
+  template void launch_csr_apply_dot<T>(const Geo&, const CsrOp<T>&, const T*, T*, double*,  \
+                                        hipStream_t);
 INST(float)
 INST(double)
 #undef INST

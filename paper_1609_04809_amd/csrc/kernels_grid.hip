@@ -395,6 +395,7 @@ __device__ __forceinline__ T prolong_node(const DGeo& gc, const T* __restrict__ 
 constexpr int SW_RESID = 3;
 constexpr int SW_HEAD_RB0 = 4;
 constexpr int SW_HEAD_JAC = 5;
+constexpr int SW_APPLY = 6;  // out = A x with partial sums of x.(A x)
 constexpr int SW_TX = 128;  // unknowns per tile in x (2 per thread)
 constexpr int SW_TY = 4;    // unknowns per tile in y (1 per thread row)
 constexpr int SW_LX = SW_TX + 2, SW_LY = SW_TY + 2;
@@ -614,7 +615,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       prefetch_k(p + 1);
     }
     const T bcur[2] = {bpf[0], bpf[1]};  // b of plane p-1 (red-black: [0], its updated unknown)
-    if (!RB) prefetch_b(p);
+    if (!RB && MODE != SW_APPLY) prefetch_b(p);
     __syncthreads();
     T w[3][4];
     window_x(p & 1, w);
@@ -663,7 +664,10 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
           dg = op.wc;
         }
         const T res = (RB ? bcur[0] : bcur[u]) - ax;
-        if (MODE == SW_RESID) {
+        if (MODE == SW_APPLY) {
+          store(k, u, ax);
+          sq += (double)x1[q] * (double)ax;
+        } else if (MODE == SW_RESID) {
           store(k, u, res);
           sq += (double)res * (double)res;
         } else if (HEAD) {
@@ -707,7 +711,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         for (int c = 0; c < 3; ++c) kwp[r][c] = kwc[r][c];
     }
   }
-  if ((MODE == SW_RESID && NORM) || HEAD) {
+  if ((MODE == SW_RESID && NORM) || HEAD || MODE == SW_APPLY) {
     const double t = block_sum(sq);
     if (tid == 0)
       I.partials[bx + (long)gridDim.x * (by + (long)gridDim.y * zc)] = t;
@@ -785,6 +789,23 @@ __global__ __launch_bounds__(256) void k_head(Geo g, StencilParams<T> op, T omeg
     const T q = res / dg;
     const bool upd = KS == SM_JACOBI || ((i + j + k) & 1) == 0;
     ((T*)I.c)[p] = upd ? (KS == SM_JACOBI ? x[p] + omega * q : x[p] + q) : x[p];
+  }
+  const double t = block_sum(sq);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * plane)] = t;
+}
+
+// q = A x with per-block partial sums of x.q.
+template <typename T, int DIM, int KIND>
+__global__ __launch_bounds__(256) void k_apply_dot(Geo g, StencilParams<T> op, Batch B) {
+  NODE_INDEX(DIM, g)
+  double sq = 0.0;
+  if (inside) {
+    const T* __restrict__ x = (const T*)I.a;
+    T ax, dg;
+    Apply<T, DIM, KIND>::at(op, (const T*)I.kappa, dgeo(g), x, p, i, j, k, ax, dg);
+    ((T*)I.c)[p] = ax;
+    sq = (double)x[p] * (double)ax;
   }
   const double t = block_sum(sq);
   if (threadIdx.x == 0 && threadIdx.y == 0)
@@ -1285,6 +1306,21 @@ void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, co
 }
 
 template <typename T>
+void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, hipStream_t s) {
+  if (use_sweep3(g)) {
+    if (op.kind == OP_KAPPA)
+      launch_sweep3<T, OP_KAPPA, SW_APPLY, false, true>(g, op, T(0), B, s);
+    else
+      launch_sweep3<T, OP_CONST, SW_APPLY, false, true>(g, op, T(0), B, s);
+    return;
+  }
+  const dim3 gr = node_grid(g, B.count), bl(BX, BY);
+#define L_AD(D, K) hipLaunchKernelGGL((k_apply_dot<T, D, K>), gr, bl, 0, s, g, op, B)
+  DISPATCH_DIM_KIND(g.dim, op.kind, L_AD);
+#undef L_AD
+}
+
+template <typename T>
 void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(gc, B.count), bl(BX, BY);
   if (gf.dim == 2)
@@ -1383,6 +1419,8 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
                                  const Batch&, hipStream_t);                                \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \
                                hipStream_t);                                                \
+  template void launch_apply_dot<T>(const Geo&, const StencilParams<T>&, const Batch&,      \
+                                    hipStream_t);                                           \
   template void launch_restrict<T>(const Geo&, const Geo&, const Batch&, hipStream_t);      \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const Batch&, hipStream_t);   \
   template void launch_coarse_solve<T>(const Geo&, int, const Batch&, hipStream_t);         \

@@ -19,6 +19,9 @@ struct Level {
   Geo g;
   // FP64 vectors (x and b of level 0 are the caller's)
   double *x64 = nullptr, *b64 = nullptr, *t64 = nullptr, *r64 = nullptr;
+  // preconditioned CG on level 0 (MG_FLAG_PCG): direction, A times it,
+  // preconditioned residual, residual and previous residual
+  double *p64 = nullptr, *q64 = nullptr, *z64 = nullptr, *rk64 = nullptr, *ro64 = nullptr;
   // FP32 vectors (FP32_IR contexts)
   float *x32 = nullptr, *b32 = nullptr, *t32 = nullptr, *r32 = nullptr;
   // coefficients per cell
@@ -54,7 +57,13 @@ enum OpCode {
   OC_CSR_RESID,
   OC_HEAD,      // residual partial sums + first smoothing step (sub: kind)
   OC_CSR_HEAD,
+  OC_APPLY_DOT,      // q = A x with partials of x.q
+  OC_CSR_APPLY_DOT,
+  OC_PCG,            // CG vector kernel (sub: PcgOp), pointers in ext[]
 };
+
+// CG vector kernels (OpRec::sub of OC_PCG)
+enum PcgOp { PO_DOTS2 = 0, PO_SCALARS, PO_DIR, PO_UPDATE, PO_ZSCALE };
 
 // One kernel launch of a cycle for one request.  Ops with equal keys (all
 // fields but `item`, `level` and `csr`) can run as one batched launch.
@@ -70,6 +79,7 @@ struct OpRec {
   long count = 0;   // OC_REDUCE: partials; OC_FILL / OC_COPY: elements
   Item item{};
   const void* csr = nullptr;  // CsrOp<T>* (CSR ops, not batchable)
+  void* ext[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // OC_PCG operands
 };
 
 bool same_key(const OpRec& a, const OpRec& b);
@@ -100,10 +110,11 @@ struct mg_ctx {
   int tail_lds[2] = {0, 0};     // dynamic LDS bytes of the tail launch (FP64, FP32)
   double* pinned = nullptr;     // host pinned scalars
   hipStream_t cap = nullptr;    // private stream for graph capture
-  // one cached graph per iteration kind (plain, first fused, steady fused),
-  // valid for the (u, b) it was captured with
-  hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
-  const void* gkey[3][2] = {};
+  // one cached graph per iteration kind (plain, first fused, steady fused,
+  // first CG, steady CG), valid for the (u, b) it was captured with
+  static constexpr int kIterKinds = 5;
+  hipGraphExec_t gexec[kIterKinds] = {};
+  const void* gkey[kIterKinds][2] = {};
   // profiling
   int prof_kernel = -1;
   bool prof_on = false;

@@ -211,6 +211,11 @@ void launch_cast_f32(const double* a, float* b, long count, hipStream_t s);
 void launch_count_bad_kappa(const double* k, long count, int* bad_nonpos, int* bad_nonfinite,
                             hipStream_t s);
 
+// q = A x with per-block partial sums of x.q (the operator-apply step of
+// preconditioned CG):  a = x, c = q, kappa, partials.
+template <typename T>
+void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, hipStream_t s);
+
 // ---- CSR kernels (kernels_csr.hip) ----------------------------------------
 template <typename T>
 void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
@@ -225,8 +230,27 @@ long csr_residual_blocks_max(int rows);  // upper bound over launch variants
 template <typename T>
 void launch_csr_head(const Geo& g, const CsrOp<T>& A, int kind, const T* x, const T* b, T* xout,
                      T omega, double* partials, hipStream_t s);
+// q = A x with per-block partial sums of x.q, over all rows.
+template <typename T>
+void launch_csr_apply_dot(const Geo& g, const CsrOp<T>& A, const T* x, T* q, double* partials,
+                          hipStream_t s);
 template <typename T>
 void launch_csr_smooth(const Geo& g, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s);
+
+// ---- preconditioned CG vector kernels (kernels_pcg.hip) -------------------
+// Device scalars of the iteration (indices into the context's scal[]);
+// scal[0] holds ||r||^2 and scal[1] ||b||^2 as for every solve.
+enum PcgScalar { PCG_PQ = 3, PCG_RZ = 4, PCG_ZR = 5, PCG_ZRO = 6, PCG_BETA = 7 };
+constexpr int kPcgBlocks = 1024;  // blocks (and partial sums) of a vector kernel
+long pcg_blocks(long n);
+void launch_pcg_dots2(const double* z, const double* r, const double* ro, long n, double* pa,
+                      double* pb, hipStream_t s);
+void launch_pcg_scalars(double* scal, int first, hipStream_t s);
+void launch_pcg_dir(const double* z, double* p, const double* scal, long n, int first,
+                    hipStream_t s);
+void launch_pcg_update(double* u, const double* p, double* r, double* ro, const double* q,
+                       const double* scal, long n, double* part, hipStream_t s);
+void launch_pcg_zscale(const float* c, double* z, const double* scal, long n, hipStream_t s);
 
 }  // namespace mg

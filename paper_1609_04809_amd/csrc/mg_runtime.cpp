@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <initializer_list>
 #include <string>
 #include <utility>
 #include <vector>
@@ -94,7 +95,8 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
-  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE)) { why = "unknown flags"; return false; }
+  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG)) { why = "unknown flags"; return false; }
+  if ((o->flags & MG_FLAG_PCG) && o->nu_pre != o->nu_post) { why = "CG needs a symmetric cycle (nu_pre == nu_post)"; return false; }
   const long nc = o->n >> (o->levels - 1);
   const long m = ipow(nc - 1, o->dim);
   if (m > kCoarseMaxUnknowns) {
@@ -149,6 +151,14 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     }
     L.t64 = P.take<double>(g.nodes);
     L.r64 = P.take<double>(g.nodes);
+    if (l == 0 && (o.flags & MG_FLAG_PCG)) {
+      L.p64 = P.take<double>(g.nodes);
+      L.q64 = P.take<double>(g.nodes);
+      L.z64 = P.take<double>(g.nodes);
+      L.rk64 = P.take<double>(g.nodes);
+      L.ro64 = P.take<double>(g.nodes);
+      maxpart = std::max(maxpart, 2 * (long)kPcgBlocks);
+    }
     if (ir) {
       L.x32 = P.take<float>(g.nodes);
       L.b32 = P.take<float>(g.nodes);
@@ -503,10 +513,10 @@ long residual_partials(mg_ctx* c, int l) {
   return c->csr ? csr_residual_blocks(c->lv[l].rows) : grid_blocks(c->lv[l].g);
 }
 
-void emit_reduce(mg_ctx* c, const Sink& sink, long count, double* out) {
+void emit_reduce(mg_ctx* c, const Sink& sink, long count, double* out, double* part = nullptr) {
   OpRec o = base_op<double>(c, OC_REDUCE, 0);
   o.count = count;
-  o.item.partials = c->partials;
+  o.item.partials = part ? part : c->partials;
   o.item.scal = out;
   sink(o);
 }
@@ -623,11 +633,86 @@ bool head_fusion(const mg_ctx* c) {
 // spare);  IT_FUSED = the V-cycle without its head (taken from the spare),
 // then the fused residual norm + next head.  In every kind u holds the new
 // iterate and scal[0] its squared residual norm at the end.
-enum IterKind { IT_PLAIN = 0, IT_FUSED_FIRST = 1, IT_FUSED = 2 };
+enum IterKind { IT_PLAIN = 0, IT_FUSED_FIRST = 1, IT_FUSED = 2, IT_PCG_FIRST = 3, IT_PCG = 4 };
+
+// One CG vector kernel on level-0 vectors (see kernels_pcg.hip).
+void emit_pcg_op(mg_ctx* c, const Sink& sink, int sub, std::initializer_list<void*> vecs,
+                 long count, int flag = 0) {
+  OpRec o = base_op<double>(c, OC_PCG, 0);
+  o.sub = sub;
+  o.count = count;
+  o.item.flag = flag;
+  o.item.scal = c->scal;
+  o.item.partials = c->partials;
+  int q = 0;
+  for (void* v : vecs) o.ext[q++] = v;
+  sink(o);
+}
+
+// Conjugate gradients preconditioned by one V-cycle, one iteration (the
+// steps in the order of the oracle's solve_pcg, with the preconditioner
+// application of iteration k-1 moved to the front of iteration k so that
+// the residual norm is the last value of an iteration):
+//   z = B r;  beta = (z.r - z.r_old) / rz (0 first);  rz = z.r;
+//   p = z + beta p (p = z first);  q = A p;  alpha = rz / p.q;
+//   u += alpha p;  r_old = r;  r -= alpha q;  ||r||^2 into scal[0].
+// B is the V-cycle from a zero guess on A z = r (FP64), or in FP32 on
+// r / ||r|| scaled back by ||r||.  r lives in its own vector: the cycle
+// uses the level's residual buffer internally.
+void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
+  Level& L0 = c->lv[0];
+  const long N = L0.g.nodes;
+  double* S = c->scal;
+  if (c->ir) {
+    OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+    o.item.a = L0.rk64;
+    o.item.c = L0.b32;
+    o.item.scal = S + 0;
+    sink(o);
+    emit_vcycle<float>(c, sink, L0.x32, L0.t32, L0.b32, true);
+    emit_pcg_op(c, sink, PO_ZSCALE, {L0.x32, L0.z64}, N);
+  } else {
+    emit_vcycle<double>(c, sink, L0.z64, L0.t64, L0.rk64, true);
+  }
+  const long PB = pcg_blocks(N);
+  emit_pcg_op(c, sink, PO_DOTS2, {L0.z64, L0.rk64, L0.ro64}, N);
+  emit_reduce(c, sink, PB, S + PCG_ZR, c->partials);
+  emit_reduce(c, sink, PB, S + PCG_ZRO, c->partials + PB);
+  emit_pcg_op(c, sink, PO_SCALARS, {}, 0, first);
+  emit_pcg_op(c, sink, PO_DIR, {L0.z64, L0.p64}, N, first);
+  OpRec a = base_op<double>(c, c->csr ? OC_CSR_APPLY_DOT : OC_APPLY_DOT, 0);
+  a.item.a = L0.p64;
+  a.item.c = L0.q64;
+  a.item.partials = c->partials;
+  if (c->csr) a.csr = Bufs<double>::csr(L0);
+  sink(a);
+  emit_reduce(c, sink, residual_partials(c, 0), S + PCG_PQ, c->partials);
+  emit_pcg_op(c, sink, PO_UPDATE, {u, L0.p64, L0.rk64, L0.ro64, L0.q64}, N);
+  emit_reduce(c, sink, PB, S + 0, c->partials);
+}
+
+// Start of a CG solve: u = 0, ||b||^2 into scal[1], r = b - A u (= b on
+// the unknowns; the vector kernels also stream boundary entries, which
+// stay 0) with ||r||^2 into scal[0].
+void emit_pcg_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+  Level& L0 = c->lv[0];
+  emit_fill<double>(c, sink, 0, u);
+  OpRec o = base_op<double>(c, OC_NORM2, 0);
+  o.item.a = b;
+  o.item.partials = c->partials;
+  sink(o);
+  emit_reduce(c, sink, norm2_blocks(L0.g), c->scal + 1);
+  emit_residual<double>(c, sink, 0, u, b, L0.rk64, c->partials);
+  emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+}
 
 void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
                     int kind = IT_PLAIN) {
   Level& L0 = c->lv[0];
+  if (kind == IT_PCG_FIRST || kind == IT_PCG) {
+    emit_pcg_iteration(c, sink, u, kind == IT_PCG_FIRST);
+    return;
+  }
   if (kind != IT_PLAIN) {
     emit_vcycle<double>(c, sink, u, L0.t64, b, false, kind == IT_FUSED);
     emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
@@ -679,7 +764,9 @@ int prof_class(int code) {
     case OC_RESID:
     case OC_CSR_RESID:
     case OC_HEAD:
-    case OC_CSR_HEAD: return PK_RESID;
+    case OC_CSR_HEAD:
+    case OC_APPLY_DOT:
+    case OC_CSR_APPLY_DOT: return PK_RESID;
     case OC_RESTRICT: return PK_RESTRICT;
     case OC_PROLONG: return PK_PROLONG;
     default: return -1;
@@ -735,7 +822,7 @@ void drop_graph(mg_ctx* c, int kind) {
 }
 
 void drop_graphs(mg_ctx* c) {
-  for (int k = 0; k < 3; ++k) drop_graph(c, k);
+  for (int k = 0; k < mg_ctx::kIterKinds; ++k) drop_graph(c, k);
 }
 
 // Run one iteration of the given kind: replay the cached graph (captured on
@@ -812,6 +899,11 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
                              (T*)it.c, it.partials, s);
       break;
     case OC_HEAD: launch_head<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
+    case OC_APPLY_DOT: launch_apply_dot<T>(o.g, params_of<T>(o), B, s); break;
+    case OC_CSR_APPLY_DOT:
+      launch_csr_apply_dot<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (T*)it.c,
+                              it.partials, s);
+      break;
     case OC_CSR_HEAD:
       launch_csr_head<T>(o.g, *(const CsrOp<T>*)o.csr, o.sub, (const T*)it.a, (const T*)it.b,
                          (T*)it.c, (T)o.omega, it.partials, s);
@@ -829,7 +921,8 @@ namespace mg {
 
 bool batchable(const OpRec& a) {
   return a.code != OC_FILL && a.code != OC_COPY && a.code != OC_CSR_SMOOTH &&
-         a.code != OC_CSR_RESID && a.code != OC_CSR_HEAD;
+         a.code != OC_CSR_RESID && a.code != OC_CSR_HEAD && a.code != OC_CSR_APPLY_DOT &&
+         a.code != OC_PCG;
 }
 
 bool same_key(const OpRec& a, const OpRec& b) {
@@ -837,6 +930,24 @@ bool same_key(const OpRec& a, const OpRec& b) {
          a.g.n == b.g.n && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
          a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.omega == b.omega && a.m == b.m &&
          a.count == b.count && batchable(a) && batchable(b);
+}
+
+void launch_pcg(const OpRec& o, hipStream_t s) {
+  double* const* v = reinterpret_cast<double* const*>(o.ext);
+  double* S = o.item.scal;
+  double* part = o.item.partials;
+  switch (o.sub) {
+    case PO_DOTS2:
+      launch_pcg_dots2(v[0], v[1], v[2], o.count, part, part + pcg_blocks(o.count), s);
+      break;
+    case PO_SCALARS: launch_pcg_scalars(S, o.item.flag, s); break;
+    case PO_DIR: launch_pcg_dir(v[0], v[1], S, o.count, o.item.flag, s); break;
+    case PO_UPDATE: launch_pcg_update(v[0], v[1], v[2], v[3], v[4], S, o.count, part, s); break;
+    case PO_ZSCALE:
+      launch_pcg_zscale(reinterpret_cast<const float*>(o.ext[0]), v[1], S, o.count, s);
+      break;
+    default: break;
+  }
 }
 
 void launch_ops(const OpRec* const* ops, int n, hipStream_t s) {
@@ -848,6 +959,7 @@ void launch_ops(const OpRec* const* ops, int n, hipStream_t s) {
     case OC_REDUCE: launch_reduce_final(o.count, B, s); return;
     case OC_SCALE_CAST: launch_scale_cast(o.g, B, s); return;
     case OC_IR_UPDATE: launch_ir_update(o.g, B, s); return;
+    case OC_PCG: launch_pcg(o, s); return;
     default: break;
   }
   if (o.prec == 0)
@@ -1005,7 +1117,11 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   hipStream_t s = as_stream(stream);
   *iters = 0;
   if (hist) hist[0] = 1.0;
-  emit_prologue(c, launch_sink(c, s), u, b);
+  const bool pcg = (c->o.flags & MG_FLAG_PCG) != 0;
+  if (pcg)
+    emit_pcg_prologue(c, launch_sink(c, s), u, b);
+  else
+    emit_prologue(c, launch_sink(c, s), u, b);
   HIP_TRY(hipGetLastError());
   double nb2 = 0.0;
   mg_status st = read_scalar(c, 1, &nb2, s);
@@ -1015,7 +1131,9 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   const double nb = std::sqrt(nb2);
   const bool fuse = head_fusion(c);
   for (int k = 1; k <= c->o.max_iter; ++k) {
-    st = run_iteration(c, u, b, s, !fuse ? IT_PLAIN : (k == 1 ? IT_FUSED_FIRST : IT_FUSED));
+    const int kind = pcg ? (k == 1 ? IT_PCG_FIRST : IT_PCG)
+                         : (!fuse ? IT_PLAIN : (k == 1 ? IT_FUSED_FIRST : IT_FUSED));
+    st = run_iteration(c, u, b, s, kind);
     if (st != MG_OK) return st;
     double n2 = 0.0;
     st = read_scalar(c, 0, &n2, s);

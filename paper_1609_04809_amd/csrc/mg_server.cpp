@@ -419,6 +419,7 @@ mg_status mg_server_submit(mg_server* S, const mg_options* o, const double* b_ho
   if (!S || !o || !b_host || !u_host || !id) return fail(MG_E_ARG, "NULL argument");
   if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be > 0");
   if (o->op != MG_OP_STENCIL) return fail(MG_E_ARG, "serving takes matrix-free requests");
+  if (o->flags & MG_FLAG_PCG) return fail(MG_E_ARG, "serving runs the cycle iteration, not CG");
   if (mg_footprint_bytes(o) == 0) return MG_E_ARG;  // message set by mg_footprint_bytes
   auto r = std::make_unique<Request>();
   r->o = *o;

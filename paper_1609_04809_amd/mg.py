@@ -26,6 +26,7 @@ PREC = {"fp64": 0, "fp32_ir": 1}
 FLAG_NO_GRAPH = 1
 FLAG_NO_TAIL = 2
 FLAG_NO_FUSE = 4
+FLAG_PCG = 8
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4

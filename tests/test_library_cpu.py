@@ -64,7 +64,8 @@ def test_options_validation_and_footprint():
                 dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
                 dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
                 dict(dim=3, n=16, levels=3, max_iter=0),
-                dict(dim=3, n=16, levels=3, flags=8)):
+                dict(dim=3, n=16, levels=3, flags=16),
+                dict(dim=3, n=16, levels=3, flags=8, nu_pre=2, nu_post=1)):
         o = mg.make_options(**bad)
         assert L.mg_footprint_bytes(ctypes.byref(o)) == 0, bad
         assert L.mg_last_error().decode()
@@ -80,3 +81,13 @@ def test_paper_dof_counts_through_the_library():
     o = mg.make_options(3, 512, 6)
     # 513^3 = 135,005,697 nodes; footprint covers at least two such vectors
     assert L.mg_footprint_bytes(ctypes.byref(o)) >= 2 * 8 * 135005697
+
+
+def test_pcg_footprint_adds_five_finest_vectors():
+    mg = _lib()
+    L = mg.lib()
+    o = mg.make_options(3, 64, 6)
+    o_pcg = mg.make_options(3, 64, 6, flags=mg.FLAG_PCG)
+    extra = L.mg_footprint_bytes(ctypes.byref(o_pcg)) - L.mg_footprint_bytes(ctypes.byref(o))
+    assert extra >= 5 * 8 * 65 ** 3
+    assert extra <= 5 * 8 * 65 ** 3 + 2 * 8 * 1024 + 4096
