@@ -46,6 +46,8 @@ from .transfer import prolongation, restriction
 from .mg import (
     Hierarchy,
     build_hierarchy,
+    cycle,
+    CYCLE_SCHEDULE,
     jacobi_sweep,
     rb_half_sweep,
     smooth,

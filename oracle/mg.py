@@ -40,6 +40,7 @@ class Hierarchy:
     n: int
     levels: int
     smoother: str = "rbgs"          # "jacobi" or "rbgs"
+    cycle: str = "V"                # "V", "W" or "F"
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 2.0 / 3.0
@@ -62,11 +63,13 @@ def colour_mask(dim, n, colour):
 
 
 def build_hierarchy(dim, n, levels, kappa=None, smoother="rbgs", nu_pre=2,
-                    nu_post=2, omega=2.0 / 3.0, fp32=False):
+                    nu_post=2, omega=2.0 / 3.0, fp32=False, cycle="V"):
     """Assemble every level's operator and the transfers (Sec. 5.1)."""
     if levels < 1 or n % (1 << (levels - 1)) != 0 or (n >> (levels - 1)) < 2:
         raise ValueError("need n divisible by 2^(levels-1) and n_c >= 2")
-    H = Hierarchy(dim=dim, n=n, levels=levels, smoother=smoother,
+    if cycle not in CYCLE_SCHEDULE:
+        raise ValueError("cycle must be V, W or F")
+    H = Hierarchy(dim=dim, n=n, levels=levels, smoother=smoother, cycle=cycle,
                   nu_pre=nu_pre, nu_post=nu_post, omega=omega)
     kaps = kappa_hierarchy(dim, n, levels, kappa)
     for l in range(levels):
@@ -131,13 +134,23 @@ def coarse_solve(H, b, fp32=False):
 # V-cycle (Algorithm 1) and the outer iteration
 # --------------------------------------------------------------------------
 
-def vcycle(H, l, x, b, fp32=False):
-    """One V-cycle on level l for A_l x = b, starting from x.
+# Coarse-level cycles run from a level by each cycle kind, in order: the
+# V-cycle solves the residual equation once, the W-cycle twice, the F-cycle
+# by an F-cycle followed by a V-cycle.
+CYCLE_SCHEDULE = {"V": ("V",), "W": ("W", "W"), "F": ("F", "V")}
+
+
+def cycle(H, l, x, b, kind="V", fp32=False):
+    """One multigrid cycle of the given kind on level l for A_l x = b,
+    starting from x.
 
     Steps in the order of Algorithm 1: pre-smoothing, restriction of the
-    residual, recursive solve of the residual equation from a zero guess
-    (exact on the coarsest level), prolongation of the correction added to
-    x, post-smoothing.
+    residual, approximate solve of the coarse residual equation from a zero
+    guess, prolongation of the correction added to x, post-smoothing.  The
+    coarse equation is solved by the cycles of CYCLE_SCHEDULE[kind], each
+    starting from the previous one's result (Algorithm 1 is the V-cycle; the
+    paper mentions other cycle shapes, Sec. 5.3); directly above the
+    coarsest level it is solved exactly, once, for every kind.
     """
     if l == H.levels - 1:
         return coarse_solve(H, b, fp32)
@@ -146,11 +159,20 @@ def vcycle(H, l, x, b, fp32=False):
     x = smooth(H, l, x, b, pre=True, fp32=fp32)
     r = b - A @ x
     bc = P.T @ r
-    zero = np.zeros(bc.shape[0], dtype=bc.dtype)
-    e = vcycle(H, l + 1, zero, bc, fp32)
+    e = np.zeros(bc.shape[0], dtype=bc.dtype)
+    if l + 1 == H.levels - 1:
+        e = coarse_solve(H, bc, fp32)
+    else:
+        for sub in CYCLE_SCHEDULE[kind]:
+            e = cycle(H, l + 1, e, bc, sub, fp32)
     x = x + P @ e
     x = smooth(H, l, x, b, pre=False, fp32=fp32)
     return x
+
+
+def vcycle(H, l, x, b, fp32=False):
+    """One V-cycle (Algorithm 1) on level l for A_l x = b, starting from x."""
+    return cycle(H, l, x, b, "V", fp32)
 
 
 def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
@@ -167,7 +189,7 @@ def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
     if nb == 0.0:
         return np.zeros_like(b), 0, hist, "ok"
     for k in range(1, max_iter + 1):
-        u = vcycle(H, 0, u, b)
+        u = cycle(H, 0, u, b, H.cycle)
         rho = np.linalg.norm(b - A @ u) / nb
         hist.append(rho)
         if not np.isfinite(rho) or rho > diverge:
@@ -198,7 +220,7 @@ def solve_ir(H, b, tol, max_iter=100, diverge=1e3):
     for k in range(1, max_iter + 1):
         s = np.linalg.norm(r)
         r32 = (r / s).astype(np.float32)
-        c32 = vcycle(H, 0, np.zeros_like(r32), r32, fp32=True)
+        c32 = cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True)
         u = u + s * c32.astype(np.float64)
         r = b - A @ u
         rho = np.linalg.norm(r) / nb
@@ -211,19 +233,22 @@ def solve_ir(H, b, tol, max_iter=100, diverge=1e3):
 
 
 def precondition(H, r, fp32=False):
-    """The multigrid preconditioner: z = one V-cycle from a zero guess on
-    A z = r.  With fp32, the cycle runs in float32 on r / ||r|| and is
-    scaled back: z = ||r|| * float64(cycle32(float32(r / ||r||))).  The
-    cycle is symmetric (post-smoothing reverses the colour order of the
-    pre-smoothing, nu_pre = nu_post), so in exact arithmetic z = B r with
-    B symmetric positive definite."""
+    """The multigrid preconditioner: z = one cycle (H.cycle, V or W) from a
+    zero guess on A z = r.  With fp32, the cycle runs in float32 on
+    r / ||r|| and is scaled back: z = ||r|| * float64(cycle32(float32(r /
+    ||r||))).  The V- and W-cycles are symmetric (post-smoothing reverses
+    the colour order of the pre-smoothing, nu_pre = nu_post), so in exact
+    arithmetic z = B r with B symmetric positive definite; the F-cycle is
+    not and is refused."""
+    if H.cycle == "F":
+        raise ValueError("CG needs a symmetric cycle (V or W)")
     if not fp32:
-        return vcycle(H, 0, np.zeros_like(r), r)
+        return cycle(H, 0, np.zeros_like(r), r, H.cycle)
     s = np.linalg.norm(r)
     if s == 0.0:
         return np.zeros_like(r)
     r32 = (r / s).astype(np.float32)
-    return s * vcycle(H, 0, np.zeros_like(r32), r32, fp32=True).astype(np.float64)
+    return s * cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True).astype(np.float64)
 
 
 def solve_pcg(H, b, tol, max_iter=100, diverge=1e3, fp32=False, precond=None):

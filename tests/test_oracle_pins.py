@@ -471,3 +471,79 @@ def test_pcg_beats_the_stationary_cycle_and_fp32_cycle_matches():
     u32, k32, hist32, st32 = O.solve_pcg(H, b, 1e-8, fp32=True)
     assert st32 == "ok" and abs(k32 - k) <= 1
     assert np.linalg.norm(u32 - u) <= 1e-6 * np.linalg.norm(u)
+
+
+# ---- W- and F-cycles --------------------------------------------------------
+
+def _cycle_matrix_kind(H, l, kind):
+    """Error propagation matrix of one cycle of the given kind on level l,
+    built from the smoother, transfer and coarse matrices: the coarse
+    residual equation is solved by the schedule's cycles from zero, so the
+    correction is (I - M) A_c^-1 P^T r with M the product of their error
+    matrices (exact, M = 0, directly above the coarsest level)."""
+    A = H.A[l].toarray()
+    N = A.shape[0]
+    I = np.eye(N)
+    if l == H.levels - 1:
+        return np.zeros((N, N))
+    Dinv = np.diag(1.0 / np.diag(A))
+    if H.smoother == "jacobi":
+        S = I - H.omega * Dinv @ A
+        Spre = np.linalg.matrix_power(S, H.nu_pre)
+        Spost = np.linalg.matrix_power(S, H.nu_post)
+    else:
+        m0 = np.diag(H.mask[l].astype(float))
+        m1 = I - m0
+        S0 = I - m0 @ Dinv @ A
+        S1 = I - m1 @ Dinv @ A
+        Spre = np.linalg.matrix_power(S1 @ S0, H.nu_pre)
+        Spost = np.linalg.matrix_power(S0 @ S1, H.nu_post)
+    Ac = H.A[l + 1].toarray()
+    Nc = Ac.shape[0]
+    M = np.zeros((Nc, Nc))
+    if l + 1 < H.levels - 1:
+        M = np.eye(Nc)
+        for sub in {"V": ("V",), "W": ("W", "W"), "F": ("F", "V")}[kind]:
+            M = _cycle_matrix_kind(H, l + 1, sub) @ M
+    P = H.P[l].toarray()
+    return Spost @ (I - P @ (np.eye(Nc) - M) @ np.linalg.inv(Ac) @ P.T @ A) @ Spre
+
+
+@pytest.mark.parametrize("kind", ["V", "W", "F"])
+@pytest.mark.parametrize("dim,n,levels,smoother", [(2, 16, 3, "rbgs"), (2, 32, 4, "jacobi"),
+                                                   (3, 16, 4, "rbgs")])
+def test_cycle_kinds_equal_dense_cycle_operators(kind, dim, n, levels, smoother, rng):
+    H = O.build_hierarchy(dim, n, levels, smoother=smoother, cycle=kind)
+    N = (n - 1) ** dim
+    x = rng.uniform(-1, 1, N)
+    b = rng.uniform(-1, 1, N)
+    E = _cycle_matrix_kind(H, 0, kind)
+    ustar = np.linalg.solve(H.A[0].toarray(), b)
+    want = E @ x + (np.eye(N) - E) @ ustar
+    np.testing.assert_allclose(O.cycle(H, 0, x, b, kind), want, rtol=0, atol=1e-11)
+    if kind == "V":
+        np.testing.assert_allclose(E, _cycle_matrix(H, 0), rtol=0, atol=1e-12)
+
+
+def test_w_and_f_cycles_reduce_to_v_on_two_levels(rng):
+    H = O.build_hierarchy(3, 8, 2)
+    x = rng.uniform(-1, 1, 343)
+    b = rng.uniform(-1, 1, 343)
+    v = O.cycle(H, 0, x, b, "V")
+    for kind in ("W", "F"):
+        assert np.array_equal(O.cycle(H, 0, x, b, kind), v)
+
+
+def test_w_and_f_cycles_contract_at_least_as_fast():
+    dim, n = 3, 32
+    kappa = W.kappa_lognormal(dim, n, 0)
+    b = W.rhs_uniform(dim, n, 3)
+    ks = {}
+    for kind in ("V", "F", "W"):
+        H = O.build_hierarchy(dim, n, 5, kappa=kappa, cycle=kind)
+        u, k, hist, st = O.solve(H, b, 1e-8)
+        assert st == "ok"
+        ks[kind] = k
+    assert ks["W"] <= ks["F"] <= ks["V"], ks
+    with pytest.raises(ValueError):
+        O.solve_pcg(O.build_hierarchy(2, 8, 2, cycle="F"), np.ones(49), 1e-8)
