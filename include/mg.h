@@ -55,6 +55,12 @@ typedef enum {
 typedef enum { MG_OP_STENCIL = 0, MG_OP_CSR = 1 } mg_opfmt;
 typedef enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1 } mg_smoother;
 typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
+/* Cycle shape: how the coarse residual equation of a level is solved --
+ * by one coarse cycle (V, Algorithm 1), by two (W), or by an F-cycle
+ * followed by a V-cycle (F); directly above the coarsest level always
+ * exactly, once.  The paper mentions other cycle shapes besides the V-cycle
+ * (Sec. 5.3). */
+typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
 
 /* Flags (mg_options.flags). */
 #define MG_FLAG_NO_GRAPH 1   /* launch kernels one by one instead of replaying
@@ -75,7 +81,9 @@ typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
                                 preconditioning cycle runs in FP32 on
                                 r / ||r||.  Iterations and the history then
                                 count CG iterations, with the recursively
-                                updated residual.  Not for the server. */
+                                updated residual.  V- or W-cycles only (the
+                                F-cycle is not symmetric).  Not for the
+                                server. */
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -89,10 +97,11 @@ typedef struct {
   int precision;    /* mg_precision */
   int max_iter;     /* maximum number of cycles / refinement steps, >= 1 */
   int flags;        /* MG_FLAG_* */
+  int cycle;        /* mg_cycle */
 } mg_options;
 
 /* Fill *o with the defaults: 3D, n = 64, levels = 6, stencil, red-black,
- * V(2,2), omega = 2/3, FP64, max_iter = 100, flags = 0. */
+ * V(2,2), omega = 2/3, FP64, max_iter = 100, flags = 0, V-cycle. */
 void mg_options_default(mg_options* o);
 
 /* Device bytes that mg_setup(o, kappa_dev != NULL, ...) allocates for its

@@ -993,7 +993,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
   {
     T* xd = sm + D.lv[0].ox;
     T* bd = sm + D.lv[0].ob;
-    const bool cx = !I.flag;
+    const bool cx = !(I.flag & 1);
     for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n), [&](long p, int, int, int) {
       bd[p] = b0g[p];
       if (cx) xd[p] = x0g[p];
@@ -1041,10 +1041,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
       }
     }
   };
-  for (int l = 0; l + 1 < nl; ++l) {
+  // pre-smoothing of level l (from 0 when `zero`) and restriction of its
+  // residual to level l+1
+  auto down = [&](int l, bool zero) {
     const int n = D.lv[l].n;
     const DGeo g = dgeo(DIM, n);
-    bool zero = (l > 0) || I.flag;
     smooth(l, true, &zero);
     T* x = X(l);
     if (zero) {
@@ -1070,10 +1071,9 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
       resid_restrict(D.r0);  // device memory
     else
       resid_restrict(sm + D.lv[l].orr);
-  }
-  cholesky_solve_block<T>(DIM, D.lv[nl - 1].n, D.L, D.m, sm + D.lv[nl - 1].ob, X(nl - 1),
-                          reinterpret_cast<double*>(tail_lds + D.oy));
-  for (int l = nl - 2; l >= 0; --l) {
+  };
+  // prolongation of level l+1's correction into level l, post-smoothing
+  auto up = [&](int l) {
     const int n = D.lv[l].n;
     const DGeo gc = dgeo(DIM, D.lv[l + 1].n);
     T* x = X(l);
@@ -1084,6 +1084,44 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
     __syncthreads();
     bool zero = false;
     smooth(l, false, &zero);
+  };
+  auto coarse = [&]() {
+    cholesky_solve_block<T>(DIM, D.lv[nl - 1].n, D.L, D.m, sm + D.lv[nl - 1].ob, X(nl - 1),
+                            reinterpret_cast<double*>(tail_lds + D.oy));
+    __syncthreads();
+  };
+  // The cycle over the tail levels, iteratively: each level visited by a
+  // cycle of some kind (V, W or F) runs that kind's coarse cycles (V: one V;
+  // W: two W; F: an F then a V; one exact solve directly above the
+  // coarsest level) before its post-smoothing.  Level l's kind and the
+  // number of its coarse cycles started are kept in 2-bit fields of `kinds`
+  // and `starts`; every thread runs the same control flow.
+  if (nl == 1) {
+    coarse();
+  } else {
+    unsigned kinds = (unsigned)(I.flag >> 1) & 3u, starts = 0;
+    auto kind_of = [&](int l) { return (int)((kinds >> (2 * l)) & 3u); };
+    auto started = [&](int l) { return (int)((starts >> (2 * l)) & 3u); };
+    int l = 0;
+    down(0, (I.flag & 1) != 0);
+    for (;;) {
+      const int kd = kind_of(l);
+      const int nsub = kd == CYC_V ? 1 : 2;
+      if (l + 1 < nl - 1 && started(l) < nsub) {
+        const int i = started(l);
+        const int sub = kd == CYC_W ? CYC_W : (kd == CYC_F && i == 0 ? CYC_F : CYC_V);
+        starts += 1u << (2 * l);
+        ++l;
+        kinds = (kinds & ~(3u << (2 * l))) | ((unsigned)sub << (2 * l));
+        starts &= ~(3u << (2 * l));
+        down(l, i == 0);
+        continue;
+      }
+      if (l + 1 == nl - 1) coarse();
+      up(l);
+      if (l == 0) break;
+      --l;
+    }
   }
   const T* src = X(0);
   for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n),

@@ -103,6 +103,11 @@ struct CsrOp {
   long sy;      // node stride in y
 };
 
+// Cycle kinds (the values of mg_cycle): how a level's coarse residual
+// equation is solved -- one V-cycle, two W-cycles, or an F-cycle then a
+// V-cycle.
+enum CycleKind { CYC_V = 0, CYC_W = 1, CYC_F = 2 };
+
 // Smoothing step kinds (mg_apply_smooth "step" 0..2).
 enum SmoothKind { SM_JACOBI = 0, SM_RB0 = 1, SM_RB1 = 2 };
 

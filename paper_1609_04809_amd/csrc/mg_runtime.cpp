@@ -96,7 +96,8 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
   if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG)) { why = "unknown flags"; return false; }
-  if ((o->flags & MG_FLAG_PCG) && o->nu_pre != o->nu_post) { why = "CG needs a symmetric cycle (nu_pre == nu_post)"; return false; }
+  if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) { why = "cycle must be V, W or F"; return false; }
+  if ((o->flags & MG_FLAG_PCG) && (o->nu_pre != o->nu_post || o->cycle == MG_CYCLE_F)) { why = "CG needs a symmetric cycle (V or W, nu_pre == nu_post)"; return false; }
   const long nc = o->n >> (o->levels - 1);
   const long m = ipow(nc - 1, o->dim);
   if (m > kCoarseMaxUnknowns) {
@@ -556,11 +557,23 @@ void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spa
   }
 }
 
-// One V-cycle (Algorithm 1) for A_0 x = b starting from x0 (or from 0 when
-// x0_zero); the result is written back to x0.  Levels >= 1 and the spare
-// level-0 buffer are internal.  Levels from c->tail0 on run in one
-// workgroup per request.  head_done: the first level-0 pre-smoothing step
-// has already been applied to x0, its result is in spare0.
+// Coarse-level cycles that solve a level's coarse residual equation, per
+// cycle kind (mg_cycle): V one V-cycle, W two W-cycles, F an F-cycle then a
+// V-cycle; directly above the coarsest level one exact solve.
+static_assert(MG_CYCLE_V == CYC_V && MG_CYCLE_W == CYC_W && MG_CYCLE_F == CYC_F,
+              "cycle kinds of the tail kernel");
+inline int cycle_subs(int kind) { return kind == MG_CYCLE_V ? 1 : 2; }
+inline int cycle_sub(int kind, int i) {
+  return kind == MG_CYCLE_W ? MG_CYCLE_W : (kind == MG_CYCLE_F && i == 0 ? MG_CYCLE_F : MG_CYCLE_V);
+}
+
+// One cycle of the context's kind (Algorithm 1 for the V-cycle) for
+// A_0 x = b starting from x0 (or from 0 when x0_zero); the result is
+// written back to x0.  Levels >= 1 and the spare level-0 buffer are
+// internal.  Levels from c->tail0 on run in one workgroup per request (the
+// tail kernel follows the same schedule).  head_done: the first level-0
+// pre-smoothing step has already been applied to x0, its result is in
+// spare0.
 template <typename T>
 void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero,
                  bool head_done = false) {
@@ -577,40 +590,48 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
   }
   const int lt = c->tail0 >= 0 ? c->tail0 : L - 1;  // first level not cycled level by level
   if (head_done) std::swap(cur[0], spare[0]);
-  for (int l = 0; l < lt; ++l) {
-    bool zero = (l > 0) || x0_zero;
-    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &zero, bb[l], l == 0 && head_done);
-    if (zero) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
+  // one visit of level l by a cycle of `kind`, its iterate starting at 0
+  // when `zero`
+  std::function<void(int, int, bool)> visit = [&](int l, int kind, bool zero) {
+    if (l == lt) {
+      if (c->tail0 >= 0) {
+        OpRec o = base_op<T>(c, OC_TAIL, lt);
+        o.count = c->tail_lds[Bufs<T>::prec];
+        o.item.a = Bufs<T>::tail(c);
+        o.item.b = bb[lt];
+        o.item.c = cur[lt];
+        o.item.flag = (zero ? 1 : 0) | (kind << 1);
+        sink(o);
+      } else {
+        OpRec o = base_op<T>(c, OC_COARSE, L - 1);
+        o.item.b = bb[L - 1];
+        o.item.c = cur[L - 1];
+        o.item.L = c->Lc;
+        sink(o);
+      }
+      return;
+    }
+    bool z = zero;
+    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done);
+    if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, l);
     o.item.a = Bufs<T>::r(c->lv[l]);
     o.item.c = Bufs<T>::b(c->lv[l + 1]);
     sink(o);
-  }
-  if (c->tail0 >= 0) {
-    OpRec o = base_op<T>(c, OC_TAIL, lt);
-    o.count = c->tail_lds[Bufs<T>::prec];
-    o.item.a = Bufs<T>::tail(c);
-    o.item.b = bb[lt];
-    o.item.c = cur[lt];
-    // a coarse level's correction starts from 0; level 0 from x0 unless x0_zero
-    o.item.flag = (lt > 0 || x0_zero) ? 1 : 0;
-    sink(o);
-  } else {
-    OpRec o = base_op<T>(c, OC_COARSE, L - 1);
-    o.item.b = bb[L - 1];
-    o.item.c = cur[L - 1];
-    o.item.L = c->Lc;
-    sink(o);
-  }
-  for (int l = lt - 1; l >= 0; --l) {
-    OpRec o = base_op<T>(c, OC_PROLONG, l);
-    o.item.a = cur[l + 1];
-    o.item.c = cur[l];
-    sink(o);
-    bool zero = false;
-    smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &zero, bb[l]);
-  }
+    if (l + 1 == L - 1) {
+      visit(l + 1, kind, true);
+    } else {
+      for (int i = 0; i < cycle_subs(kind); ++i) visit(l + 1, cycle_sub(kind, i), i == 0);
+    }
+    OpRec pr = base_op<T>(c, OC_PROLONG, l);
+    pr.item.a = cur[l + 1];
+    pr.item.c = cur[l];
+    sink(pr);
+    bool nz = false;
+    smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l]);
+  };
+  visit(0, c->o.cycle, x0_zero);
   if (cur[0] != x0) {
     OpRec o = base_op<T>(c, OC_COPY, 0);
     o.count = c->lv[0].g.nodes;
@@ -1000,6 +1021,7 @@ void mg_options_default(mg_options* o) {
   o->precision = MG_PREC_FP64;
   o->max_iter = 100;
   o->flags = 0;
+  o->cycle = MG_CYCLE_V;
 }
 
 size_t mg_footprint_bytes(const mg_options* o) {

@@ -23,6 +23,7 @@ STATUS_NAMES = {0: "ok", 1: "arg", 2: "nomem", 3: "hip", 4: "not_spd",
 OP = {"stencil": 0, "csr": 1}
 SMOOTHER = {"jacobi": 0, "rbgs": 1}
 PREC = {"fp64": 0, "fp32_ir": 1}
+CYCLE = {"V": 0, "W": 1, "F": 2}
 FLAG_NO_GRAPH = 1
 FLAG_NO_TAIL = 2
 FLAG_NO_FUSE = 4
@@ -45,7 +46,7 @@ class Options(ctypes.Structure):
                 ("op", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
-                ("max_iter", ctypes.c_int), ("flags", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("flags", ctypes.c_int), ("cycle", ctypes.c_int)]
 
 
 _VP = ctypes.c_void_p
@@ -137,13 +138,14 @@ def _ptr(t):
 
 
 def make_options(dim, n, levels, op="stencil", smoother="rbgs", nu_pre=2, nu_post=2,
-                 omega=2.0 / 3.0, precision="fp64", max_iter=100, flags=0):
+                 omega=2.0 / 3.0, precision="fp64", max_iter=100, flags=0, cycle="V"):
     o = Options()
     lib().mg_options_default(ctypes.byref(o))
     o.dim, o.n, o.levels = dim, n, levels
     o.op, o.smoother = OP[op], SMOOTHER[smoother]
     o.nu_pre, o.nu_post, o.omega = nu_pre, nu_post, omega
     o.precision, o.max_iter, o.flags = PREC[precision], max_iter, flags
+    o.cycle = CYCLE[cycle] if isinstance(cycle, str) else cycle
     return o
 
 

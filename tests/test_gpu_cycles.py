@@ -1,0 +1,98 @@
+"""W- and F-cycles (mg_options.cycle) against the oracle's cycle().
+
+Bar as for the V-cycle: FP64 cycle counts +-1, histories within 1e-6
+relative (+1e-14 absolute), and after the same number of cycles
+||u_gpu - u_oracle|| <= 1e-8 ||u_oracle||.  The one-workgroup tail runs the
+same schedule as the level-by-level launches: bitwise equal solves with and
+without it (stencil operators).
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1609_04809_amd import workloads as W
+from tests.gpu_util import dev_full, host_full, host_int, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dim, n, levels, smoother, op, kappa
+    (2, 64, 5, "jacobi", "stencil", False),   # whole cycle inside one workgroup
+    (2, 128, 6, "rbgs", "stencil", True),
+    (3, 32, 5, "rbgs", "stencil", False),
+    (3, 32, 5, "rbgs", "csr", False),
+    (3, 48, 5, "rbgs", "stencil", True),
+    (3, 64, 6, "rbgs", "stencil", True),
+]
+
+
+def _ids(c):
+    return f"{c[0]}d-n{c[1]}-{c[3]}-{c[4]}-{'kap' if c[5] else 'poi'}"
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("case", CASES, ids=_ids)
+def test_fp64_w_f_cycles_match_oracle(case, kind):
+    torch_cuda()
+    from paper_1609_04809_amd.mg import Solver
+    dim, n, levels, sm, op, kap = case
+    kappa = W.kappa_lognormal(dim, n, 17) if kap else None
+    b = W.rhs_uniform(dim, n, 6)
+    tol = 1e-8
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=sm, cycle=kind)
+    u_or, k_or, hist_or, st = O.solve(H, b, tol)
+    assert st == "ok"
+    with Solver(dim, n, levels, kappa=kappa, op=op, smoother=sm, cycle=kind) as S:
+        u, k, hist, st = S.solve(dev_full(dim, n, b), tol)
+    assert st == "ok" and abs(k - k_or) <= 1, (k, k_or)
+    kk = min(k, k_or)
+    np.testing.assert_allclose(hist[1:kk + 1], hist_or[1:kk + 1], rtol=1e-6, atol=1e-14)
+    if k != k_or:
+        u_or, _, _, _ = O.solve(H, b, 1e-300, max_iter=k)
+    ug = host_int(dim, n, u)
+    assert np.linalg.norm(ug - u_or) <= 1e-8 * np.linalg.norm(u_or)
+
+
+@pytest.mark.parametrize("kind", ["W", "F"])
+@pytest.mark.parametrize("dim,n,levels,kap,prec", [
+    (2, 64, 5, False, "fp64"),
+    (3, 64, 6, True, "fp64"),
+    (3, 32, 5, True, "fp32_ir"),
+    (2, 256, 7, False, "fp32_ir"),
+])
+def test_w_f_tail_and_grid_levels_agree_bitwise(kind, dim, n, levels, kap, prec):
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_TAIL, Solver
+    kappa = W.kappa_lognormal(dim, n, 4) if kap else None
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 8))
+    outs = []
+    for flags in (0, FLAG_NO_TAIL):
+        with Solver(dim, n, levels, kappa=kappa, precision=prec, cycle=kind, flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-8)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_w_cycle_ir_and_cg_match_oracle():
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_PCG, Solver
+    dim, n, levels = 3, 48, 5
+    kappa = W.kappa_lognormal(dim, n, 5)
+    b = W.rhs_uniform(dim, n, 2)
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, cycle="W", fp32=True)
+    _, k_ir, _, _ = O.solve_ir(H, b, 1e-8)
+    u_cg, k_cg, hist_cg, _ = O.solve_pcg(H, b, 1e-8)
+    bd = dev_full(dim, n, b)
+    with Solver(dim, n, levels, kappa=kappa, cycle="W", precision="fp32_ir") as S:
+        u, k, hist, st = S.solve(bd, 1e-8)
+    assert st == "ok" and abs(k - k_ir) <= 1
+    ug = host_int(dim, n, u)
+    assert np.linalg.norm(b - H.A[0] @ ug) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-5)
+    with Solver(dim, n, levels, kappa=kappa, cycle="W", flags=FLAG_PCG) as S:
+        u, k, hist, st = S.solve(bd, 1e-8)
+    assert st == "ok" and abs(k - k_cg) <= 1
+    kk = min(k, k_cg)
+    np.testing.assert_allclose(hist[1:kk + 1], hist_cg[1:kk + 1], rtol=1e-6, atol=1e-14)
