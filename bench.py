@@ -162,9 +162,10 @@ def roofline_stencil(S, w, bd, s):
             "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": int(per)}
 
 
-def run_workload(name, steps, warmup, with_roofline=False, pcg=False):
+def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V"):
     """Time `steps` solves of a workload: the plain cycle iteration, or with
-    pcg conjugate gradients preconditioned by one cycle per iteration."""
+    pcg conjugate gradients preconditioned by one cycle per iteration; cycle
+    V (the workload's), W or F."""
     import torch
     from paper_1609_04809_amd import workloads as W
     from paper_1609_04809_amd.mg import FLAG_PCG, Solver
@@ -173,16 +174,17 @@ def run_workload(name, steps, warmup, with_roofline=False, pcg=False):
     t0 = time.perf_counter()
     S = Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=w.smoother,
                nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision=w.precision,
-               flags=FLAG_PCG if pcg else 0)
+               flags=FLAG_PCG if pcg else 0, cycle=cycle)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     t, k, hist, u = time_solves(S, bd, w.tol, steps, warmup)
     res = {"workload": name, "dofs": w.dofs, "unknowns": w.unknowns,
            "MDOF_per_s": round(w.dofs / t / 1e6, 1), "ms_per_solve": round(t * 1e3, 3),
            "cycles": k, "final_rel_residual": hist[-1], "setup_s": round(setup_s, 3),
-           "precision": w.precision, "op": w.op, "method": "pcg" if pcg else "cycle"}
+           "precision": w.precision, "op": w.op, "method": "pcg" if pcg else "cycle",
+           "cycle": cycle}
     roof = None
-    if pcg:
+    if pcg or cycle != "V":
         pass
     elif w.op == "csr":
         if with_roofline:
@@ -295,6 +297,13 @@ def main():
             log(f"[bench] {other} (pcg): {r['MDOF_per_s']} MDOF/s, {r['cycles']} iterations, "
                 f"{r['ms_per_solve']} ms/solve")
             extra.append(r)
+        # other cycle shapes on the CSR and the variable-coefficient workloads
+        for other in ("poisson3d_128_csr_rbgs", "kappa3d_192_rbgs_ir"):
+            for kind in ("W", "F"):
+                r, _, _ = run_workload(other, max(3, args.steps // 4), 1, cycle=kind)
+                log(f"[bench] {other} ({kind}-cycle): {r['MDOF_per_s']} MDOF/s, "
+                    f"{r['cycles']} cycles, {r['ms_per_solve']} ms/solve")
+                extra.append(r)
     serving = None
     if not args.no_serve:
         from paper_1609_04809_amd import serve_load
