@@ -72,6 +72,14 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 each cycle in a launch of its own instead of
                                 in one pass with the next cycle's first
                                 pre-smoothing step (same results bitwise) */
+#define MG_FLAG_PAIR 16      /* on 3D stencil levels with n >= 32, launch
+                                consecutive red-black half-sweeps as one pass
+                                each (x, b and the result cross HBM once per
+                                pair; a halo of width 2 is recomputed in
+                                LDS).  Same results bitwise; slower than
+                                separate half-sweeps on MI355X, whose
+                                half-sweep is HBM-bound while the pair is
+                                bound by LDS traffic and occupancy. */
 #define MG_FLAG_PCG 8        /* mg_solve runs conjugate gradients
                                 preconditioned by one V-cycle per iteration
                                 (multigrid as a Krylov preconditioner,
@@ -221,7 +229,8 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  * such launches and their summed duration in milliseconds.
  *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
  *              1 = residual (with or without norm), 2 = restriction,
- *              3 = prolongation + add
+ *              3 = prolongation + add, 4 = pair of red-black half-sweeps
+ *              in one pass
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

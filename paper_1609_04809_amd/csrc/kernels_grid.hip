@@ -719,6 +719,244 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 }
 
 // ---------------------------------------------------------------------------
+// Two red-black half-sweeps in one pass on the 3D levels with n >= 32:
+// colour CA, then colour 1-CA, bitwise what two k_sweep3 half-sweeps give.
+// A block owns the same 128 x 4 tile as k_sweep3 and marches its planes in
+// z.  At step s it stages plane s of x with a halo of 2 in x and y (LDS
+// slot s % 3), updates colour CA on plane s-1 over the tile and a ring of
+// width 1 around it (the ring is recomputed by the neighbouring blocks as
+// well) into the x' planes (slot (s-1) % 3, colour 1-CA copied), and then
+// updates colour 1-CA on plane s-2 of the tile from three x' planes and
+// writes both colours of that plane.  x, b and the result cross HBM once
+// for the two half-sweeps instead of twice.  Cell layers of kappa are
+// staged with the same halo (4 slots).  ZERO: x = 0 (not read).
+// ---------------------------------------------------------------------------
+constexpr int P2_XX = SW_TX + 4, P2_XY = SW_TY + 4;  // staged x plane, halo 2
+constexpr int P2_YX = SW_TX + 2, P2_YY = SW_TY + 2;  // x' plane, halo 1
+constexpr int P2_KX = SW_TX + 3, P2_KY = SW_TY + 3;  // cell layer, cells from i0-2, j0-2
+
+template <typename T, int KIND, int CA, bool ZERO>
+__global__ __launch_bounds__(256) void k_sweep3_pair(Geo g, StencilParams<T> op, int kz, int nzc,
+                                                     int remap, Batch B) {
+  constexpr bool KAP = KIND == OP_KAPPA;
+  constexpr int CB = 1 - CA;
+  __shared__ T sxp[ZERO ? 1 : 3][P2_XY][P2_XX];
+  __shared__ T syp[3][P2_YY][P2_YX];
+  __shared__ T skp[KAP ? 4 : 1][P2_KY][P2_KX];
+  const int n = g.n, m = n - 1;
+  const long sy = g.sy, sz = g.sz;
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if (remap) {
+    const int gxy = gridDim.x * gridDim.y;
+    const int nb = gxy * gridDim.z;
+    const int L = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+    bx = L % gridDim.x;
+    by = (L / gridDim.x) % gridDim.y;
+    bz = L / gxy;
+  }
+  const int item = bz / nzc, zc = bz % nzc;
+  const Item& I = B.it[item];
+  const T* __restrict__ x = (const T*)I.a;
+  const T* __restrict__ b = (const T*)I.b;
+  T* __restrict__ out = (T*)I.c;
+  const T* __restrict__ kap = (const T*)I.kappa;
+  const int i0 = 1 + bx * SW_TX, j0 = 1 + by * SW_TY, k0 = 1 + zc * kz;
+  const int k1 = min(k0 + kz - 1, m);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int i = i0 + 2 * tx, j = j0 + ty;
+  const bool row_ok = j <= m;
+  const bool ok0 = row_ok && i <= m, ok1 = row_ok && i + 1 <= m;
+  auto cl = [](int v, int hi) { return min(max(v, 0), hi); };
+
+  // staging of x planes (halo 2) and cell layers: every load at a clamped
+  // address and behind no branch (positions off the grid are only seen by
+  // stencils of nodes that are not updated)
+  constexpr int NXP = (P2_XX * P2_XY + 255) / 256;
+  constexpr int NKP = (P2_KX * P2_KY + 255) / 256;
+  int xoff[NXP];
+  T xpf[NXP];
+#pragma unroll
+  for (int q = 0; q < NXP; ++q) {
+    const int e = tid + 256 * q;
+    const int r = e / P2_XX, c = e - r * P2_XX;
+    xoff[q] = cl(i0 - 2 + c, n) + cl(j0 - 2 + r, n) * (int)sy;
+  }
+  auto prefetch_x = [&](int z) {
+    const T* __restrict__ xz = x + (long)cl(z, n) * sz;
+#pragma unroll
+    for (int q = 0; q < NXP; ++q) xpf[q] = xz[xoff[q]];
+  };
+  auto commit_x = [&](int slot) {
+    T* dst = &sxp[ZERO ? 0 : slot][0][0];
+#pragma unroll
+    for (int q = 0; q < NXP; ++q) {
+      const int e = tid + 256 * q;
+      if (e < P2_XX * P2_XY) dst[e] = xpf[q];
+    }
+  };
+  int koff[NKP];
+  T kpf[NKP];
+  if (KAP) {
+#pragma unroll
+    for (int q = 0; q < NKP; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e / P2_KX, c = e - r * P2_KX;
+      koff[q] = cl(i0 - 2 + c, n - 1) + n * cl(j0 - 2 + r, n - 1);
+    }
+  }
+  auto prefetch_k = [&](int cz) {
+    const T* __restrict__ kz_ = kap + (long)n * n * cl(cz, n - 1);
+#pragma unroll
+    for (int q = 0; q < NKP; ++q) kpf[q] = kz_[koff[q]];
+  };
+  auto commit_k = [&](int slot) {
+    T* dst = &skp[KAP ? slot : 0][0][0];
+#pragma unroll
+    for (int q = 0; q < NKP; ++q) {
+      const int e = tid + 256 * q;
+      if (e < P2_KX * P2_KY) dst[e] = kpf[q];
+    }
+  };
+  auto xs = [](int z) { return (z + 3) % 3; };  // slot of x / x' plane z (z >= -1)
+  auto ks = [](int z) { return (z + 4) & 3; };  // slot of cell layer z (z >= -2)
+
+  // right-hand sides: of the ring+tile positions of the plane updated next
+  // (colour CA) and of this thread's two unknowns (colour 1-CA)
+  constexpr int NYP = (P2_YX * P2_YY + 255) / 256;
+  int boff[NYP];
+#pragma unroll
+  for (int q = 0; q < NYP; ++q) {
+    const int e = tid + 256 * q;
+    const int r = e / P2_YX, c = e - r * P2_YX;
+    boff[q] = cl(i0 - 1 + c, n) + cl(j0 - 1 + r, n) * (int)sy;
+  }
+  T bA[NYP], bB[2];
+  auto prefetch_bA = [&](int z) {
+    const T* __restrict__ bz_ = b + (long)cl(z, n) * sz;
+#pragma unroll
+    for (int q = 0; q < NYP; ++q) bA[q] = bz_[boff[q]];
+  };
+  const long pb0 = min(i, n - 1) + min(j, n) * sy;
+  auto prefetch_bB = [&](int z) {
+    const long p = pb0 + (long)cl(z, n) * sz;
+    bB[0] = b[p];
+    bB[1] = b[p + 1];
+  };
+
+  // colour CA on plane q over the ring and the tile -> x' plane q
+  auto update_a = [&](int q, const T (&bv)[NYP]) {
+    T* __restrict__ yd = &syp[xs(q)][0][0];
+#pragma unroll
+    for (int t = 0; t < NYP; ++t) {
+      const int e = tid + 256 * t;
+      if (e >= P2_YX * P2_YY) continue;
+      const int r = e / P2_YX, c = e - r * P2_YX;
+      const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+      const bool unk = gi >= 1 && gi <= m && gj >= 1 && gj <= m && q >= 1 && q <= m;
+      const bool upd = unk && ((gi + gj + q) & 1) == CA;
+      T val;
+      if (!upd) {
+        val = ZERO ? T(0) : sxp[ZERO ? 0 : xs(q)][r + 1][c + 1];
+      } else {
+        T kk[2][2][2];
+        if (KAP) {
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+              for (int aa = 0; aa < 2; ++aa) kk[cc][bb][aa] = skp[ks(q - 1 + cc)][r + bb][c + aa];
+        }
+        if (ZERO) {
+          const T dg = KAP ? kappa_diag3(op, kk) : op.wc;
+          val = bv[t] / dg;
+        } else {
+          T v[3][3][3];
+#pragma unroll
+          for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+              for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = sxp[xs(q - 1 + dz)][r + dy][c + dx];
+          T ax, dg;
+          if (KAP) {
+            ax = stencil3_kappa(op, kk, v, dg);
+          } else {
+            ax = stencil3_const(op, v);
+            dg = op.wc;
+          }
+          val = v[1][1][1] + (bv[t] - ax) / dg;
+        }
+      }
+      yd[e] = val;
+    }
+  };
+  // colour 1-CA on plane q of the tile from the x' planes; both colours out
+  auto update_b = [&](int q, const T (&bv)[2]) {
+    const long p = i + j * sy + (long)q * sz;
+    auto one = [&](auto ubc) {
+      constexpr int ub = decltype(ubc)::value;  // updated column
+      constexpr int ua = 1 - ub;
+      if (ua == 0 ? ok0 : ok1) out[p + ua] = syp[xs(q)][ty + 1][2 * tx + ua + 1];
+      if (!(ub == 0 ? ok0 : ok1)) return;
+      T v[3][3][3];
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) v[dz][dy][dx] = syp[xs(q - 1 + dz)][ty + dy][2 * tx + ub + dx];
+      T ax, dg;
+      if (KAP) {
+        T kk[2][2][2];
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int aa = 0; aa < 2; ++aa)
+              kk[cc][bb][aa] = skp[ks(q - 1 + cc)][ty + 1 + bb][2 * tx + ub + 1 + aa];
+        ax = stencil3_kappa(op, kk, v, dg);
+      } else {
+        ax = stencil3_const(op, v);
+        dg = op.wc;
+      }
+      out[p + ub] = v[1][1][1] + (bv[ub] - ax) / dg;
+    };
+    if (((i + j + q) & 1) == CB)  // the same for a whole wavefront (row j)
+      one(std::integral_constant<int, 0>{});
+    else
+      one(std::integral_constant<int, 1>{});
+  };
+
+  // each load is issued one step before its use
+  if (!ZERO) prefetch_x(k0 - 2);
+  if (KAP) prefetch_k(k0 - 3);
+  prefetch_bA(k0 - 3);
+  prefetch_bB(k0 - 4);
+  for (int s = k0 - 2; s <= k1 + 2; ++s) {
+    if (!ZERO) {
+      commit_x(xs(s));  // plane s
+      prefetch_x(s + 1);
+    }
+    if (KAP) {
+      commit_k(ks(s - 1));  // cell layer s-1
+      prefetch_k(s);
+    }
+    T bAc[NYP];
+#pragma unroll
+    for (int q = 0; q < NYP; ++q) bAc[q] = bA[q];  // b of plane s-1
+    const T bBs[2] = {bB[0], bB[1]};                // b of plane s-2
+    prefetch_bA(s);
+    prefetch_bB(s - 1);
+    __syncthreads();
+    if (s >= k0) update_a(s - 1, bAc);
+    __syncthreads();
+    if (s >= k0 + 2) update_b(s - 2, bBs);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // batched node kernels
 // ---------------------------------------------------------------------------
 template <typename T>
@@ -1317,6 +1555,33 @@ void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero
 #undef L_SM
 }
 
+bool pair_sweeps(const Geo& g) { return use_sweep3(g); }
+
+template <typename T>
+void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
+                        const Batch& B, hipStream_t s) {
+  int kz, nzc;
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  const dim3 bl(64, SW_TY);
+  const int rm = sweep3_remap();
+#define L_PAIR(K, CA, Z) \
+  hipLaunchKernelGGL((k_sweep3_pair<T, K, CA, Z>), gr, bl, 0, s, g, op, kz, nzc, rm, B)
+#define L_PAIR_K(K)                                  \
+  do {                                               \
+    if (first == SM_RB0) {                           \
+      if (zero) L_PAIR(K, 0, true); else L_PAIR(K, 0, false); \
+    } else {                                         \
+      if (zero) L_PAIR(K, 1, true); else L_PAIR(K, 1, false); \
+    }                                                \
+  } while (0)
+  if (op.kind == OP_KAPPA)
+    L_PAIR_K(OP_KAPPA);
+  else
+    L_PAIR_K(OP_CONST);
+#undef L_PAIR_K
+#undef L_PAIR
+}
+
 template <typename T>
 void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
                  hipStream_t s) {
@@ -1453,6 +1718,8 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_copy<T>(const T*, T*, long, hipStream_t);                            \
   template void launch_residual<T>(const Geo&, const StencilParams<T>&, bool, const Batch&, \
                                    hipStream_t);                                            \
+  template void launch_smooth_pair<T>(const Geo&, const StencilParams<T>&, int, bool,      \
+                                      const Batch&, hipStream_t);                           \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
                                  const Batch&, hipStream_t);                                \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \

@@ -181,6 +181,13 @@ void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const 
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s);
+// Two red-black half-sweeps in one pass, colour `first` (SM_RB0 / SM_RB1)
+// then the other; bitwise the result of two launch_smooth calls.  Only on
+// levels where pair_sweeps(g):  a = x_in (nullptr: x = 0), b = b, c = x_out.
+bool pair_sweeps(const Geo& g);
+template <typename T>
+void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
+                        const Batch& B, hipStream_t s);
 // b_c = P^T r:  a = r (fine), c = b_c (coarse).
 template <typename T>
 void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s);

@@ -95,7 +95,7 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
-  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG)) { why = "unknown flags"; return false; }
+  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG | MG_FLAG_PAIR)) { why = "unknown flags"; return false; }
   if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) { why = "cycle must be V, W or F"; return false; }
   if ((o->flags & MG_FLAG_PCG) && (o->nu_pre != o->nu_post || o->cycle == MG_CYCLE_F)) { why = "CG needs a symmetric cycle (V or W, nu_pre == nu_post)"; return false; }
   const long nc = o->n >> (o->levels - 1);
@@ -533,27 +533,40 @@ void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
 // Smoothing on level l from *cur (or from 0 if *zero), ping-ponging between
 // *cur and *spare; on return *cur holds the smoothed iterate.  With
 // `skip`, the first step is not emitted: it has already been done, from
-// *spare into *cur.
+// *spare into *cur.  With MG_FLAG_PAIR, consecutive red-black half-sweeps
+// on the large 3D stencil levels go out as pairs (one pass each, bitwise
+// the same result).
 template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
                   const T* b, bool skip = false) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
-  auto step = [&](int kind) {
-    if (skip) {
-      skip = false;
-      return;
-    }
-    emit_smooth<T>(c, sink, l, kind, *zero ? nullptr : *cur, b, *spare);
-    std::swap(*cur, *spare);
-    *zero = false;
-  };
+  std::vector<int> steps;
   for (int it = 0; it < nu; ++it) {
     if (c->o.smoother == MG_SMOOTH_JACOBI) {
-      step(SM_JACOBI);
+      steps.push_back(SM_JACOBI);
     } else {
-      step(pre ? SM_RB0 : SM_RB1);
-      step(pre ? SM_RB1 : SM_RB0);
+      steps.push_back(pre ? SM_RB0 : SM_RB1);
+      steps.push_back(pre ? SM_RB1 : SM_RB0);
     }
+  }
+  if (skip && !steps.empty()) steps.erase(steps.begin());
+  const bool pairs = !c->csr && c->o.smoother == MG_SMOOTH_RBGS &&
+                     pair_sweeps(c->lv[l].g) && (c->o.flags & MG_FLAG_PAIR);
+  for (size_t q = 0; q < steps.size();) {
+    if (pairs && q + 1 < steps.size()) {
+      OpRec o = base_op<T>(c, OC_SMOOTH2, l);
+      o.sub = steps[q] | ((*zero ? 1 : 0) << 4);
+      o.item.a = *zero ? nullptr : *cur;
+      o.item.b = b;
+      o.item.c = *spare;
+      sink(o);
+      q += 2;
+    } else {
+      emit_smooth<T>(c, sink, l, steps[q], *zero ? nullptr : *cur, b, *spare);
+      q += 1;
+    }
+    std::swap(*cur, *spare);
+    *zero = false;
   }
 }
 
@@ -776,12 +789,13 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
 }
 
 // profiling hooks: bracket level-0 launches of the selected kernel class
-enum ProfKind { PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3 };
+enum ProfKind { PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4 };
 
 int prof_class(int code) {
   switch (code) {
     case OC_SMOOTH:
     case OC_CSR_SMOOTH: return PK_SMOOTH;
+    case OC_SMOOTH2: return PK_SMOOTH2;
     case OC_RESID:
     case OC_CSR_RESID:
     case OC_HEAD:
@@ -920,6 +934,9 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
                              (T*)it.c, it.partials, s);
       break;
     case OC_HEAD: launch_head<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
+    case OC_SMOOTH2:
+      launch_smooth_pair<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, B, s);
+      break;
     case OC_APPLY_DOT: launch_apply_dot<T>(o.g, params_of<T>(o), B, s); break;
     case OC_CSR_APPLY_DOT:
       launch_csr_apply_dot<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (T*)it.c,
@@ -1332,7 +1349,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
 
 mg_status mg_profile_enable(mg_ctx* c, int kernel_id, int enable) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > 3) return fail(MG_E_ARG, "kernel_id must be 0..3");
+  if (kernel_id < 0 || kernel_id > 4) return fail(MG_E_ARG, "kernel_id must be 0..4");
   c->prof_kernel = kernel_id;
   c->prof_on = enable != 0;
   c->prof_launches = 0;

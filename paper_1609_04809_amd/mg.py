@@ -28,11 +28,12 @@ FLAG_NO_GRAPH = 1
 FLAG_NO_TAIL = 2
 FLAG_NO_FUSE = 4
 FLAG_PCG = 8
+FLAG_PAIR = 16
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
 # mg_profile_enable kernel ids
-PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG = 0, 1, 2, 3
+PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG, PROF_PAIR = 0, 1, 2, 3, 4
 
 
 class MgError(RuntimeError):

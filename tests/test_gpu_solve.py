@@ -246,3 +246,29 @@ def test_edge_cases():
     with pytest.raises(MgError) as e:
         Solver(3, 16, 4, kappa=kap)
     assert e.value.status == 7
+
+
+@pytest.mark.parametrize("dim,n,levels,kap,prec,nu", [
+    (3, 64, 6, False, "fp64", (2, 2)),
+    (3, 64, 6, True, "fp64", (2, 2)),
+    (3, 32, 5, False, "fp32_ir", (2, 2)),
+    (3, 64, 6, True, "fp32_ir", (1, 1)),
+    (3, 64, 6, False, "fp64", (3, 2)),
+    (3, 96, 6, True, "fp64", (2, 3)),
+])
+def test_paired_half_sweeps_agree_bitwise(dim, n, levels, kap, prec, nu):
+    """Two red-black half-sweeps in one pass compute bitwise what two
+    separate half-sweep launches compute (whole solves compared)."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_PAIR, Solver
+    kappa = W.kappa_lognormal(dim, n, 12) if kap else None
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 13))
+    outs = []
+    for flags in (FLAG_PAIR, 0):
+        with Solver(dim, n, levels, kappa=kappa, precision=prec, nu_pre=nu[0], nu_post=nu[1],
+                    flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-8)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])

@@ -64,7 +64,7 @@ def test_options_validation_and_footprint():
                 dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
                 dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
                 dict(dim=3, n=16, levels=3, max_iter=0),
-                dict(dim=3, n=16, levels=3, flags=16),
+                dict(dim=3, n=16, levels=3, flags=32),
                 dict(dim=3, n=16, levels=3, flags=8, nu_pre=2, nu_post=1),
                 dict(dim=3, n=16, levels=3, cycle=3),
                 dict(dim=3, n=16, levels=3, flags=8, cycle="F")):
