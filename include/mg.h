@@ -68,10 +68,13 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
 #define MG_FLAG_NO_TAIL 2    /* cycle every level with grid-wide launches, also
                                 the small coarse levels that otherwise run
                                 inside one workgroup */
-#define MG_FLAG_NO_FUSE 4    /* FP64 solves: compute the stopping residual of
-                                each cycle in a launch of its own instead of
-                                in one pass with the next cycle's first
-                                pre-smoothing step (same results bitwise) */
+#define MG_FLAG_NO_FUSE 4    /* launch the fused steps separately (same
+                                results bitwise): the stopping residual of an
+                                FP64 cycle, otherwise computed in one pass
+                                with the next cycle's first pre-smoothing
+                                step, and on 3D stencil levels with n >= 32
+                                the prolongation, otherwise done while the
+                                first post-smoothing step stages x */
 #define MG_FLAG_PAIR 16      /* on 3D stencil levels with n >= 32, launch
                                 consecutive red-black half-sweeps as one pass
                                 each (x, b and the result cross HBM once per
@@ -230,7 +233,7 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
  *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps
- *              in one pass
+ *              in one pass, 5 = prolongation fused into a smoothing step
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

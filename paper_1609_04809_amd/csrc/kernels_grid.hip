@@ -414,7 +414,11 @@ inline int sweep3_kz(int m) {
   return m >= 255 ? 16 : (m >= 127 ? 8 : 4);
 }
 
-template <typename T, int KIND, int MODE, bool ZERO, bool NORM>
+// PRO (smoothing modes): the coarse correction e of the next coarser level
+// (Item::e) is prolongated and added to x as x is staged, so the launch
+// smooths x + P e -- the prolongation step fused into the first
+// post-smoothing step, bitwise as k_prolong_add followed by the sweep.
+template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
                                                 int nzc, int remap, Batch B) {
   using V2 = typename Vec2<T>::type;
@@ -474,12 +478,67 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 #pragma unroll
     for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
   };
-  auto commit_x = [&](int s) {
+  // Coarse planes of e (PRO) for the tile and its halo: coarse columns
+  // 64 bx .. 64 bx + 65, rows 2 by .. 2 by + 3, plane K in slot K % 3,
+  // staged from registers one step after their loads.
+  constexpr int CX = SW_TX / 2 + 2, CY = SW_TY / 2 + 2;
+  constexpr int NCS = (CX * CY + 255) / 256;
+  __shared__ T sc[PRO ? 3 : 1][CY][CX];
+  const int nco = n >> 1;
+  const long syc = nco + 1, szc = syc * syc;
+  const T* __restrict__ ec = PRO ? (const T*)I.e : nullptr;
+  int coff[NCS];
+  T cpf[NCS];
+  if (PRO) {
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) {
+      const int e = tid + 256 * q;
+      const int r = e / CX, c = e - r * CX;
+      coff[q] = min(64 * bx + c, nco) + min(2 * by + r, nco) * (int)syc;
+    }
+  }
+  auto prefetch_c = [&](int K) {
+    const T* __restrict__ ez = ec + (long)min(K, nco) * szc;
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) cpf[q] = ez[coff[q]];
+  };
+  auto commit_c = [&](int K) {
+    T* dst = &sc[PRO ? K % 3 : 0][0][0];
+#pragma unroll
+    for (int q = 0; q < NCS; ++q) {
+      const int e = tid + 256 * q;
+      if (e < CX * CY) dst[e] = cpf[q];
+    }
+  };
+  // the multilinear interpolant of e at staged fine node (gi, gj, z), in the
+  // arithmetic of prolong_node
+  auto pe = [&](int gi, int gj, int z) -> T {
+    const int a0 = (gi >> 1) - 64 * bx, a1 = ((gi + 1) >> 1) - 64 * bx;
+    const int r0 = (gj >> 1) - 2 * by, r1 = ((gj + 1) >> 1) - 2 * by;
+    const int s0 = (z >> 1) % 3, s1 = ((z + 1) >> 1) % 3;
+    const T wi = (gi & 1) ? T(0.5) : T(1), wj = (gj & 1) ? T(0.5) : T(1);
+    const T wk = (z & 1) ? T(0.5) : T(1);
+    auto line = [&](int rr, int ss) -> T {
+      return (gi & 1) ? wi * (sc[ss][rr][a0] + sc[ss][rr][a1]) : sc[ss][rr][a0];
+    };
+    auto plane = [&](int ss) -> T {
+      return (gj & 1) ? wj * (line(r0, ss) + line(r1, ss)) : line(r0, ss);
+    };
+    return (z & 1) ? wk * (plane(s0) + plane(s1)) : plane(s0);
+  };
+  auto commit_x = [&](int s, int z) {
     T* dst = &sx[s][0][0];
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
       const int e = tid + 256 * q;
-      if (e < SW_LX * SW_LY) dst[e] = xpf[q];
+      if (e < SW_LX * SW_LY) {
+        if (PRO) {
+          const int r = e / SW_LX, c = e - r * SW_LX;
+          dst[e] = xpf[q] + pe(i0 - 1 + c, j0 - 1 + r, min(z, n));
+        } else {
+          dst[e] = xpf[q];
+        }
+      }
     }
   };
   int koff[NK];
@@ -607,8 +666,26 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   }
   prefetch_x(k0 - 1);
   if (KAP) prefetch_k(k0 - 1);
+  // PRO: coarse planes c0 .. c0+2 cover the fine planes committed before
+  // the first odd step stages the next one; an odd step q stages coarse
+  // plane (q+3)/2 (needed from fine plane q+2 on) into the slot of plane
+  // (q-3)/2, whose last fine plane q-2 was committed two steps before
+  const int c0 = (k0 - 1) >> 1;
+  if (PRO) {
+#pragma unroll
+    for (int K = c0; K <= c0 + 2; ++K) {
+      prefetch_c(K);
+      commit_c(K);
+    }
+    prefetch_c(c0 + 3);
+    __syncthreads();
+  }
   for (int p = k0 - 1; p <= k1 + 1; ++p) {
-    commit_x(p & 1);
+    if (PRO && (p & 1) && ((p + 3) >> 1) > c0 + 2) {
+      commit_c((p + 3) >> 1);
+      prefetch_c(((p + 3) >> 1) + 1);
+    }
+    commit_x(p & 1, p);
     prefetch_x(p + 1);
     if (KAP) {
       commit_k(p & 1);
@@ -1558,6 +1635,29 @@ void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero
 bool pair_sweeps(const Geo& g) { return use_sweep3(g); }
 
 template <typename T>
+void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T omega,
+                           const Batch& B, hipStream_t s) {
+  int kz, nzc;
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  const dim3 bl(64, SW_TY);
+  const int rm = sweep3_remap();
+#define L_SP(K, M) \
+  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true>), gr, bl, 0, s, g, op, omega, kz, nzc, rm, B)
+#define L_SP_K(K)                                          \
+  do {                                                     \
+    if (kind == SM_JACOBI) L_SP(K, SM_JACOBI);             \
+    else if (kind == SM_RB0) L_SP(K, SM_RB0);              \
+    else L_SP(K, SM_RB1);                                  \
+  } while (0)
+  if (op.kind == OP_KAPPA)
+    L_SP_K(OP_KAPPA);
+  else
+    L_SP_K(OP_CONST);
+#undef L_SP_K
+#undef L_SP
+}
+
+template <typename T>
 void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
                         const Batch& B, hipStream_t s) {
   int kz, nzc;
@@ -1720,6 +1820,8 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
                                    hipStream_t);                                            \
   template void launch_smooth_pair<T>(const Geo&, const StencilParams<T>&, int, bool,      \
                                       const Batch&, hipStream_t);                           \
+  template void launch_smooth_prolong<T>(const Geo&, const StencilParams<T>&, int, T,       \
+                                         const Batch&, hipStream_t);                        \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
                                  const Batch&, hipStream_t);                                \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \

@@ -58,6 +58,7 @@ enum OpCode {
   OC_HEAD,      // residual partial sums + first smoothing step (sub: kind)
   OC_CSR_HEAD,
   OC_SMOOTH2,        // two red-black half-sweeps in one pass (sub: first kind | zero << 4)
+  OC_SMOOTH_PRO,     // x + P e then one smoothing step (sub: kind), item.e = e
   OC_APPLY_DOT,      // q = A x with partials of x.q
   OC_CSR_APPLY_DOT,
   OC_PCG,            // CG vector kernel (sub: PcgOp), pointers in ext[]

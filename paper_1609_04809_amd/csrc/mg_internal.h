@@ -80,6 +80,7 @@ struct Item {
   double* partials;
   double* scal;
   const double* L;
+  const void* e;  // coarse correction (prolongation fused into a sweep)
   int flag;
 };
 
@@ -185,6 +186,13 @@ void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero
 // then the other; bitwise the result of two launch_smooth calls.  Only on
 // levels where pair_sweeps(g):  a = x_in (nullptr: x = 0), b = b, c = x_out.
 bool pair_sweeps(const Geo& g);
+// x + P e, then one smoothing step (SM_JACOBI / SM_RB0 / SM_RB1) of it, in
+// one pass; bitwise launch_prolong_add followed by launch_smooth.  Only on
+// levels where pair_sweeps(g):  a = x (the level's iterate before the
+// correction), e = e (coarse correction), b = b, c = x_out.
+template <typename T>
+void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T omega,
+                           const Batch& B, hipStream_t s);
 template <typename T>
 void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
                         const Batch& B, hipStream_t s);

@@ -637,12 +637,28 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     } else {
       for (int i = 0; i < cycle_subs(kind); ++i) visit(l + 1, cycle_sub(kind, i), i == 0);
     }
-    OpRec pr = base_op<T>(c, OC_PROLONG, l);
-    pr.item.a = cur[l + 1];
-    pr.item.c = cur[l];
-    sink(pr);
+    // on the large 3D stencil levels the prolongation is fused into the
+    // first post-smoothing step (bitwise the same)
+    const bool fuse_pro = !c->csr && c->o.nu_post >= 1 && pair_sweeps(c->lv[l].g) &&
+                          !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
     bool nz = false;
-    smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l]);
+    if (fuse_pro) {
+      OpRec o = base_op<T>(c, OC_SMOOTH_PRO, l);
+      o.sub = c->o.smoother == MG_SMOOTH_JACOBI ? SM_JACOBI : SM_RB1;
+      o.item.a = cur[l];
+      o.item.e = cur[l + 1];
+      o.item.b = bb[l];
+      o.item.c = spare[l];
+      sink(o);
+      std::swap(cur[l], spare[l]);
+      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true);
+    } else {
+      OpRec pr = base_op<T>(c, OC_PROLONG, l);
+      pr.item.a = cur[l + 1];
+      pr.item.c = cur[l];
+      sink(pr);
+      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l]);
+    }
   };
   visit(0, c->o.cycle, x0_zero);
   if (cur[0] != x0) {
@@ -789,13 +805,16 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
 }
 
 // profiling hooks: bracket level-0 launches of the selected kernel class
-enum ProfKind { PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4 };
+enum ProfKind {
+  PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4, PK_SMOOTH_PRO = 5
+};
 
 int prof_class(int code) {
   switch (code) {
     case OC_SMOOTH:
     case OC_CSR_SMOOTH: return PK_SMOOTH;
     case OC_SMOOTH2: return PK_SMOOTH2;
+    case OC_SMOOTH_PRO: return PK_SMOOTH_PRO;
     case OC_RESID:
     case OC_CSR_RESID:
     case OC_HEAD:
@@ -937,6 +956,7 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
     case OC_SMOOTH2:
       launch_smooth_pair<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, B, s);
       break;
+    case OC_SMOOTH_PRO: launch_smooth_prolong<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
     case OC_APPLY_DOT: launch_apply_dot<T>(o.g, params_of<T>(o), B, s); break;
     case OC_CSR_APPLY_DOT:
       launch_csr_apply_dot<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (T*)it.c,
@@ -1349,7 +1369,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
 
 mg_status mg_profile_enable(mg_ctx* c, int kernel_id, int enable) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > 4) return fail(MG_E_ARG, "kernel_id must be 0..4");
+  if (kernel_id < 0 || kernel_id > 5) return fail(MG_E_ARG, "kernel_id must be 0..5");
   c->prof_kernel = kernel_id;
   c->prof_on = enable != 0;
   c->prof_launches = 0;

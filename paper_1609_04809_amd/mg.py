@@ -33,7 +33,7 @@ FLAG_PAIR = 16
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
 # mg_profile_enable kernel ids
-PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG, PROF_PAIR = 0, 1, 2, 3, 4
+PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG, PROF_PAIR, PROF_SMOOTH_PRO = 0, 1, 2, 3, 4, 5
 
 
 class MgError(RuntimeError):
