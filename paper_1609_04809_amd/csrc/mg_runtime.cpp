@@ -637,9 +637,12 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     } else {
       for (int i = 0; i < cycle_subs(kind); ++i) visit(l + 1, cycle_sub(kind, i), i == 0);
     }
-    // on the large 3D stencil levels the prolongation is fused into the
-    // first post-smoothing step (bitwise the same)
-    const bool fuse_pro = !c->csr && c->o.nu_post >= 1 && pair_sweeps(c->lv[l].g) &&
+    // on the large 3D constant-coefficient stencil levels the prolongation
+    // is fused into the first post-smoothing step (bitwise the same; with
+    // per-cell kappa the fused kernel's register and LDS use cost more than
+    // the pass it saves)
+    const bool fuse_pro = !c->csr && !c->kappa && c->o.nu_post >= 1 &&
+                          pair_sweeps(c->lv[l].g) &&
                           !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
     bool nz = false;
     if (fuse_pro) {
