@@ -21,6 +21,9 @@ What it computes, and where the paper defines it:
 * conjugate gradients preconditioned by one V-cycle per iteration
   (multigrid as a Krylov preconditioner, Sec. 1), in FP64 or with the
   cycle in FP32;
+* the mass-shifted matrix K + sigma M, warm-started solves and the
+  Crank-Nicolson time loop of the heat-equation model problem (Sec. 6.2;
+  module ``oracle.heat``);
 * independent exact references (dense Cholesky, DST-I diagonalisation,
   sparse LU) used only to pin the rest.
 
@@ -31,9 +34,11 @@ iterative-refinement inner cycle, by definition of that mode).
 from .q1 import (
     element_factors,
     element_matrix,
+    element_mass,
     n_interior,
     interior_coords,
     assemble,
+    assemble_full,
     assemble_load_quadrature,
     apply_matfree,
     apply_rows,
@@ -67,8 +72,8 @@ from .exact import (
 )
 
 __all__ = [
-    "element_factors", "element_matrix", "n_interior", "interior_coords",
-    "assemble", "assemble_load_quadrature", "apply_matfree", "apply_rows",
+    "element_factors", "element_matrix", "element_mass", "n_interior",
+    "interior_coords", "assemble", "assemble_full", "assemble_load_quadrature", "apply_matfree", "apply_rows",
     "kappa_coarsen", "kappa_hierarchy", "to_full", "to_interior",
     "prolongation", "restriction",
     "Hierarchy", "build_hierarchy", "jacobi_sweep", "rb_half_sweep", "smooth",

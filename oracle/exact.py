@@ -12,8 +12,8 @@ import scipy.linalg as sla
 import scipy.sparse.linalg as spla
 
 
-def dst_eigenvalues(dim, n):
-    """Eigenvalues of the kappa = 1 Q1 matrix on the sine basis.
+def dst_eigenvalues(dim, n, sigma=0.0):
+    """Eigenvalues of the kappa = 1 Q1 matrix K + sigma M on the sine basis.
 
     The 1D Q1 stiffness and mass matrices on the unknowns are the
     tridiagonal (1/h) tri(-1, 2, -1) and (h/6) tri(1, 4, 1); both are
@@ -21,9 +21,10 @@ def dst_eigenvalues(dim, n):
     eigenvalues k^(k) = (2/h)(1 - cos(pi k/n)) and
     m^(k) = (h/3)(2 + cos(pi k/n)).  The d-dimensional matrix is the sum
     over directions of Kronecker products (stiffness in one direction, mass
-    in the others), so its eigenvalue for mode (k_x, k_y[, k_z]) is
-    sum_d k^(k_d) prod_{e != d} m^(k_e).  Returned as a full array of shape
-    (n-1,)*dim indexed [k_z, k_y, k_x].
+    in the others) and the mass matrix the Kronecker product of the 1D mass
+    matrices, so the eigenvalue for mode (k_x, k_y[, k_z]) is
+    sum_d k^(k_d) prod_{e != d} m^(k_e) + sigma prod_d m^(k_d).  Returned as
+    a full array of shape (n-1,)*dim indexed [k_z, k_y, k_x].
     """
     h = 1.0 / n
     k = np.arange(1, n)
@@ -39,14 +40,22 @@ def dst_eigenvalues(dim, n):
             shape[dim - 1 - e] = n - 1          # axis of direction e
             term = term * v.reshape(shape)
         lam += term
+    if sigma != 0.0:
+        mass = np.ones((n - 1,) * dim)
+        for e in range(dim):
+            shape = [1] * dim
+            shape[dim - 1 - e] = n - 1
+            mass = mass * mh.reshape(shape)
+        lam += sigma * mass
     return lam
 
 
-def dst_solve(dim, n, b_int):
-    """u* = A^-1 b for kappa = 1 by DST-I diagonalisation, any size."""
+def dst_solve(dim, n, b_int, sigma=0.0):
+    """u* = A^-1 b for kappa = 1 (A = K + sigma M) by DST-I
+    diagonalisation, any size."""
     B = np.asarray(b_int, dtype=np.float64).reshape((n - 1,) * dim)
     Bh = sfft.dstn(B, type=1, norm="ortho")
-    U = sfft.idstn(Bh / dst_eigenvalues(dim, n), type=1, norm="ortho")
+    U = sfft.idstn(Bh / dst_eigenvalues(dim, n, sigma), type=1, norm="ortho")
     return U.ravel()
 
 

@@ -22,7 +22,11 @@ design notes of the repository):
   of its children.
 * The outer iteration (Sec. 5.5.1) starts from u = 0 and stops after the
   first cycle whose relative residual ||b - A u||_2 / ||b||_2 over the
-  unknowns is <= tol.
+  unknowns is <= tol.  Started from a given u0 (a warm start, as in the
+  time loop of Sec. 6.2), it first tests u0 itself and stops after zero
+  cycles if u0 already meets the tolerance.
+* With a mass shift sigma > 0 every level has the matrix K_l + sigma M_l
+  (rediscretised, like K_l).
 """
 
 from dataclasses import dataclass, field
@@ -44,6 +48,7 @@ class Hierarchy:
     nu_pre: int = 2
     nu_post: int = 2
     omega: float = 2.0 / 3.0
+    sigma: float = 0.0              # mass shift: A_l = K_l + sigma M_l
     A: list = field(default_factory=list)       # A[l], l = 0 finest
     diag: list = field(default_factory=list)
     P: list = field(default_factory=list)       # P[l]: level l+1 -> level l
@@ -63,18 +68,20 @@ def colour_mask(dim, n, colour):
 
 
 def build_hierarchy(dim, n, levels, kappa=None, smoother="rbgs", nu_pre=2,
-                    nu_post=2, omega=2.0 / 3.0, fp32=False, cycle="V"):
+                    nu_post=2, omega=2.0 / 3.0, fp32=False, cycle="V", sigma=0.0):
     """Assemble every level's operator and the transfers (Sec. 5.1)."""
     if levels < 1 or n % (1 << (levels - 1)) != 0 or (n >> (levels - 1)) < 2:
         raise ValueError("need n divisible by 2^(levels-1) and n_c >= 2")
     if cycle not in CYCLE_SCHEDULE:
         raise ValueError("cycle must be V, W or F")
+    if not (np.isfinite(sigma) and sigma >= 0.0):
+        raise ValueError("sigma must be finite and >= 0")
     H = Hierarchy(dim=dim, n=n, levels=levels, smoother=smoother, cycle=cycle,
-                  nu_pre=nu_pre, nu_post=nu_post, omega=omega)
+                  nu_pre=nu_pre, nu_post=nu_post, omega=omega, sigma=sigma)
     kaps = kappa_hierarchy(dim, n, levels, kappa)
     for l in range(levels):
         nl = n >> l
-        A = assemble(dim, nl, kaps[l])
+        A = assemble(dim, nl, kaps[l], sigma)
         H.nl.append(nl)
         H.A.append(A)
         H.diag.append(A.diagonal().copy())
@@ -175,19 +182,31 @@ def vcycle(H, l, x, b, fp32=False):
     return cycle(H, l, x, b, "V", fp32)
 
 
+def _start(A, b, u0):
+    """(u, r, nb, hist) at the start of a solve: u = 0 (hist[0] = 1) or the
+    warm start u0 (hist[0] = ||b - A u0|| / ||b||)."""
+    nb = np.linalg.norm(b)
+    if u0 is None:
+        return np.zeros_like(b), b.copy(), nb, [1.0]
+    u = np.array(u0, dtype=np.float64)
+    r = b - A @ u
+    return u, r, nb, [np.linalg.norm(r) / nb if nb > 0.0 else 0.0]
+
+
 def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
     """Outer fixed-point iteration of V-cycles (Sec. 5.5.1) in FP64.
 
-    Returns (u, iters, hist, status) with hist[0] = 1 and hist[k] the
-    relative residual after cycle k; status is "ok", "maxit" or "diverged".
+    Returns (u, iters, hist, status) with hist[0] the relative residual of
+    the start (1 from u = 0) and hist[k] the relative residual after cycle
+    k; status is "ok", "maxit" or "diverged".
     """
     b = np.asarray(b, dtype=np.float64)
     A = H.A[0]
-    nb = np.linalg.norm(b)
-    u = np.zeros_like(b) if u0 is None else np.array(u0, dtype=np.float64)
-    hist = [1.0]
+    u, _, nb, hist = _start(A, b, u0)
     if nb == 0.0:
-        return np.zeros_like(b), 0, hist, "ok"
+        return np.zeros_like(b), 0, [1.0], "ok"
+    if u0 is not None and hist[0] <= tol:
+        return u, 0, hist, "ok"
     for k in range(1, max_iter + 1):
         u = cycle(H, 0, u, b, H.cycle)
         rho = np.linalg.norm(b - A @ u) / nb
@@ -199,24 +218,23 @@ def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
     return u, max_iter, hist, "maxit"
 
 
-def solve_ir(H, b, tol, max_iter=100, diverge=1e3):
+def solve_ir(H, b, tol, max_iter=100, diverge=1e3, u0=None):
     """FP32-inner / FP64-outer iterative refinement.
 
     FP64: r = b - A u, s = ||r||; the correction equation is solved
     approximately by one float32 V-cycle (operators rounded from the FP64
     assembly, coarse solve in FP64) applied to float32(r / s) from a zero
-    guess; then u += s * float64(c).  Stops like :func:`solve`.
+    guess; then u += s * float64(c).  Starts and stops like :func:`solve`.
     """
     if not H.A32:
         raise ValueError("hierarchy built without fp32=True")
     b = np.asarray(b, dtype=np.float64)
     A = H.A[0]
-    nb = np.linalg.norm(b)
-    u = np.zeros_like(b)
-    hist = [1.0]
+    u, r, nb, hist = _start(A, b, u0)
     if nb == 0.0:
+        return np.zeros_like(b), 0, [1.0], "ok"
+    if u0 is not None and hist[0] <= tol:
         return u, 0, hist, "ok"
-    r = b.copy()
     for k in range(1, max_iter + 1):
         s = np.linalg.norm(r)
         r32 = (r / s).astype(np.float32)
@@ -251,13 +269,14 @@ def precondition(H, r, fp32=False):
     return s * cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True).astype(np.float64)
 
 
-def solve_pcg(H, b, tol, max_iter=100, diverge=1e3, fp32=False, precond=None):
+def solve_pcg(H, b, tol, max_iter=100, diverge=1e3, fp32=False, precond=None, u0=None):
     """Conjugate gradients on A u = b preconditioned by one V-cycle per
     iteration.  The paper names multigrid as a preconditioner for Krylov
     solvers (Sec. 1, with GMRES); A is symmetric positive definite and the
     V-cycle symmetric, so CG is the Krylov method used here.
 
-    Steps per iteration k (u_0 = 0, r_0 = b, z_0 = B r_0, p_0 = z_0):
+    Steps per iteration k (u_0 = 0 or the warm start, r_0 = b - A u_0,
+    z_0 = B r_0, p_0 = z_0):
       q = A p;  alpha = (r, z) / (p, q);  u += alpha p;  r' = r - alpha q;
       stop if ||r'|| / ||b|| <= tol;
       z' = B r';  beta = (z', r' - r) / (r, z);  p = z' + beta p.
@@ -267,18 +286,17 @@ def solve_pcg(H, b, tol, max_iter=100, diverge=1e3, fp32=False, precond=None):
     the recursively updated residual r'.
 
     precond: optional replacement for the V-cycle (a function r -> z), for
-    the special cases that pin this routine.  Returns (u, iters, hist,
-    status) like :func:`solve`.
+    the special cases that pin this routine.  Starts, stops and returns
+    (u, iters, hist, status) like :func:`solve`.
     """
     b = np.asarray(b, dtype=np.float64)
     A = H.A[0]
     M = precond if precond is not None else (lambda v: precondition(H, v, fp32))
-    nb = np.linalg.norm(b)
-    u = np.zeros_like(b)
-    hist = [1.0]
+    u, r, nb, hist = _start(A, b, u0)
     if nb == 0.0:
+        return np.zeros_like(b), 0, [1.0], "ok"
+    if u0 is not None and hist[0] <= tol:
         return u, 0, hist, "ok"
-    r = b.copy()
     z = M(r)
     p = z.copy()
     rz = r @ z

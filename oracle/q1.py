@@ -18,7 +18,9 @@ Conventions used throughout the oracle:
 
 The system is the standard Galerkin discretisation assembled cell by cell
 (Sec. 2): the stiffness matrix of -div(kappa grad u) with kappa constant on
-each cell.
+each cell, plus sigma times the mass matrix when a shift sigma >= 0 is
+given (the Crank-Nicolson step of the heat equation of Sec. 6.2, scaled by
+2/dt, has the matrix K + (2/dt) M).
 """
 
 import itertools
@@ -41,6 +43,22 @@ def element_factors(h):
     k = np.array([[1.0, -1.0], [-1.0, 1.0]]) / h
     m = np.array([[2.0, 1.0], [1.0, 2.0]]) * (h / 6.0)
     return k, m
+
+
+def element_mass(dim, h):
+    """Q1 element mass matrix on a cube of side h: the tensor product of
+    the 1D mass factors, M_e[a, b] = prod_d m[v_d, w_d]."""
+    _, m = element_factors(h)
+    verts = local_vertices(dim)
+    nv = len(verts)
+    Me = np.zeros((nv, nv))
+    for a, v in enumerate(verts):
+        for b, w in enumerate(verts):
+            p = 1.0
+            for d in range(dim):
+                p *= m[v[d], w[d]]
+            Me[a, b] = p
+    return Me
 
 
 def local_vertices(dim):
@@ -132,17 +150,19 @@ def _cells(dim, n, kappa):
 # assembly
 # --------------------------------------------------------------------------
 
-def assemble(dim, n, kappa=None):
-    """Global stiffness matrix on the unknowns, assembled cell by cell.
+def assemble(dim, n, kappa=None, sigma=0.0):
+    """Global matrix K + sigma M on the unknowns, assembled cell by cell.
 
     For every cell c and every pair of local vertices (a, b) whose nodes are
-    both interior, kappa_c * K_e[a, b] is added to A[node_a, node_b]
-    (Sec. 2; the paper stores its matrices in CSR, Sec. 6.1).  ``kappa`` is
-    an array of n^d cell values (x fastest) or None for kappa = 1.
+    both interior, kappa_c * K_e[a, b] + sigma * M_e[a, b] is added to
+    A[node_a, node_b] (Sec. 2; the paper stores its matrices in CSR,
+    Sec. 6.1).  ``kappa`` is an array of n^d cell values (x fastest) or None
+    for kappa = 1; the mass term is not weighted by kappa.
     Returns a SciPy CSR matrix of shape (N_I, N_I).
     """
     h = 1.0 / n
     Ke = element_matrix(dim, h)
+    Me = element_mass(dim, h)
     kap = _cells(dim, n, kappa)
     imap = _interior_map(dim, n)
     NI = n_interior(dim, n)
@@ -151,14 +171,15 @@ def assemble(dim, n, kappa=None):
     for a, v in enumerate(verts):
         ia = imap[_vslice(v, n)]
         for b, w in enumerate(verts):
-            # zero element entries (face pairs in 3D) are kept as explicit
-            # zeros: the structural pattern is every pair of nodes sharing a
-            # cell, 3^d per interior row away from the boundary
+            # zero element entries (face pairs in 3D without a mass term)
+            # are kept as explicit zeros: the structural pattern is every
+            # pair of nodes sharing a cell, 3^d per interior row away from
+            # the boundary
             ib = imap[_vslice(w, n)]
             mask = (ia >= 0) & (ib >= 0)
             rows.append(ia[mask].astype(np.int32))
             cols.append(ib[mask].astype(np.int32))
-            vals.append(kap[mask] * Ke[a, b])
+            vals.append(kap[mask] * Ke[a, b] + sigma * Me[a, b])
     rows = np.concatenate(rows)
     cols = np.concatenate(cols)
     vals = np.concatenate(vals)
@@ -168,14 +189,45 @@ def assemble(dim, n, kappa=None):
     return A
 
 
-def apply_matfree(dim, n, kappa, x_full):
+def assemble_full(dim, n):
+    """Stiffness K and mass M (kappa = 1) over every node of the grid,
+    boundary nodes included, assembled cell by cell; rows and columns are
+    the full-grid node numbers (x fastest).  Used where Dirichlet data
+    enters a right-hand side."""
+    h = 1.0 / n
+    Ke = element_matrix(dim, h)
+    Me = element_mass(dim, h)
+    N = (n + 1) ** dim
+    num = np.arange(N).reshape((n + 1,) * dim)
+    verts = local_vertices(dim)
+    rows, cols, kv, mv = [], [], [], []
+    for a, v in enumerate(verts):
+        ia = num[_vslice(v, n)].ravel()
+        for b, w in enumerate(verts):
+            ib = num[_vslice(w, n)].ravel()
+            rows.append(ia)
+            cols.append(ib)
+            kv.append(np.full(ia.size, Ke[a, b]))
+            mv.append(np.full(ia.size, Me[a, b]))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    K = sp.coo_matrix((np.concatenate(kv), (rows, cols)), shape=(N, N)).tocsr()
+    M = sp.coo_matrix((np.concatenate(mv), (rows, cols)), shape=(N, N)).tocsr()
+    K.sum_duplicates()
+    M.sum_duplicates()
+    return K, M
+
+
+def apply_matfree(dim, n, kappa, x_full, sigma=0.0):
     """y = A x on the full grid, cell by cell, without forming A.
 
-    Same cell-by-cell definition as :func:`assemble`; boundary values of x
-    are treated as 0 (eliminated) and boundary values of y are set to 0.
+    Same cell-by-cell definition as :func:`assemble` (with the mass shift
+    sigma); boundary values of x are treated as 0 (eliminated) and boundary
+    values of y are set to 0.
     """
     h = 1.0 / n
     Ke = element_matrix(dim, h)
+    Me = element_mass(dim, h)
     kap = _cells(dim, n, kappa)
     x = np.array(x_full, dtype=np.float64).reshape((n + 1,) * dim)
     _zero_boundary(x)
@@ -183,24 +235,28 @@ def apply_matfree(dim, n, kappa, x_full):
     verts = local_vertices(dim)
     for a, v in enumerate(verts):
         acc = np.zeros((n,) * dim)
+        accm = np.zeros((n,) * dim)
         for b, w in enumerate(verts):
             if Ke[a, b] != 0.0:
                 acc += Ke[a, b] * x[_vslice(w, n)]
-        y[_vslice(v, n)] += kap * acc
+            if sigma != 0.0:
+                accm += Me[a, b] * x[_vslice(w, n)]
+        y[_vslice(v, n)] += kap * acc + sigma * accm
     _zero_boundary(y)
     return y
 
 
-def apply_rows(dim, n, kappa, x_full, nodes):
+def apply_rows(dim, n, kappa, x_full, nodes, sigma=0.0):
     """(A x)_p for a list of interior nodes p, each computed on its own.
 
     ``nodes`` is an integer array of shape (S, dim) with columns (x, y[, z]).
     For node p and each of the 2^d cells containing it (p is local vertex a
-    of that cell), the cell adds kappa_c * sum_w K_e[a, w] x[cell + w].
-    Boundary values of x are treated as 0.
+    of that cell), the cell adds sum_w (kappa_c K_e[a, w] + sigma M_e[a, w])
+    x[cell + w].  Boundary values of x are treated as 0.
     """
     h = 1.0 / n
     Ke = element_matrix(dim, h)
+    Me = element_mass(dim, h)
     kap = _cells(dim, n, kappa)
     x = np.array(x_full, dtype=np.float64).reshape((n + 1,) * dim)
     _zero_boundary(x)
@@ -211,10 +267,13 @@ def apply_rows(dim, n, kappa, x_full, nodes):
         cell = nodes - np.array(v)            # (S, dim) in (x, y, z) order
         kc = kap[tuple(cell[:, d] for d in reversed(range(dim)))]
         acc = np.zeros(nodes.shape[0])
+        accm = np.zeros(nodes.shape[0])
         for b, w in enumerate(verts):
             q = cell + np.array(w)
-            acc += Ke[a, b] * x[tuple(q[:, d] for d in reversed(range(dim)))]
-        out += kc * acc
+            xv = x[tuple(q[:, d] for d in reversed(range(dim)))]
+            acc += Ke[a, b] * xv
+            accm += Me[a, b] * xv
+        out += kc * acc + sigma * accm
     return out
 
 

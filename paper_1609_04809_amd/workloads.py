@@ -1,8 +1,9 @@
 """Seeded synthetic inputs for the Q1 multigrid workloads.
 
 This module holds the input recipes only (random right-hand sides,
-coefficients, request traces and the manufactured load of the 2D model
-problem); it contains none of the solver's arithmetic.  Both the GPU path and
+coefficients, request traces, the manufactured load of the 2D model
+problem and the data of the heat-equation model problem); it contains none
+of the solver's arithmetic.  Both the GPU path and
 the CPU oracle are fed from here, so every comparison sees bit-identical
 inputs.  All randomness is NumPy PCG64 ``default_rng(seed)`` on the host.
 
@@ -124,6 +125,78 @@ def workload_inputs(w):
         raise ValueError(w.rhs)
     kappa = kappa_lognormal(w.dim, w.n, w.seed) if w.kappa == "lognormal" else None
     return b, kappa
+
+
+# --------------------------------------------------------------------------
+# heat-equation model problem (Crank-Nicolson time loop)
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class HeatWorkload:
+    """u_t - Laplace(u) = f on (0,1)^dim with Dirichlet data, solution
+    u = exp(-0.1 t) sin(pi x) cos(pi y) [cos(pi z)]; Crank-Nicolson steps
+    of length dt, each a solve with K + (2/dt) M warm-started from the
+    previous step."""
+    name: str
+    dim: int
+    n: int
+    levels: int
+    dt: float
+    steps: int
+    tol: float
+    smoother: str = "rbgs"
+    nu_pre: int = 3
+    nu_post: int = 3
+    op: str = "stencil"
+    precision: str = "fp64"
+
+    @property
+    def dofs(self):
+        return (self.n + 1) ** self.dim
+
+    @property
+    def unknowns(self):
+        return (self.n - 1) ** self.dim
+
+    @property
+    def sigma(self):
+        return 2.0 / self.dt
+
+
+# 512^3 cells: 135,005,697 nodes, the size of the paper's scaling run;
+# T = 5 in 500 steps of 0.01; V(3,3) Gauss-Seidel.
+HEAT_WORKLOADS = {
+    "heat3d_512_cn": HeatWorkload("heat3d_512_cn", 3, 512, 9, 0.01, 500, 1e-8),
+    "heat3d_64_cn": HeatWorkload("heat3d_64_cn", 3, 64, 6, 0.01, 10, 1e-8),
+}
+
+
+def heat_profile(dim, n):
+    """s(x) = sin(pi x) cos(pi y) [cos(pi z)] at every node, full layout."""
+    c = np.arange(n + 1) / n
+    out = np.sin(np.pi * c)                           # x (fastest)
+    for _ in range(dim - 1):
+        out = np.multiply.outer(np.cos(np.pi * c), out)
+    return out.ravel()
+
+
+def heat_gamma(t):
+    """Time factor of the solution and of the Dirichlet data."""
+    return float(np.exp(-0.1 * t))
+
+
+def heat_lambda(dim, t):
+    """Time factor of the source: f = u_t - Laplace(u) = (dim pi^2 - 0.1)
+    exp(-0.1 t) s(x)."""
+    return float((dim * np.pi ** 2 - 0.1) * np.exp(-0.1 * t))
+
+
+def heat_inputs(w):
+    """(profile_full, u0_interior): the nodal profile s (Dirichlet data
+    gamma(t) s on the boundary, source lambda(t) s) and the solution at
+    t = 0 on the unknowns."""
+    s = heat_profile(w.dim, w.n)
+    return s, full_to_interior(w.dim, w.n, s)
 
 
 # --------------------------------------------------------------------------
