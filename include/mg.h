@@ -1,12 +1,14 @@
 /*
  * mg.h -- C ABI of the Q1 geometric-multigrid library for MI355X (gfx950).
  *
- * The library solves A u = b, where A is the conforming Q1 finite element
- * stiffness matrix of -div(kappa grad u) on the unit square (dim = 2) or unit
- * cube (dim = 3), n cells per direction, homogeneous Dirichlet data, with the
- * multigrid V-cycle of the paper's Algorithm 1 (Sec. 5.3) on a hierarchy of
- * nested uniformly refined meshes (Sec. 5.1).  One GPU holds the whole
- * hierarchy.
+ * The library solves A u = b, where A = K + sigma M is the conforming Q1
+ * finite element stiffness matrix K of -div(kappa grad u) plus sigma >= 0
+ * times the mass matrix M (sigma = 0: the Poisson-type problem; sigma =
+ * 2/dt: the Crank-Nicolson step of the heat equation, Sec. 6.2) on the unit
+ * square (dim = 2) or unit cube (dim = 3), n cells per direction,
+ * homogeneous Dirichlet data on the unknowns, with the multigrid V-cycle of
+ * the paper's Algorithm 1 (Sec. 5.3) on a hierarchy of nested uniformly
+ * refined meshes (Sec. 5.1).  One GPU holds the whole hierarchy.
  *
  * Layouts (all arrays x fastest):
  *   node vectors  (n_l+1)^dim entries, all nodes of level l including the
@@ -96,6 +98,12 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 updated residual.  V- or W-cycles only (the
                                 F-cycle is not symmetric).  Not for the
                                 server. */
+#define MG_FLAG_WARM 32      /* mg_solve starts from the u it is given (a
+                                warm start, e.g. the previous time step)
+                                instead of u = 0: it sets u's boundary
+                                entries to 0, computes hist[0] = ||b - A u|| /
+                                ||b|| and returns after 0 iterations if that
+                                already meets tol.  Not for the server. */
 
 typedef struct {
   int dim;          /* 2 or 3 */
@@ -110,10 +118,15 @@ typedef struct {
   int max_iter;     /* maximum number of cycles / refinement steps, >= 1 */
   int flags;        /* MG_FLAG_* */
   int cycle;        /* mg_cycle */
+  double sigma;     /* mass shift: A = K + sigma M on every level, finite,
+                       >= 0.  With sigma > 0 a matrix-free stencil context
+                       takes no kappa (kappa = 1), MG_FLAG_PAIR is refused,
+                       and the server refuses the request. */
 } mg_options;
 
 /* Fill *o with the defaults: 3D, n = 64, levels = 6, stencil, red-black,
- * V(2,2), omega = 2/3, FP64, max_iter = 100, flags = 0, V-cycle. */
+ * V(2,2), omega = 2/3, FP64, max_iter = 100, flags = 0, V-cycle,
+ * sigma = 0. */
 void mg_options_default(mg_options* o);
 
 /* Device bytes that mg_setup(o, kappa_dev != NULL, ...) allocates for its
@@ -136,22 +149,52 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream,
                    mg_ctx** out);
 
 /* Solve A u = b to a relative residual ||b - A u||_2 / ||b||_2 <= tol
- * (2-norm over the unknowns), starting from u = 0, one V(nu_pre, nu_post)
- * cycle per iteration (Sec. 5.5.1).  With MG_PREC_FP32_IR each iteration is
+ * (2-norm over the unknowns), starting from u = 0 (or from the given u with
+ * MG_FLAG_WARM), one V(nu_pre, nu_post) cycle per iteration (Sec. 5.5.1).
+ * With MG_PREC_FP32_IR each iteration is
  * one FP32 V-cycle on the scaled FP64 residual, followed by an FP64 update
  * and residual.
  *   b_dev      device, (n+1)^dim doubles; boundary entries ignored.
- *   u_dev      device, (n+1)^dim doubles, output; boundary entries set to 0.
- *              Must not alias b_dev.
+ *   u_dev      device, (n+1)^dim doubles, output (and with MG_FLAG_WARM
+ *              the initial iterate on its unknowns); boundary entries set
+ *              to 0.  Must not alias b_dev.
  *   tol        > 0.
  *   iters      host, out: cycles done.
  *   hist_host  host, out, room for max_iter + 1 doubles (or NULL):
- *              hist[0] = 1, hist[k] = relative residual after cycle k.
+ *              hist[0] = 1 (warm start: the relative residual of the
+ *              initial u), hist[k] = relative residual after cycle k.
  * Returns MG_OK, or MG_E_MAXIT / MG_E_DIVERGED with u, iters and hist
  * holding the last iterate; b = 0 gives u = 0, iters = 0, MG_OK.
  * MG_E_NONFINITE if b holds NaN/Inf.  Host-synchronous. */
 mg_status mg_solve(mg_ctx* ctx, const double* b_dev, double* u_dev, double tol,
                    int* iters, double* hist_host, void* stream);
+
+/* Right-hand side of one Crank-Nicolson step of the heat equation (the
+ * model problem of Sec. 6.2) for a context with A = K + sigma M, sigma =
+ * 2/dt (kappa = 1): on the unknowns
+ *   b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f,
+ * the Crank-Nicolson equation M (u' - u)/dt + K (u' + u)/2 = M (f + f')/2
+ * times 2/dt with the Dirichlet values of u' moved to the right-hand side.
+ *   u_dev   device, (n+1)^dim doubles: the solution at t_n on the unknowns
+ *           (boundary entries ignored), e.g. the previous mg_solve output.
+ *   g0_dev  device, (n+1)^dim doubles or NULL (= 0): x0 takes c0 * g0 on the
+ *           boundary nodes (the Dirichlet data at t_n); interior entries
+ *           ignored.
+ *   g1_dev  device, (n+1)^dim doubles or NULL: x1 = c1 * g1 on the boundary
+ *           nodes, 0 inside (the Dirichlet data at t_{n+1}).
+ *   f_dev   device, (n+1)^dim doubles or NULL: nodal source values on every
+ *           node (the load is M f, the Galerkin load of the source's Q1
+ *           interpolant), scaled by cf (e.g. f(t_n) + f(t_{n+1}) for
+ *           separable data).
+ *   b_dev   device, (n+1)^dim doubles, out: boundary entries set to 0; must
+ *           not alias the inputs.
+ * The same arrays may serve as g0 and g1 (time-separable Dirichlet data).
+ * FP64 in every context.  Errors: MG_E_ARG (NULL u or b, aliasing, a
+ * context with per-cell kappa).  Stream-ordered, no synchronisation. */
+mg_status mg_cn_rhs(mg_ctx* ctx, const double* u_dev, const double* g0_dev,
+                    double c0, const double* g1_dev, double c1,
+                    const double* f_dev, double cf, double* b_dev,
+                    void* stream);
 
 /* Release a context and its device memory (NULL is ignored). */
 void mg_destroy(mg_ctx* ctx);

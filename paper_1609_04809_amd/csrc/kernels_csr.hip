@@ -185,7 +185,8 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
 // (3D, s_elem = h/12).  kappa == nullptr means kappa = 1.  Values are
 // formed in FP64 and rounded to T.
 template <typename T, int DIM>
-__global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_elem, int rows,
+__global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_elem,
+                            double s_mass, int rows,
                             const int* __restrict__ rowmap, const int* __restrict__ rowptr,
                             int* __restrict__ col, T* __restrict__ val) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -214,7 +215,9 @@ __global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_el
             ks += kappa[cell];
           }
         }
-    return s_elem * (DIM == 3 ? f3[cls] : f2[cls]) * ks;
+    // the mass entry: (h/6)^dim 2^(dim-cls) per cell, on 2^(dim-cls) cells
+    const double mass = s_mass * (double)(1 << (2 * (DIM - cls)));
+    return s_elem * (DIM == 3 ? f3[cls] : f2[cls]) * ks + mass;
   };
   int pos = rowptr[r];
   col[pos] = node;
@@ -271,16 +274,16 @@ long csr_residual_blocks(int rows) { return cdiv_i(rows, kCsrVariants[csr_varian
 long csr_residual_blocks_max(int rows) { return cdiv_i(rows, CSR_MIN_ROWS); }
 
 template <typename T>
-void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
+void launch_csr_build(const Geo& g, const double* kappa, double s_elem, double s_mass, int rows,
                       const int* rowmap, const int* rowptr, int* col, T* val, hipStream_t s) {
   const unsigned blocks = (unsigned)cdiv_i(rows, 256);
   if (blocks == 0) return;
   if (g.dim == 2)
     hipLaunchKernelGGL((k_csr_build<T, 2>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
-                       rows, rowmap, rowptr, col, val);
+                       s_mass, rows, rowmap, rowptr, col, val);
   else
     hipLaunchKernelGGL((k_csr_build<T, 3>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
-                       rows, rowmap, rowptr, col, val);
+                       s_mass, rows, rowmap, rowptr, col, val);
 }
 
 template <typename T>
@@ -317,8 +320,8 @@ void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, co
 }
 
 #define INST(T)                                                                              \
-  template void launch_csr_build<T>(const Geo&, const double*, double, int, const int*,      \
-                                    const int*, int*, T*, hipStream_t);                      \
+  template void launch_csr_build<T>(const Geo&, const double*, double, double, int,         \
+                                    const int*, const int*, int*, T*, hipStream_t);          \
   template void launch_csr_residual<T>(const Geo&, const CsrOp<T>&, const T*, const T*, T*,  \
                                        double*, hipStream_t);                                \
   template void launch_csr_smooth<T>(const Geo&, const CsrOp<T>&, int, const T*, const T*,   \

@@ -118,6 +118,29 @@ __device__ __forceinline__ T stencil3_const(const StencilParams<T>& op, const V&
   return stencil3_const_sum(op, v[1][1][1], g, a0, a1, b0, b1, c0, c1);
 }
 
+// K + sigma M (kappa = 1): every neighbour is coupled.  The same parts as
+// for kappa = 1 plus the face neighbours: fo = the x- and y-faces of the
+// node's own plane (the xe + ye parts of that plane), z0 / z1 = the centre
+// values of the planes below / above.
+template <typename T>
+__device__ __forceinline__ T stencil3_mass_sum(const StencilParams<T>& op, T xc, T g, T fo, T a0,
+                                               T a1, T b0, T b1, T c0, T c1, T z0, T z1) {
+  const T e = (g + (a0 + a1)) + (b0 + b1);
+  const T c = c0 + c1;
+  const T f = fo + (z0 + z1);
+  return op.wc * xc + op.wf * f + op.w1 * e + op.w2 * c;
+}
+
+template <typename T, typename V>
+__device__ __forceinline__ T stencil3_mass(const StencilParams<T>& op, const V& v) {
+  T a0, b0, c0, a1, b1, c1, fa, fb, g;
+  plane_parts<T>(v[0], 0, a0, b0, c0);
+  plane_parts<T>(v[2], 0, a1, b1, c1);
+  plane_parts<T>(v[1], 0, fa, fb, g);
+  return stencil3_mass_sum(op, v[1][1][1], g, fa + fb, a0, a1, b0, b1, c0, c1, v[0][1][1],
+                           v[2][1][1]);
+}
+
 // kappa per cell: cell (c, b, a) of the eight around p (sides sx = 2a-1,
 // sy = 2b-1, sz = 2c-1) with coefficient kappa_abc contributes
 //   kappa_abc * h/12 * (4 x_p - x_{p+sx+sy} - x_{p+sx+sz} - x_{p+sy+sz}
@@ -214,6 +237,20 @@ struct Apply<T, 3, OP_CONST> {
     T v[3][3][3];
     gather27(x, p, g.sy, g.sz, v);  // face entries are loaded but carry weight 0
     ax = stencil3_const(op, v);
+    dg = op.wc;
+  }
+  __device__ static T diag(const StencilParams<T>& op, const T*, const DGeo&, int, int, int) {
+    return op.wc;
+  }
+};
+
+template <typename T>
+struct Apply<T, 3, OP_MASS> {
+  __device__ static void at(const StencilParams<T>& op, const T*, const DGeo& g,
+                            const T* __restrict__ x, long p, int, int, int, T& ax, T& dg) {
+    T v[3][3][3];
+    gather27(x, p, g.sy, g.sz, v);
+    ax = stencil3_mass(op, v);
     dg = op.wc;
   }
   __device__ static T diag(const StencilParams<T>& op, const T*, const DGeo&, int, int, int) {
@@ -597,7 +634,9 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   // unknowns per plane, alternately i and i+1, so one set of sums suffices.
   constexpr bool RB = MODE == SM_RB0 || MODE == SM_RB1;
   constexpr bool KAP = KIND == OP_KAPPA;
-  constexpr int NC = RB ? 1 : 2;  // unknowns computed per thread and plane
+  constexpr bool MASS = KIND == OP_MASS;
+  constexpr int NS = MASS ? 4 : 3;  // side parts carried per plane
+  constexpr int NC = RB ? 1 : 2;    // unknowns computed per thread and plane
   const int colour = MODE == SM_RB1 ? 1 : 0;
   const long pb0 = min(i, n - 1) + min(j, n) * sy;  // clamped into the grid
   T bpf[2] = {T(0), T(0)};
@@ -653,16 +692,18 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 
   // sums carried per computed unknown q (see above):
   //   s2 / s1: side parts of planes p-2 / p-1 for the unknowns two / one
-  //            plane(s) up: {x-edges, y-edges, corners} (kappa: {Q, -, -})
-  //   g1, x1, k1s: plane-(p-1) parts of its own unknown: in-plane corners
-  //            (kappa: P), centre value, coefficient sum (kappa)
-  T s2[NC][3], s1[NC][3], g1[NC], x1[NC], k1s[NC];
+  //            plane(s) up: {x-edges, y-edges, corners} (kappa: {Q, -, -};
+  //            with the mass term also the centre value, a face neighbour)
+  //   g1, x1, k1s, f1: plane-(p-1) parts of its own unknown: in-plane
+  //            corners (kappa: P), centre value, coefficient sum (kappa),
+  //            in-plane faces (mass term)
+  T s2[NC][NS], s1[NC][NS], g1[NC], x1[NC], k1s[NC], f1[NC];
   T xo1 = T(0);  // red-black: old value of the other unknown at plane p-1
 #pragma unroll
   for (int q = 0; q < NC; ++q) {
-    g1[q] = x1[q] = k1s[q] = T(0);
+    g1[q] = x1[q] = k1s[q] = f1[q] = T(0);
 #pragma unroll
-    for (int t = 0; t < 3; ++t) s2[q][t] = s1[q][t] = T(0);
+    for (int t = 0; t < NS; ++t) s2[q][t] = s1[q][t] = T(0);
   }
   prefetch_x(k0 - 1);
   if (KAP) prefetch_k(k0 - 1);
@@ -702,7 +743,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     // the other one); the same for a whole wavefront (one row j), so the
     // branch below does not diverge, and inside it every window index is a
     // constant (runtime indices into register arrays become select chains)
-    T sn[NC][3], gn[NC], xn[NC], kn[NC], xon;
+    T sn[NC][NS], gn[NC], xn[NC], kn[NC], fn[NC], xon;
     const int k = p - 1;
     auto step = [&](auto upc) {
       constexpr int up = decltype(upc)::value;
@@ -715,10 +756,13 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
           sn[q][1] = kappa_side<T>(kwp, w, cs);  // R of the unknown at p-1 (layer p-1)
           sn[q][2] = T(0);
           kappa_plane<T>(kwp, kwc, w, cc, gn[q], kn[q]);
+          fn[q] = T(0);
         } else {
           plane_parts<T>(w, cs, sn[q][0], sn[q][1], sn[q][2]);
+          if constexpr (MASS) sn[q][3] = w[1][cs + 1];
           T ea, eb;
           plane_parts<T>(w, cc, ea, eb, gn[q]);
+          fn[q] = MASS ? ea + eb : T(0);
           kn[q] = T(0);
         }
         xn[q] = w[1][cc + 1];
@@ -735,6 +779,10 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         if (KAP) {
           ax = op.s * (g1[q] - (s2[q][0] + sn[q][1]));
           dg = op.s * T(4) * k1s[q];
+        } else if constexpr (MASS) {
+          ax = stencil3_mass_sum(op, x1[q], g1[q], f1[q], s2[q][0], sn[q][0], s2[q][1],
+                                 sn[q][1], s2[q][2], sn[q][2], s2[q][3], sn[q][3]);
+          dg = op.wc;
         } else {
           ax = stencil3_const_sum(op, x1[q], g1[q], s2[q][0], sn[q][0], s2[q][1], sn[q][1],
                                   s2[q][2], sn[q][2]);
@@ -772,13 +820,14 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 #pragma unroll
     for (int q = 0; q < NC; ++q) {
 #pragma unroll
-      for (int t = 0; t < 3; ++t) {
+      for (int t = 0; t < NS; ++t) {
         s2[q][t] = s1[q][t];
         s1[q][t] = sn[q][t];
       }
       g1[q] = gn[q];
       x1[q] = xn[q];
       k1s[q] = kn[q];
+      f1[q] = fn[q];
     }
     xo1 = xon;
     if (KAP) {
@@ -816,6 +865,7 @@ template <typename T, int KIND, int CA, bool ZERO>
 __global__ __launch_bounds__(256) void k_sweep3_pair(Geo g, StencilParams<T> op, int kz, int nzc,
                                                      int remap, Batch B) {
   constexpr bool KAP = KIND == OP_KAPPA;
+  static_assert(KIND != OP_MASS, "paired half-sweeps carry no face couplings");
   constexpr int CB = 1 - CA;
   __shared__ T sxp[ZERO ? 1 : 3][P2_XY][P2_XX];
   __shared__ T syp[3][P2_YY][P2_YX];
@@ -1319,7 +1369,7 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
   auto X = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ot : D.lv[l].ox); };
   auto S = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ox : D.lv[l].ot); };
   auto params = [&](int l) {
-    return StencilParams<T>{KIND, D.lv[l].wc, D.lv[l].w1, D.lv[l].w2, D.lv[l].s};
+    return StencilParams<T>{KIND, D.lv[l].wc, D.lv[l].w1, D.lv[l].w2, D.lv[l].s, D.lv[l].wf};
   };
   // nu sweeps on level l from X(l) (or from 0 if *zero)
   auto smooth = [&](int l, bool pre, bool* zero) {
@@ -1484,6 +1534,97 @@ __global__ void k_count_bad_kappa(const double* __restrict__ k, long count, int*
   if (b) atomicAdd(nonfinite, b);
 }
 
+// ---------------------------------------------------------------------------
+// Crank-Nicolson right-hand side (launch_cn_rhs), FP64:
+//   b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f  on the unknowns,
+// x0 = u inside and c0 g0 on the boundary, x1 = c1 g1 on the boundary and 0
+// inside.  One thread per unknown; the 3^dim neighbours are summed per
+// class (centre, faces, edges, corners) and weighted per class.  Blocks
+// whose unknowns all lie away from the boundary read u without boundary
+// tests; the others select per neighbour.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ __launch_bounds__(256) void k_cn_rhs(Geo g, CnWeights w, const double* __restrict__ u,
+                                                const double* __restrict__ g0,
+                                                const double* __restrict__ g1,
+                                                const double* __restrict__ f,
+                                                double* __restrict__ b) {
+  const int n = g.n, m = n - 1;
+  const int i0 = 1 + blockIdx.x * BX, j0 = 1 + blockIdx.y * BY;
+  const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+  const int k = DIM == 3 ? 1 + (int)blockIdx.z : 0;
+  if (i > m || j > m) return;
+  const long p = i + j * g.sy + (long)k * g.sz;
+  const bool inner = i0 > 1 && i0 + BX - 1 < m && j0 > 1 && j0 + BY - 1 < m &&
+                     (DIM == 2 || (k > 1 && k < m));
+  constexpr int DZ = DIM == 3 ? 1 : 0;
+  double s0[DIM + 1], s1[DIM + 1], sf[DIM + 1];
+#pragma unroll
+  for (int c = 0; c <= DIM; ++c) s0[c] = s1[c] = sf[c] = 0.0;
+  if (inner) {
+#pragma unroll
+    for (int dz = -DZ; dz <= DZ; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+          const long q = p + dx + dy * g.sy + dz * g.sz;
+          s0[cls] += u[q];
+          if (f) sf[cls] += f[q];
+        }
+  } else {
+#pragma unroll
+    for (int dz = -DZ; dz <= DZ; ++dz)
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+          const long q = p + dx + dy * g.sy + dz * g.sz;
+          const int qi = i + dx, qj = j + dy, qk = k + dz;
+          const bool bnd =
+              qi == 0 || qi == n || qj == 0 || qj == n || (DIM == 3 && (qk == 0 || qk == n));
+          if (bnd) {
+            if (g0) s0[cls] += w.c0 * g0[q];
+            if (g1) s1[cls] += w.c1 * g1[q];
+          } else {
+            s0[cls] += u[q];
+          }
+          if (f) sf[cls] += f[q];
+        }
+  }
+  double acc = 0.0, accf = 0.0;
+#pragma unroll
+  for (int c = 0; c <= DIM; ++c) {
+    acc += w.wb[c] * s0[c] - w.wa[c] * s1[c];
+    accf += w.wm[c] * sf[c];
+  }
+  b[p] = acc + w.cf * accf;
+}
+
+// v = 0 on the boundary nodes; thread t covers one node of the 2 dim faces.
+template <int DIM>
+__global__ void k_zero_boundary(Geo g, double* __restrict__ v) {
+  const long N1 = g.n + 1;
+  const long face = DIM == 3 ? N1 * N1 : N1;
+  const long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  if (t >= 2 * DIM * face) return;
+  const int fi = (int)(t / face);
+  const long r = t - fi * face;
+  const long side = (fi & 1) ? g.n : 0;
+  const long a = r % N1, c = DIM == 3 ? r / N1 : 0;
+  long i, j, k;
+  if ((fi >> 1) == 0) {
+    i = side; j = a; k = c;
+  } else if ((fi >> 1) == 1) {
+    i = a; j = side; k = c;
+  } else {
+    i = a; j = c; k = side;
+  }
+  v[i + j * g.sy + k * g.sz] = 0.0;
+}
+
 inline unsigned flat_blocks(long count) {
   long b = (count + 255) / 256;
   if (b > 65536) b = 65536;
@@ -1550,27 +1691,40 @@ void launch_copy(const T* a, T* b, long count, hipStream_t s) {
   hipLaunchKernelGGL(k_copy<T>, dim3(flat_blocks(count)), dim3(256), 0, s, a, b, count);
 }
 
+// 2D operators are OP_CONST (any sigma) or OP_KAPPA; 3D ones any kind.
 #define DISPATCH_DIM_KIND(dim, kind, MACRO)                                      \
   do {                                                                           \
     if ((dim) == 2) {                                                            \
-      if ((kind) == OP_CONST) MACRO(2, OP_CONST); else MACRO(2, OP_KAPPA);       \
+      if ((kind) == OP_KAPPA) MACRO(2, OP_KAPPA); else MACRO(2, OP_CONST);       \
     } else {                                                                     \
-      if ((kind) == OP_CONST) MACRO(3, OP_CONST); else MACRO(3, OP_KAPPA);       \
+      if ((kind) == OP_KAPPA) MACRO(3, OP_KAPPA);                                \
+      else if ((kind) == OP_MASS) MACRO(3, OP_MASS);                             \
+      else MACRO(3, OP_CONST);                                                   \
     }                                                                            \
   } while (0)
+
+// f(std::integral_constant<int, K>) for the operator kind K of a 3D level.
+template <typename F>
+inline void with_kind3(int kind, F f) {
+  if (kind == OP_KAPPA)
+    f(std::integral_constant<int, OP_KAPPA>{});
+  else if (kind == OP_MASS)
+    f(std::integral_constant<int, OP_MASS>{});
+  else
+    f(std::integral_constant<int, OP_CONST>{});
+}
 
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
                      hipStream_t s) {
   if (use_sweep3(g)) {
-    const bool kap = op.kind == OP_KAPPA;
-    if (norm) {
-      if (kap) launch_sweep3<T, OP_KAPPA, SW_RESID, false, true>(g, op, T(0), B, s);
-      else launch_sweep3<T, OP_CONST, SW_RESID, false, true>(g, op, T(0), B, s);
-    } else {
-      if (kap) launch_sweep3<T, OP_KAPPA, SW_RESID, false, false>(g, op, T(0), B, s);
-      else launch_sweep3<T, OP_CONST, SW_RESID, false, false>(g, op, T(0), B, s);
-    }
+    with_kind3(op.kind, [&](auto k) {
+      constexpr int K = decltype(k)::value;
+      if (norm)
+        launch_sweep3<T, K, SW_RESID, false, true>(g, op, T(0), B, s);
+      else
+        launch_sweep3<T, K, SW_RESID, false, false>(g, op, T(0), B, s);
+    });
     return;
   }
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
@@ -1612,13 +1766,13 @@ template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s) {
   if (use_sweep3(g)) {
-    if (op.kind == OP_KAPPA) {
-      if (zero) launch_sweep3_smooth<T, OP_KAPPA, true>(g, op, kind, omega, B, s);
-      else launch_sweep3_smooth<T, OP_KAPPA, false>(g, op, kind, omega, B, s);
-    } else {
-      if (zero) launch_sweep3_smooth<T, OP_CONST, true>(g, op, kind, omega, B, s);
-      else launch_sweep3_smooth<T, OP_CONST, false>(g, op, kind, omega, B, s);
-    }
+    with_kind3(op.kind, [&](auto k) {
+      constexpr int K = decltype(k)::value;
+      if (zero)
+        launch_sweep3_smooth<T, K, true>(g, op, kind, omega, B, s);
+      else
+        launch_sweep3_smooth<T, K, false>(g, op, kind, omega, B, s);
+    });
     return;
   }
 #define L_SM(D, K)                                                       \
@@ -1651,6 +1805,8 @@ void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T
   } while (0)
   if (op.kind == OP_KAPPA)
     L_SP_K(OP_KAPPA);
+  else if (op.kind == OP_MASS)
+    L_SP_K(OP_MASS);
   else
     L_SP_K(OP_CONST);
 #undef L_SP_K
@@ -1674,6 +1830,7 @@ void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, boo
       if (zero) L_PAIR(K, 1, true); else L_PAIR(K, 1, false); \
     }                                                \
   } while (0)
+  // (the runtime pairs half-sweeps only for OP_CONST and OP_KAPPA levels)
   if (op.kind == OP_KAPPA)
     L_PAIR_K(OP_KAPPA);
   else
@@ -1687,13 +1844,13 @@ void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, co
                  hipStream_t s) {
   const bool jac = kind == SM_JACOBI;
   if (use_sweep3(g)) {
-    if (op.kind == OP_KAPPA) {
-      if (jac) launch_sweep3<T, OP_KAPPA, SW_HEAD_JAC, false, true>(g, op, omega, B, s);
-      else launch_sweep3<T, OP_KAPPA, SW_HEAD_RB0, false, true>(g, op, omega, B, s);
-    } else {
-      if (jac) launch_sweep3<T, OP_CONST, SW_HEAD_JAC, false, true>(g, op, omega, B, s);
-      else launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true>(g, op, omega, B, s);
-    }
+    with_kind3(op.kind, [&](auto k) {
+      constexpr int K = decltype(k)::value;
+      if (jac)
+        launch_sweep3<T, K, SW_HEAD_JAC, false, true>(g, op, omega, B, s);
+      else
+        launch_sweep3<T, K, SW_HEAD_RB0, false, true>(g, op, omega, B, s);
+    });
     return;
   }
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
@@ -1711,16 +1868,34 @@ void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, co
 template <typename T>
 void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, hipStream_t s) {
   if (use_sweep3(g)) {
-    if (op.kind == OP_KAPPA)
-      launch_sweep3<T, OP_KAPPA, SW_APPLY, false, true>(g, op, T(0), B, s);
-    else
-      launch_sweep3<T, OP_CONST, SW_APPLY, false, true>(g, op, T(0), B, s);
+    with_kind3(op.kind, [&](auto k) {
+      launch_sweep3<T, decltype(k)::value, SW_APPLY, false, true>(g, op, T(0), B, s);
+    });
     return;
   }
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
 #define L_AD(D, K) hipLaunchKernelGGL((k_apply_dot<T, D, K>), gr, bl, 0, s, g, op, B)
   DISPATCH_DIM_KIND(g.dim, op.kind, L_AD);
 #undef L_AD
+}
+
+void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, const double* g0,
+                   const double* g1, const double* f, double* b, hipStream_t s) {
+  const dim3 gr = node_grid(g, 1), bl(BX, BY);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, g0, g1, f, b);
+  else
+    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, g0, g1, f, b);
+}
+
+void launch_zero_boundary(const Geo& g, double* v, hipStream_t s) {
+  const long N1 = g.n + 1;
+  const long total = 2L * g.dim * (g.dim == 3 ? N1 * N1 : N1);
+  const unsigned blocks = (unsigned)((total + 255) / 256);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_zero_boundary<2>, dim3(blocks), dim3(256), 0, s, g, v);
+  else
+    hipLaunchKernelGGL(k_zero_boundary<3>, dim3(blocks), dim3(256), 0, s, g, v);
 }
 
 template <typename T>

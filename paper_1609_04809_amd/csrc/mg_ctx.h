@@ -62,6 +62,7 @@ enum OpCode {
   OC_APPLY_DOT,      // q = A x with partials of x.q
   OC_CSR_APPLY_DOT,
   OC_PCG,            // CG vector kernel (sub: PcgOp), pointers in ext[]
+  OC_ZERO_BOUNDARY,  // c = 0 on the boundary nodes (FP64)
 };
 
 // CG vector kernels (OpRec::sub of OC_PCG)
@@ -75,8 +76,8 @@ struct OpRec {
   int sub = 0;      // OC_SMOOTH: kind | zero << 4;  OC_RESID: norm
   int level = 0;    // level index within its context (profiling)
   Geo g{}, gc{};    // level geometry and the next coarser one
-  int opkind = 0;   // OP_CONST / OP_KAPPA
-  double wc = 0, w1 = 0, w2 = 0, s = 0, omega = 0;
+  int opkind = 0;   // OP_CONST / OP_KAPPA / OP_MASS
+  double wc = 0, w1 = 0, w2 = 0, s = 0, wf = 0, omega = 0;
   int m = 0;        // coarsest unknowns
   long count = 0;   // OC_REDUCE: partials; OC_FILL / OC_COPY: elements
   Item item{};

@@ -54,20 +54,25 @@ constexpr int kCsrTile = 8;
 // Requests fused into one batched launch at most.
 constexpr int kMaxBatch = 16;
 
-enum OpKind { OP_CONST = 0, OP_KAPPA = 1 };
+enum OpKind { OP_CONST = 0, OP_KAPPA = 1, OP_MASS = 2 };
 
 // Launch-wide parameters of the matrix-free Q1 operator of one level; the
 // per-cell coefficients of OP_KAPPA travel per request in Item::kappa.
-//  OP_CONST: kappa = 1, the assembled stencil weights
-//     2D: wc = 8/3, w1 = -1/3 (x/y neighbours), w2 = -1/3 (diagonals)
-//     3D: wc = 8h/3, w1 = -h/6 (edge neighbours), w2 = -h/12 (corners);
-//         face neighbours have weight 0.
+//  OP_CONST: kappa = 1, the assembled stencil weights of K + sigma M
+//     2D: wc = 8/3, w1 = -1/3 (x/y neighbours), w2 = -1/3 (diagonals),
+//         each plus sigma times the mass weight (h/6)^2 * {16, 4, 1};
+//     3D (sigma = 0): wc = 8h/3, w1 = -h/6 (edge neighbours), w2 = -h/12
+//         (corners); face neighbours have weight 0.
+//  OP_MASS (3D, sigma > 0): K + sigma M with kappa = 1: wc, w1 (edges) and
+//     w2 (corners) as for OP_CONST plus sigma (h/6)^3 * {64, 4, 1}, and
+//     wf = sigma (h/6)^3 * 16 on the six face neighbours.
 //  OP_KAPPA: element matrix scale s = 1/6 (2D), h/12 (3D).
 template <typename T>
 struct StencilParams {
   int kind;
   T wc, w1, w2;
   T s;
+  T wf;
 };
 
 // One request's buffers in a batched launch.  The role of each pointer is
@@ -122,7 +127,7 @@ struct TailLevel {
   int ox, ot, ob, orr;  // iterate, spare, right-hand side, residual
   int ok;               // cell coefficients (OP_KAPPA)
   const T* kappa;       // device copy of the level's coefficients (OP_KAPPA)
-  T wc, w1, w2, s;      // operator parameters of the level
+  T wc, w1, w2, s, wf;  // operator parameters of the level
 };
 template <typename T>
 struct TailDesc {
@@ -236,9 +241,25 @@ void launch_count_bad_kappa(const double* k, long count, int* bad_nonpos, int* b
 template <typename T>
 void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, hipStream_t s);
 
+// Crank-Nicolson right-hand side (FP64) on the unknowns of a level with
+// kappa = 1:  b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f, where x0 is
+// u inside and c0 g0 on the boundary, x1 is c1 g1 on the boundary and 0
+// inside (g0, g1, f may be nullptr: 0).  Weights per neighbour class
+// |dx| + |dy| (+ |dz|): wb of sigma M - K, wa of sigma M + K, wm of M.
+struct CnWeights {
+  double wb[4], wa[4], wm[4];
+  double c0, c1, cf;
+};
+void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, const double* g0,
+                   const double* g1, const double* f, double* b, hipStream_t s);
+// v = 0 on the boundary nodes of the level (interior untouched).
+void launch_zero_boundary(const Geo& g, double* v, hipStream_t s);
+
 // ---- CSR kernels (kernels_csr.hip) ----------------------------------------
+// Entries of K + sigma M: s_elem scales the stiffness element factors,
+// s_mass = sigma (h/6)^dim the mass ones.
 template <typename T>
-void launch_csr_build(const Geo& g, const double* kappa, double s_elem, int rows,
+void launch_csr_build(const Geo& g, const double* kappa, double s_elem, double s_mass, int rows,
                       const int* rowmap, const int* rowptr, int* col, T* val, hipStream_t s);
 template <typename T>
 void launch_csr_residual(const Geo& g, const CsrOp<T>& A, const T* x, const T* b, T* r,

@@ -95,7 +95,9 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
-  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG | MG_FLAG_PAIR)) { why = "unknown flags"; return false; }
+  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG | MG_FLAG_PAIR | MG_FLAG_WARM)) { why = "unknown flags"; return false; }
+  if (!(std::isfinite(o->sigma) && o->sigma >= 0.0)) { why = "sigma must be finite and >= 0"; return false; }
+  if (o->sigma > 0.0 && (o->flags & MG_FLAG_PAIR)) { why = "MG_FLAG_PAIR needs sigma == 0"; return false; }
   if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) { why = "cycle must be V, W or F"; return false; }
   if ((o->flags & MG_FLAG_PCG) && (o->nu_pre != o->nu_post || o->cycle == MG_CYCLE_F)) { why = "CG needs a symmetric cycle (V or W, nu_pre == nu_post)"; return false; }
   const long nc = o->n >> (o->levels - 1);
@@ -123,6 +125,8 @@ bool valid_options(const mg_options* o, std::string& why) {
 // rediscretised entries (up to the rounding of each entry).
 int tail_start(const mg_options& o, bool kappa) {
   if (o.flags & MG_FLAG_NO_TAIL) return -1;
+  // the tail's per-cell operator has no mass term
+  if (kappa && o.sigma > 0.0) return -1;
   auto fits = [&](int l) {
     return tail_lds_bytes(o.dim, o.n, o.levels, l, kappa, 8, true) <= kTailLdsBytes;
   };
@@ -210,8 +214,8 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
 // neighbour at offset d, from the cell coefficients kap (nullptr = 1):
 // the sum over the cells containing both nodes of kappa_c times the element
 // matrix entry, which depends only on the number of nonzero components of d.
-double q1_entry(int dim, int n, const std::vector<double>* kap, int i, int j, int k, int dx,
-                int dy, int dz) {
+double q1_entry(int dim, int n, const std::vector<double>* kap, double sigma, int i, int j, int k,
+                int dx, int dy, int dz) {
   const double h = 1.0 / n;
   const double f3[4] = {4.0, 0.0, -1.0, -1.0};
   const double f2[3] = {4.0, -1.0, -2.0};
@@ -231,7 +235,9 @@ double q1_entry(int dim, int n, const std::vector<double>* kap, int i, int j, in
           ks += (*kap)[cell];
         }
       }
-  return dim == 3 ? (h / 12.0) * f3[cls] * ks : (1.0 / 6.0) * f2[cls] * ks;
+  // mass: (h/6)^dim 2^(dim-cls) per cell on the 2^(dim-cls) shared cells
+  const double mass = sigma * std::pow(h / 6.0, dim) * (double)(1 << (2 * (dim - cls)));
+  return (dim == 3 ? (h / 12.0) * f3[cls] * ks : (1.0 / 6.0) * f2[cls] * ks) + mass;
 }
 
 // Dense coarsest matrix and its Cholesky factor (row major, lower).
@@ -256,7 +262,7 @@ mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
           if (dim == 3 && (qk < 1 || qk > mi)) continue;
           const int q2 = (qi - 1) + mi * (qj - 1) + (dim == 3 ? mi * mi * (qk - 1) : 0);
           A[(size_t)q * m + q2] =
-              q1_entry(dim, n, c->kappa ? &kap : nullptr, i, j, k, dx, dy, dz);
+              q1_entry(dim, n, c->kappa ? &kap : nullptr, c->o.sigma, i, j, k, dx, dy, dz);
         }
   }
   // Cholesky A = L L^T (lower, row major), in place.
@@ -319,10 +325,11 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   HIP_TRY(hipMemcpyAsync(Lv.rowptr, rowptr.data(), (rows + 1) * sizeof(int),
                          hipMemcpyHostToDevice, s));
   const double selem = dim == 3 ? (1.0 / n) / 12.0 : 1.0 / 6.0;
-  launch_csr_build<double>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col, Lv.val64,
-                           s);
+  const double smass = c->o.sigma * std::pow((1.0 / n) / 6.0, dim);
+  launch_csr_build<double>(Lv.g, Lv.kap64, selem, smass, rows, Lv.rowmap, Lv.rowptr, Lv.col,
+                           Lv.val64, s);
   if (Lv.val32)
-    launch_csr_build<float>(Lv.g, Lv.kap64, selem, rows, Lv.rowmap, Lv.rowptr, Lv.col,
+    launch_csr_build<float>(Lv.g, Lv.kap64, selem, smass, rows, Lv.rowmap, Lv.rowptr, Lv.col,
                             Lv.val32, s);
   HIP_TRY(hipGetLastError());
   // the host vectors must stay alive until the copies finish
@@ -342,24 +349,56 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   return MG_OK;
 }
 
+// Operator kind of the matrix-free levels: per-cell kappa, or constant
+// coefficients with (3D) or without face couplings.
+int op_kind(const mg_ctx* c) {
+  if (c->kappa) return OP_KAPPA;
+  return c->o.dim == 3 && c->o.sigma > 0.0 ? OP_MASS : OP_CONST;
+}
+
+// Mass weights (h/6)^dim 4^(dim-cls) of the assembled Q1 mass matrix for a
+// neighbour class cls = |dx| + |dy| (+ |dz|), and the stiffness weights
+// (kappa = 1) of the same classes.
+double mass_weight(int dim, double h, int cls) {
+  return std::pow(h / 6.0, dim) * (double)(1 << (2 * (dim - cls)));
+}
+double stiff_weight(int dim, double h, int cls) {
+  if (dim == 2) return cls == 0 ? 8.0 / 3.0 : -1.0 / 3.0;
+  const double w[4] = {8.0 * h / 3.0, 0.0, -h / 6.0, -h / 12.0};
+  return w[cls];
+}
+
 void set_stencil(mg_ctx* c, int l) {
   Level& Lv = c->lv[l];
   const double h = 1.0 / Lv.g.n;
-  double wc, w1, w2, s;
-  if (c->o.dim == 2) {
+  const int dim = c->o.dim;
+  const double sg = c->o.sigma;
+  double wc, w1, w2, s, wf = 0.0;
+  if (dim == 2) {
     wc = 8.0 / 3.0;
     w1 = -1.0 / 3.0;
     w2 = -1.0 / 3.0;
     s = 1.0 / 6.0;
+    if (sg > 0.0) {
+      wc += sg * mass_weight(2, h, 0);
+      w1 += sg * mass_weight(2, h, 1);
+      w2 += sg * mass_weight(2, h, 2);
+    }
   } else {
     wc = 8.0 * h / 3.0;
     w1 = -h / 6.0;
     w2 = -h / 12.0;
     s = h / 12.0;
+    if (sg > 0.0) {
+      wc += sg * mass_weight(3, h, 0);
+      wf = sg * mass_weight(3, h, 1);
+      w1 += sg * mass_weight(3, h, 2);
+      w2 += sg * mass_weight(3, h, 3);
+    }
   }
-  const int kind = c->kappa ? OP_KAPPA : OP_CONST;
-  Lv.st64 = StencilParams<double>{kind, wc, w1, w2, s};
-  Lv.st32 = StencilParams<float>{kind, (float)wc, (float)w1, (float)w2, (float)s};
+  const int kind = op_kind(c);
+  Lv.st64 = StencilParams<double>{kind, wc, w1, w2, s, wf};
+  Lv.st32 = StencilParams<float>{kind, (float)wc, (float)w1, (float)w2, (float)s, (float)wf};
 }
 
 // ---------------------------------------------------------------------------
@@ -396,7 +435,7 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
   if (l0 >= 0) {
     D.nlev = c->L - l0;
     D.dim = c->o.dim;
-    D.kind = c->kappa ? OP_KAPPA : OP_CONST;
+    D.kind = Bufs<T>::st(c->lv[l0]).kind;
     D.smoother = c->o.smoother == MG_SMOOTH_JACOBI ? 0 : 1;
     D.nu_pre = c->o.nu_pre;
     D.nu_post = c->o.nu_post;
@@ -433,6 +472,7 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
       tl.w1 = st.w1;
       tl.w2 = st.w2;
       tl.s = st.s;
+      tl.wf = st.wf;
     }
     D.oy = (int)take((long)c->m * sizeof(double));
     if (off > kTailLdsBytes) return fail(MG_E_ARG, "internal: tail levels exceed the LDS budget");
@@ -464,6 +504,7 @@ OpRec base_op(mg_ctx* c, int code, int l) {
   o.w1 = st.w1;
   o.w2 = st.w2;
   o.s = st.s;
+  o.wf = st.wf;
   o.omega = (T)c->o.omega;
   o.m = c->m;
   o.item.kappa = Bufs<T>::kap(Lv);
@@ -744,12 +785,23 @@ void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
   emit_reduce(c, sink, PB, S + 0, c->partials);
 }
 
-// Start of a CG solve: u = 0, ||b||^2 into scal[1], r = b - A u (= b on
-// the unknowns; the vector kernels also stream boundary entries, which
-// stay 0) with ||r||^2 into scal[0].
-void emit_pcg_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+// u = 0, or for a warm start u's boundary entries = 0.
+void emit_start(mg_ctx* c, const Sink& sink, double* u, bool warm) {
+  if (!warm) {
+    emit_fill<double>(c, sink, 0, u);
+    return;
+  }
+  OpRec z = base_op<double>(c, OC_ZERO_BOUNDARY, 0);
+  z.item.c = u;
+  sink(z);
+}
+
+// Start of a CG solve: u = 0 (or the warm start), ||b||^2 into scal[1],
+// r = b - A u (the vector kernels also stream boundary entries, which stay
+// 0) with ||r||^2 into scal[0].
+void emit_pcg_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool warm) {
   Level& L0 = c->lv[0];
-  emit_fill<double>(c, sink, 0, u);
+  emit_start(c, sink, u, warm);
   OpRec o = base_op<double>(c, OC_NORM2, 0);
   o.item.a = b;
   o.item.partials = c->partials;
@@ -793,15 +845,24 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
   emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
 }
 
-void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+// Start of a solve: u = 0 (or the warm start), ||b||^2 into scal[1]; for
+// FP32 refinement and for a warm start also ||b - A u||^2 into scal[0] --
+// for a warm-started solve with head fusion in one pass with the first
+// smoothing step of the first cycle (into the level-0 spare, as at the end
+// of an IT_FUSED_FIRST iteration), else with the residual in r64.
+void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool warm = false,
+                   bool fuse = false) {
   Level& L0 = c->lv[0];
-  emit_fill<double>(c, sink, 0, u);
+  emit_start(c, sink, u, warm);
   OpRec o = base_op<double>(c, OC_NORM2, 0);
   o.item.a = b;
   o.item.partials = c->partials;
   sink(o);
   emit_reduce(c, sink, norm2_blocks(L0.g), c->scal + 1);
-  if (c->ir) {
+  if (warm && fuse) {
+    emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
+    emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+  } else if (c->ir || warm) {
     emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
     emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
   }
@@ -928,7 +989,7 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 template <typename T>
 StencilParams<T> params_of(const OpRec& o) {
-  return StencilParams<T>{o.opkind, (T)o.wc, (T)o.w1, (T)o.w2, (T)o.s};
+  return StencilParams<T>{o.opkind, (T)o.wc, (T)o.w1, (T)o.w2, (T)o.s, (T)o.wf};
 }
 
 template <typename T>
@@ -983,13 +1044,14 @@ namespace mg {
 bool batchable(const OpRec& a) {
   return a.code != OC_FILL && a.code != OC_COPY && a.code != OC_CSR_SMOOTH &&
          a.code != OC_CSR_RESID && a.code != OC_CSR_HEAD && a.code != OC_CSR_APPLY_DOT &&
-         a.code != OC_PCG;
+         a.code != OC_PCG && a.code != OC_ZERO_BOUNDARY;
 }
 
 bool same_key(const OpRec& a, const OpRec& b) {
   return a.code == b.code && a.prec == b.prec && a.sub == b.sub && a.g.dim == b.g.dim &&
          a.g.n == b.g.n && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
-         a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.omega == b.omega && a.m == b.m &&
+         a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.wf == b.wf && a.omega == b.omega &&
+         a.m == b.m &&
          a.count == b.count && batchable(a) && batchable(b);
 }
 
@@ -1021,6 +1083,7 @@ void launch_ops(const OpRec* const* ops, int n, hipStream_t s) {
     case OC_SCALE_CAST: launch_scale_cast(o.g, B, s); return;
     case OC_IR_UPDATE: launch_ir_update(o.g, B, s); return;
     case OC_PCG: launch_pcg(o, s); return;
+    case OC_ZERO_BOUNDARY: launch_zero_boundary(o.g, (double*)o.item.c, s); return;
     default: break;
   }
   if (o.prec == 0)
@@ -1062,6 +1125,7 @@ void mg_options_default(mg_options* o) {
   o->max_iter = 100;
   o->flags = 0;
   o->cycle = MG_CYCLE_V;
+  o->sigma = 0.0;
 }
 
 size_t mg_footprint_bytes(const mg_options* o) {
@@ -1078,6 +1142,9 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
   *out = nullptr;
   std::string why;
   if (!valid_options(o, why)) return fail(MG_E_ARG, "%s", why.c_str());
+  if (o->sigma > 0.0 && kappa_dev && o->op == MG_OP_STENCIL)
+    return fail(MG_E_ARG, "the matrix-free operator with per-cell kappa has no mass term "
+                          "(sigma > 0 needs kappa = 1 or MG_OP_CSR)");
   hipStream_t s = as_stream(stream);
   mg_ctx* c = new mg_ctx();
   c->o = *o;
@@ -1180,21 +1247,37 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   *iters = 0;
   if (hist) hist[0] = 1.0;
   const bool pcg = (c->o.flags & MG_FLAG_PCG) != 0;
+  const bool warm = (c->o.flags & MG_FLAG_WARM) != 0;
+  const bool fuse = head_fusion(c);
   if (pcg)
-    emit_pcg_prologue(c, launch_sink(c, s), u, b);
+    emit_pcg_prologue(c, launch_sink(c, s), u, b, warm);
   else
-    emit_prologue(c, launch_sink(c, s), u, b);
+    emit_prologue(c, launch_sink(c, s), u, b, warm, fuse);
   HIP_TRY(hipGetLastError());
   double nb2 = 0.0;
   mg_status st = read_scalar(c, 1, &nb2, s);
   if (st != MG_OK) return st;
   if (!std::isfinite(nb2)) return fail(MG_E_NONFINITE, "b holds NaN or Inf");
-  if (nb2 == 0.0) return MG_OK;
+  if (nb2 == 0.0) {
+    if (warm) {
+      emit_fill<double>(c, launch_sink(c, s), 0, u);
+      HIP_TRY(hipGetLastError());
+    }
+    return MG_OK;
+  }
   const double nb = std::sqrt(nb2);
-  const bool fuse = head_fusion(c);
+  if (warm) {
+    double r2 = 0.0;
+    st = read_scalar(c, 0, &r2, s);
+    if (st != MG_OK) return st;
+    const double rho0 = std::sqrt(r2) / nb;
+    if (!std::isfinite(rho0)) return fail(MG_E_NONFINITE, "the initial u holds NaN or Inf");
+    if (hist) hist[0] = rho0;
+    if (rho0 <= tol) return MG_OK;
+  }
   for (int k = 1; k <= c->o.max_iter; ++k) {
     const int kind = pcg ? (k == 1 ? IT_PCG_FIRST : IT_PCG)
-                         : (!fuse ? IT_PLAIN : (k == 1 ? IT_FUSED_FIRST : IT_FUSED));
+                         : (!fuse ? IT_PLAIN : (k == 1 && !warm ? IT_FUSED_FIRST : IT_FUSED));
     st = run_iteration(c, u, b, s, kind);
     if (st != MG_OK) return st;
     double n2 = 0.0;
@@ -1209,6 +1292,35 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
     if (rho <= tol) return MG_OK;
   }
   return fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, c->o.max_iter);
+}
+
+mg_status mg_cn_rhs(mg_ctx* c, const double* u, const double* g0, double c0, const double* g1,
+                    double c1, const double* f, double cf, double* b, void* stream) {
+  if (!c || !u || !b) return fail(MG_E_ARG, "NULL argument");
+  if (c->kappa) return fail(MG_E_ARG, "mg_cn_rhs needs a context with kappa = 1");
+  if ((const double*)b == u || (const double*)b == g0 || (const double*)b == g1 ||
+      (const double*)b == f)
+    return fail(MG_E_ARG, "b must not alias an input");
+  if (!(std::isfinite(c0) && std::isfinite(c1) && std::isfinite(cf)))
+    return fail(MG_E_ARG, "c0, c1 and cf must be finite");
+  const Level& L0 = c->lv[0];
+  const int dim = c->o.dim;
+  const double h = 1.0 / L0.g.n, sg = c->o.sigma;
+  CnWeights w{};
+  for (int cls = 0; cls <= dim; ++cls) {
+    const double wm = mass_weight(dim, h, cls), wk = stiff_weight(dim, h, cls);
+    w.wb[cls] = sg * wm - wk;
+    w.wa[cls] = sg * wm + wk;
+    w.wm[cls] = wm;
+  }
+  w.c0 = c0;
+  w.c1 = c1;
+  w.cf = cf;
+  hipStream_t s = as_stream(stream);
+  launch_zero_boundary(L0.g, b, s);
+  launch_cn_rhs(L0.g, w, u, g0, g1, f, b, s);
+  HIP_TRY(hipGetLastError());
+  return MG_OK;
 }
 
 }  // extern "C"

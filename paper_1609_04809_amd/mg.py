@@ -29,6 +29,7 @@ FLAG_NO_TAIL = 2
 FLAG_NO_FUSE = 4
 FLAG_PCG = 8
 FLAG_PAIR = 16
+FLAG_WARM = 32
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
@@ -47,7 +48,8 @@ class Options(ctypes.Structure):
                 ("op", ctypes.c_int), ("smoother", ctypes.c_int),
                 ("nu_pre", ctypes.c_int), ("nu_post", ctypes.c_int),
                 ("omega", ctypes.c_double), ("precision", ctypes.c_int),
-                ("max_iter", ctypes.c_int), ("flags", ctypes.c_int), ("cycle", ctypes.c_int)]
+                ("max_iter", ctypes.c_int), ("flags", ctypes.c_int), ("cycle", ctypes.c_int),
+                ("sigma", ctypes.c_double)]
 
 
 _VP = ctypes.c_void_p
@@ -71,6 +73,8 @@ SIGNATURES = {
     "mg_apply_coarse_solve": (_I, [_VP, _I, _VP, _VP, _VP]),
     "mg_vcycle": (_I, [_VP, _I, _VP, _VP, _VP]),
     "mg_norm2": (_I, [_VP, _I, _I, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
+    "mg_cn_rhs": (_I, [_VP, _VP, _VP, ctypes.c_double, _VP, ctypes.c_double, _VP,
+                       ctypes.c_double, _VP, _VP]),
     "mg_profile_enable": (_I, [_VP, _I, _I]),
     "mg_profile_read": (_I, [_VP, ctypes.POINTER(ctypes.c_long),
                              ctypes.POINTER(ctypes.c_double)]),
@@ -139,7 +143,8 @@ def _ptr(t):
 
 
 def make_options(dim, n, levels, op="stencil", smoother="rbgs", nu_pre=2, nu_post=2,
-                 omega=2.0 / 3.0, precision="fp64", max_iter=100, flags=0, cycle="V"):
+                 omega=2.0 / 3.0, precision="fp64", max_iter=100, flags=0, cycle="V",
+                 sigma=0.0):
     o = Options()
     lib().mg_options_default(ctypes.byref(o))
     o.dim, o.n, o.levels = dim, n, levels
@@ -147,6 +152,7 @@ def make_options(dim, n, levels, op="stencil", smoother="rbgs", nu_pre=2, nu_pos
     o.nu_pre, o.nu_post, o.omega = nu_pre, nu_post, omega
     o.precision, o.max_iter, o.flags = PREC[precision], max_iter, flags
     o.cycle = CYCLE[cycle] if isinstance(cycle, str) else cycle
+    o.sigma = sigma
     return o
 
 
@@ -204,9 +210,12 @@ class Solver:
 
     # -- solve
     def solve(self, b, tol, u=None, raise_on_error=False):
-        """Solve with b a device float64 tensor of (n+1)^dim nodes.
+        """Solve with b a device float64 tensor of (n+1)^dim nodes (u: the
+        output, and with FLAG_WARM the initial iterate).
         Returns (u, iters, hist, status_name)."""
         if u is None:
+            if self.opts.flags & FLAG_WARM:
+                raise ValueError("a warm-started solve needs u")
             u = torch.empty_like(b)
         iters = ctypes.c_int()
         hist = (ctypes.c_double * (self.max_iter + 1))()
@@ -216,6 +225,16 @@ class Solver:
             _check(st)
         k = iters.value
         return u, k, list(hist[: k + 1]), STATUS_NAMES[st]
+
+    def cn_rhs(self, u, g0=None, c0=0.0, g1=None, c1=0.0, f=None, cf=0.0, b=None):
+        """Crank-Nicolson right-hand side b = (sigma M - K) x0 - (sigma M +
+        K) x1 + cf M f (x0 = u inside, c0 g0 on the boundary; x1 = c1 g1 on
+        the boundary); device float64 node tensors, None for absent data."""
+        if b is None:
+            b = torch.empty_like(u)
+        _check(lib().mg_cn_rhs(self._ctx, _ptr(u), _ptr(g0), float(c0), _ptr(g1), float(c1),
+                               _ptr(f), float(cf), _ptr(b), _stream()))
+        return b
 
     # -- single steps
     def _prec(self, t):

@@ -6,7 +6,8 @@ coarsest solve, norm) is run through the C ABI on seeded inputs and compared
 element by element with the oracle's definition of the step.  Sizes span
 several 64 x 4 thread tiles with ragged tails in x and y (2D n = 160:
 159 = 2*64 + 31 unknowns per row; 3D n = 80: 79 = 64 + 15), in 2D and 3D,
-for the matrix-free stencil, the kappa stencil and CSR, in FP64 and FP32.
+for the matrix-free stencil, the kappa stencil and CSR, with and without a
+mass shift (K + sigma M), in FP64 and FP32.
 
 Error bound: an entry that sums k products with magnitudes adding up to
 ``scale`` carries a rounding error below k * eps * scale; the tests use
@@ -27,30 +28,40 @@ from tests.gpu_util import (EPS32, EPS64, assert_scaled_close, boundary_is_zero,
 pytestmark = pytest.mark.gpu
 
 CASES = [
-    # dim, n, levels, kappa, op
-    (2, 160, 6, False, "stencil"),
-    (2, 160, 6, True, "stencil"),
-    (2, 160, 6, True, "csr"),
-    (3, 80, 5, False, "stencil"),
-    (3, 80, 5, True, "stencil"),
-    (3, 80, 5, False, "csr"),
-    (3, 80, 5, True, "csr"),
+    # dim, n, levels, kappa, op, sigma
+    (2, 160, 6, False, "stencil", 0.0),
+    (2, 160, 6, True, "stencil", 0.0),
+    (2, 160, 6, True, "csr", 0.0),
+    (3, 80, 5, False, "stencil", 0.0),
+    (3, 80, 5, True, "stencil", 0.0),
+    (3, 80, 5, False, "csr", 0.0),
+    (3, 80, 5, True, "csr", 0.0),
+    (2, 160, 6, False, "stencil", 200.0),
+    (3, 80, 5, False, "stencil", 200.0),
+    (3, 80, 5, False, "csr", 200.0),
+    (3, 80, 5, True, "csr", 50.0),
 ]
 
 
+def _cid(c):
+    return (f"{c[0]}d-n{c[1]}-{'kap' if c[3] else 'poi'}-{c[4]}"
+            + (f"-sigma{c[5]:g}" if c[5] else ""))
+
+
 @functools.lru_cache(maxsize=None)
-def _oracle(dim, n, levels, kap):
+def _oracle(dim, n, levels, kap, sigma):
     kappa = W.kappa_lognormal(dim, n, 11) if kap else None
-    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother="rbgs", fp32=True)
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother="rbgs", fp32=True,
+                          sigma=sigma)
     return H, kappa
 
 
 @functools.lru_cache(maxsize=None)
-def _solver(dim, n, levels, kap, op):
+def _solver(dim, n, levels, kap, op, sigma):
     from paper_1609_04809_amd.mg import Solver
-    H, kappa = _oracle(dim, n, levels, kap)
+    H, kappa = _oracle(dim, n, levels, kap, sigma)
     return Solver(dim, n, levels, kappa=kappa, op=op, smoother="rbgs",
-                  precision="fp32_ir")
+                  precision="fp32_ir", sigma=sigma)
 
 
 def _ops(H, l, prec):
@@ -66,12 +77,12 @@ def _round(v, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-n{c[1]}-{'kap' if c[3] else 'poi'}-{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=_cid)
 def test_steps_match_oracle(case, prec):
     torch = torch_cuda()
-    dim, n, levels, kap, op = case
-    H, _ = _oracle(dim, n, levels, kap)
-    S = _solver(dim, n, levels, kap, op)
+    dim, n, levels, kap, op, sigma = case
+    H, _ = _oracle(dim, n, levels, kap, sigma)
+    S = _solver(dim, n, levels, kap, op, sigma)
     tdt = "float64" if prec == "fp64" else "float32"
     rng = np.random.default_rng(zlib.crc32(repr(case + (prec,)).encode()))
     for l in (0, 1):
@@ -156,12 +167,12 @@ def test_steps_match_oracle(case, prec):
     assert np.max(np.abs(got - want)) <= tol * np.max(np.abs(want)), "coarse solve"
 
 
-@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d-n{c[1]}-{'kap' if c[3] else 'poi'}-{c[4]}")
+@pytest.mark.parametrize("case", CASES, ids=_cid)
 def test_one_vcycle_matches_oracle(case):
     torch = torch_cuda()
-    dim, n, levels, kap, op = case
-    H, _ = _oracle(dim, n, levels, kap)
-    S = _solver(dim, n, levels, kap, op)
+    dim, n, levels, kap, op, sigma = case
+    H, _ = _oracle(dim, n, levels, kap, sigma)
+    S = _solver(dim, n, levels, kap, op, sigma)
     rng = np.random.default_rng(5)
     N = (n - 1) ** dim
     x = rng.uniform(-1, 1, N)

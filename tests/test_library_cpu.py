@@ -64,7 +64,11 @@ def test_options_validation_and_footprint():
                 dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
                 dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
                 dict(dim=3, n=16, levels=3, max_iter=0),
-                dict(dim=3, n=16, levels=3, flags=32),
+                dict(dim=3, n=16, levels=3, flags=64),
+                dict(dim=3, n=16, levels=3, sigma=-1.0),
+                dict(dim=3, n=16, levels=3, sigma=float("nan")),
+                dict(dim=3, n=16, levels=3, sigma=float("inf")),
+                dict(dim=3, n=16, levels=3, sigma=5.0, flags=16),
                 dict(dim=3, n=16, levels=3, flags=8, nu_pre=2, nu_post=1),
                 dict(dim=3, n=16, levels=3, cycle=3),
                 dict(dim=3, n=16, levels=3, flags=8, cycle="F")):
@@ -74,6 +78,20 @@ def test_options_validation_and_footprint():
         ctx = ctypes.c_void_p()
         st = L.mg_setup(ctypes.byref(o), None, None, ctypes.byref(ctx))
         assert st == mg.MG_E_ARG and not ctx.value
+
+
+def test_mass_shift_with_matrix_free_kappa_is_refused_before_device_work():
+    mg = _lib()
+    L = mg.lib()
+    o = mg.make_options(3, 16, 3, sigma=200.0)
+    ctx = ctypes.c_void_p()
+    # the refusal comes before any device access, so a dummy coefficient
+    # pointer is never touched
+    st = L.mg_setup(ctypes.byref(o), ctypes.c_void_p(256), None, ctypes.byref(ctx))
+    assert st == mg.MG_E_ARG and not ctx.value
+    assert "mass" in L.mg_last_error().decode()
+    ok = mg.make_options(3, 16, 3, sigma=200.0, flags=mg.FLAG_WARM)
+    assert L.mg_footprint_bytes(ctypes.byref(ok)) > 0
 
 
 def test_paper_dof_counts_through_the_library():
