@@ -211,12 +211,12 @@ def test_heat_profile_is_the_stated_solution():
     assert W.heat_lambda(3, 0.0) == pytest.approx(3 * np.pi ** 2 - 0.1, rel=1e-15)
 
 
-def test_cn_rhs_load_is_the_galerkin_integral_of_the_interpolated_source():
-    # b = cf * int f_h phi_i with f_h the Q1 (multilinear) interpolant of the
+def test_load_vector_is_the_galerkin_integral_of_the_interpolated_source():
+    # F = int f_h phi_i with f_h the Q1 (multilinear) interpolant of the
     # nodal source values: Gauss quadrature of f_h phi_i is exact, and a
     # lumped (diagonal) load would differ for rough nodal data
     from scipy.interpolate import RegularGridInterpolator
-    dim, n, cf = 3, 6, 2.5
+    dim, n = 3, 6
     f = np.random.default_rng(9).uniform(-1, 1, (n + 1) ** 3)
     c = np.arange(n + 1) / n
     interp = RegularGridInterpolator((c, c, c), f.reshape((n + 1,) * 3), method="linear")
@@ -225,7 +225,27 @@ def test_cn_rhs_load_is_the_galerkin_integral_of_the_interpolated_source():
         pts = np.stack([z.ravel(), y.ravel(), x.ravel()], axis=1)
         return interp(pts).reshape(x.shape)
 
-    b = OH.cn_rhs(dim, n, 40.0, np.zeros((n - 1) ** 3), None, 0.0, None, 0.0, f, cf)
-    np.testing.assert_allclose(b, cf * O.assemble_load_quadrature(dim, n, fh, q=3),
+    F = OH.load_vector(dim, n, f)
+    np.testing.assert_allclose(F, O.assemble_load_quadrature(dim, n, fh, q=3),
                                rtol=1e-12, atol=1e-15)
-    assert np.abs(b - cf * O.to_interior(dim, n, f.reshape((n + 1,) * 3)) / n ** 3).max() > 1e-4
+    assert np.abs(F - O.to_interior(dim, n, f.reshape((n + 1,) * 3)) / n ** 3).max() > 1e-4
+    # the right-hand side adds cf F to the operator terms
+    b0 = OH.cn_rhs(dim, n, 40.0, np.zeros((n - 1) ** 3), None, 0.0, None, 0.0, None, 0.0)
+    b1 = OH.cn_rhs(dim, n, 40.0, np.zeros((n - 1) ** 3), None, 0.0, None, 0.0, F, 2.5)
+    assert not np.any(b0)
+    np.testing.assert_array_equal(b1, 2.5 * F)
+
+
+def test_extrapolated_start_takes_fewer_cycles_to_the_same_solution():
+    # starting each solve from 2 u^n - u^{n-1} instead of u^n changes the
+    # iteration, not its limit: both loops agree to the solve tolerance,
+    # and the extrapolated start needs no more cycles
+    dt, steps, n = 0.01, 4, 16
+    w = W.HeatWorkload("t", 3, n, 3, dt, steps, 1e-10)
+    s, u0 = W.heat_inputs(w)
+    H = O.build_hierarchy(3, n, w.levels, sigma=w.sigma, nu_pre=3, nu_post=3)
+    lam = lambda t: W.heat_lambda(3, t)
+    ua, its_a, _ = OH.run(H, dt, steps, u0, s, W.heat_gamma, s, lam, w.tol)
+    ub, its_b, hb = OH.run(H, dt, steps, u0, s, W.heat_gamma, s, lam, w.tol, extrapolate=True)
+    assert sum(its_b) < sum(its_a) and its_b[0] == its_a[0]
+    np.testing.assert_allclose(ub, ua, rtol=0, atol=1e-9 * np.abs(ua).max())
