@@ -233,6 +233,64 @@ def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V")
     return res, roof, (b, kappa, u, k)
 
 
+def run_heat(name, steps=None, precision=None, extrapolate=False):
+    """The Crank-Nicolson time loop of the heat-equation model problem:
+    `steps` steps (default the workload's: T = 5 in steps of 0.01), each a
+    right-hand side and a solve warm-started from the previous step, timed
+    as a whole with every input resident; each solve starts from the last
+    step's solution, or with `extrapolate` from the linear extrapolation of
+    the last two.  Also the finest-level half-sweep of the face-coupled
+    operator timed with HIP events over one eager step, and the nodal error
+    against the paper's exact solution at the end."""
+    import torch
+    from paper_1609_04809_amd import workloads as W
+    from paper_1609_04809_amd.heat import HeatRun
+    from paper_1609_04809_amd.mg import PROF_SMOOTH, PROF_SMOOTH_PRO
+    w = W.HEAT_WORKLOADS[name]
+    steps = steps or w.steps
+    t0 = time.perf_counter()
+    R = HeatRun(w, precision=precision, extrapolate=extrapolate)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    R.reset()
+    R.step()                       # warm-up (captures the cycle graphs)
+    R.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its = R.run(steps)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    exact = W.heat_gamma(R.t) * R.u0
+    err = float((R.u - exact).abs().max() / exact.abs().max())
+    s = 8 if (precision or w.precision) == "fp64" else 4
+    per = stencil_halfsweep_bytes(w.n, s)
+    prof = {}
+    for key, kid in (("halfsweep", PROF_SMOOTH), ("prolong_fused", PROF_SMOOTH_PRO)):
+        R.S.profile(kid, True)
+        R.step()
+        launches, ms = R.S.profile_read()
+        R.S.profile(kid, False)
+        if launches:
+            avg = ms / 1e3 / launches
+            prof[key] = {"launches": launches, "avg_us": round(avg * 1e6, 2)}
+    hs = prof.get("halfsweep")
+    if hs:
+        ach = per / (hs["avg_us"] * 1e-6) / 1e9
+        hs.update({"achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
+                   "bytes_per_launch": int(per)})
+    R.close()
+    return {"workload": name, "dofs": w.dofs, "steps": steps, "dt": w.dt,
+            "t_end": round(steps * w.dt, 6), "seconds": round(t, 3),
+            "ms_per_step": round(t * 1e3 / steps, 3),
+            "MDOF_steps_per_s": round(w.dofs * steps / t / 1e6, 1),
+            "cycles_total": int(sum(its)), "cycles_per_step_mean": round(sum(its) / steps, 3),
+            "cycles_per_step_min": int(min(its)), "cycles_per_step_max": int(max(its)),
+            "tol": w.tol, "smoother": f"{w.smoother} V({w.nu_pre},{w.nu_post})",
+            "levels": w.levels, "precision": precision or w.precision,
+            "start": "extrapolated" if extrapolate else "previous step",
+            "max_nodal_error_vs_exact": err, "setup_s": round(setup_s, 3), **prof}
+
+
 def cpu_baseline(name):
     """The oracle (test infrastructure) on the same workload: one full solve,
     assembly excluded from the timed region."""
@@ -278,6 +336,14 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--workload", default="poisson3d_128_csr_rbgs")
+    ap.add_argument("--heat-steps", type=int, default=0,
+                    help="Crank-Nicolson steps of the heat workload (0: all 500)")
+    ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation time loop")
+    ap.add_argument("--heat-extrapolate", action="store_true",
+                    help="with --heat-only: start each solve from the extrapolated guess")
+    ap.add_argument("--heat-only", default="",
+                    help="run only the heat time loop in this precision (fp64 or fp32_ir) "
+                         "and print its result (for profiling)")
     ap.add_argument("--copy-mib", type=int, default=1024,
                     help="size of the reference device copy (attainable bandwidth; "
                          "also the known-size kernel that scales PMC byte counters)")
@@ -290,6 +356,13 @@ def main():
     from paper_1609_04809_amd import workloads as W
     assert torch.cuda.is_available(), "needs a GPU"
     torch.cuda.set_device(0)
+    if args.heat_only:
+        copy_gbs = reference_copy(args.copy_mib)
+        r = run_heat("heat3d_512_cn", args.heat_steps or None, precision=args.heat_only,
+                     extrapolate=args.heat_extrapolate)
+        log(f"[bench] heat3d_512_cn ({args.heat_only}): {r}")
+        print(json.dumps({"heat": r, "copy_reference_GBs": copy_gbs}), flush=True)
+        return
     name = args.workload
     w = W.WORKLOADS[name]
     copy_gbs = reference_copy(args.copy_mib)
@@ -324,6 +397,16 @@ def main():
                 log(f"[bench] {other} ({kind}-cycle): {r['MDOF_per_s']} MDOF/s, "
                     f"{r['cycles']} cycles, {r['ms_per_solve']} ms/solve")
                 extra.append(r)
+    heat = None
+    if not args.no_extra and not args.no_heat:
+        heat = []
+        for prec, ex in (("fp64", False), ("fp64", True), ("fp32_ir", True)):
+            r = run_heat("heat3d_512_cn", args.heat_steps or None, precision=prec, extrapolate=ex)
+            log(f"[bench] heat3d_512_cn ({prec}, {r['start']}): {r['steps']} steps in "
+                f"{r['seconds']} s, "
+                f"{r['ms_per_step']} ms/step, {r['cycles_per_step_mean']} cycles/step, "
+                f"error vs exact {r['max_nodal_error_vs_exact']:.3e}; {r.get('halfsweep')}")
+            heat.append(r)
     serving = None
     if not args.no_serve:
         from paper_1609_04809_amd import serve_load
@@ -368,6 +451,7 @@ def main():
         "cpu_baseline": cpu,
         "copy_reference_GBs": copy_gbs,
         "extra": extra,
+        "heat": heat,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -172,29 +172,44 @@ mg_status mg_solve(mg_ctx* ctx, const double* b_dev, double* u_dev, double tol,
 /* Right-hand side of one Crank-Nicolson step of the heat equation (the
  * model problem of Sec. 6.2) for a context with A = K + sigma M, sigma =
  * 2/dt (kappa = 1): on the unknowns
- *   b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f,
- * the Crank-Nicolson equation M (u' - u)/dt + K (u' + u)/2 = M (f + f')/2
+ *   b = (sigma M - K) x0 - (sigma M + K) x1 + cf F,
+ * the Crank-Nicolson equation M (u' - u)/dt + K (u' + u)/2 = (F + F')/2
  * times 2/dt with the Dirichlet values of u' moved to the right-hand side.
- *   u_dev   device, (n+1)^dim doubles: the solution at t_n on the unknowns
- *           (boundary entries ignored), e.g. the previous mg_solve output.
- *   g0_dev  device, (n+1)^dim doubles or NULL (= 0): x0 takes c0 * g0 on the
- *           boundary nodes (the Dirichlet data at t_n); interior entries
- *           ignored.
- *   g1_dev  device, (n+1)^dim doubles or NULL: x1 = c1 * g1 on the boundary
- *           nodes, 0 inside (the Dirichlet data at t_{n+1}).
- *   f_dev   device, (n+1)^dim doubles or NULL: nodal source values on every
- *           node (the load is M f, the Galerkin load of the source's Q1
- *           interpolant), scaled by cf (e.g. f(t_n) + f(t_{n+1}) for
- *           separable data).
- *   b_dev   device, (n+1)^dim doubles, out: boundary entries set to 0; must
- *           not alias the inputs.
- * The same arrays may serve as g0 and g1 (time-separable Dirichlet data).
- * FP64 in every context.  Errors: MG_E_ARG (NULL u or b, aliasing, a
- * context with per-cell kappa).  Stream-ordered, no synchronisation. */
-mg_status mg_cn_rhs(mg_ctx* ctx, const double* u_dev, const double* g0_dev,
-                    double c0, const double* g1_dev, double c1,
-                    const double* f_dev, double cf, double* b_dev,
+ *   u_dev      device, (n+1)^dim doubles: the solution at t_n on the
+ *              unknowns, e.g. the previous mg_solve output; boundary entries
+ *              ignored (they must be finite).
+ *   guess_dev  device, (n+1)^dim doubles or NULL, in/out: on entry the
+ *              solution at t_{n-1}; on return 2 u - guess on the unknowns,
+ *              the linear extrapolation of the solution to t_{n+1}, a start
+ *              for the next solve (MG_FLAG_WARM).  May not alias u.
+ *   g0_dev     device, (n+1)^dim doubles or NULL (= 0): x0 takes c0 * g0 on
+ *              the boundary nodes (the Dirichlet data at t_n); interior
+ *              entries ignored.
+ *   g1_dev     device, (n+1)^dim doubles or NULL: x1 = c1 * g1 on the
+ *              boundary nodes, 0 inside (the Dirichlet data at t_{n+1}).
+ *   F_dev      device, (n+1)^dim doubles or NULL: a load vector on the
+ *              unknowns (boundary entries ignored), scaled by cf -- e.g. the
+ *              load of a source profile from mg_apply_mass and cf =
+ *              lambda(t_n) + lambda(t_{n+1}) for a source lambda(t) f(x).
+ *   b_dev      device, (n+1)^dim doubles, out: boundary entries set to 0.
+ * The same array may serve as g0 and g1 (time-separable Dirichlet data); b
+ * must not alias any input.  FP64 in every context.  Errors: MG_E_ARG (NULL
+ * u or b, aliasing, non-finite scalars, a context with per-cell kappa).
+ * Stream-ordered, no synchronisation. */
+mg_status mg_cn_rhs(mg_ctx* ctx, const double* u_dev, double* guess_dev,
+                    const double* g0_dev, double c0, const double* g1_dev,
+                    double c1, const double* F_dev, double cf, double* b_dev,
                     void* stream);
+
+/* Load vector of nodal data: F = M f on the unknowns of level 0, with M the
+ * Q1 mass matrix over all nodes -- the Galerkin load of the Q1 interpolant
+ * of f (Sec. 2).
+ *   f_dev   device, (n+1)^dim doubles, every node (boundary included).
+ *   F_dev   device, (n+1)^dim doubles, out: boundary entries set to 0; must
+ *           not alias f.
+ * FP64.  Errors: MG_E_ARG.  Stream-ordered, no synchronisation. */
+mg_status mg_apply_mass(mg_ctx* ctx, const double* f_dev, double* F_dev,
+                        void* stream);
 
 /* Release a context and its device memory (NULL is ignored). */
 void mg_destroy(mg_ctx* ctx);

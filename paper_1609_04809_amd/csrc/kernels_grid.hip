@@ -433,6 +433,9 @@ constexpr int SW_RESID = 3;
 constexpr int SW_HEAD_RB0 = 4;
 constexpr int SW_HEAD_JAC = 5;
 constexpr int SW_APPLY = 6;  // out = A x with partial sums of x.(A x)
+// out = W x + omega F (F in the b slot; W the launch's operator weights);
+// with Item::e != nullptr also e = 2 x - e at every unknown (node-local)
+constexpr int SW_CN = 7;
 constexpr int SW_TX = 128;  // unknowns per tile in x (2 per thread)
 constexpr int SW_TY = 4;    // unknowns per tile in y (1 per thread row)
 constexpr int SW_LX = SW_TX + 2, SW_LY = SW_TY + 2;
@@ -640,10 +643,16 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   const int colour = MODE == SM_RB1 ? 1 : 0;
   const long pb0 = min(i, n - 1) + min(j, n) * sy;  // clamped into the grid
   T bpf[2] = {T(0), T(0)};
+  T* const ge = MODE == SW_CN ? (T*)const_cast<void*>(I.e) : nullptr;
+  T gpf[2] = {T(0), T(0)};
   auto prefetch_b = [&](int k) {
     const long p = pb0 + (long)min(k, n) * sz;
 #pragma unroll
     for (int u = 0; u < 2; ++u) bpf[u] = b[p + u];
+    if (MODE == SW_CN && ge != nullptr) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) gpf[u] = ge[p + u];
+    }
   };
   auto store = [&](int k, int u, T v) { out[i + u + j * sy + (long)k * sz] = v; };
   double sq = 0.0;
@@ -733,6 +742,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       prefetch_k(p + 1);
     }
     const T bcur[2] = {bpf[0], bpf[1]};  // b of plane p-1 (red-black: [0], its updated unknown)
+    const T gcur[2] = {gpf[0], gpf[1]};  // SW_CN: the guess at plane p-1
     if (!RB && MODE != SW_APPLY) prefetch_b(p);
     __syncthreads();
     T w[3][4];
@@ -789,7 +799,10 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
           dg = op.wc;
         }
         const T res = (RB ? bcur[0] : bcur[u]) - ax;
-        if (MODE == SW_APPLY) {
+        if (MODE == SW_CN) {
+          store(k, u, ax + omega * bcur[u]);
+          if (ge != nullptr) ge[i + u + j * sy + (long)k * sz] = T(2) * x1[q] - gcur[u];
+        } else if (MODE == SW_APPLY) {
           store(k, u, ax);
           sq += (double)x1[q] * (double)ax;
         } else if (MODE == SW_RESID) {
@@ -1536,18 +1549,22 @@ __global__ void k_count_bad_kappa(const double* __restrict__ k, long count, int*
 
 // ---------------------------------------------------------------------------
 // Crank-Nicolson right-hand side (launch_cn_rhs), FP64:
-//   b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f  on the unknowns,
+//   b = Wb x0 - Wa x1 + cf F  on the unknowns,
 // x0 = u inside and c0 g0 on the boundary, x1 = c1 g1 on the boundary and 0
-// inside.  One thread per unknown; the 3^dim neighbours are summed per
-// class (centre, faces, edges, corners) and weighted per class.  Blocks
-// whose unknowns all lie away from the boundary read u without boundary
-// tests; the others select per neighbour.
+// inside; guess (optional) = 2 u - guess.  k_cn_rhs: one thread per
+// unknown, the 3^dim neighbours summed per class (centre, faces, edges,
+// corners) and weighted per class; blocks whose unknowns all lie away from
+// the boundary read u without boundary tests.  On the large 3D levels the
+// interior part Wb u + cf F comes from k_sweep3 (SW_CN) with u's staged
+// boundary values, and k_cn_bnd then adds, at the unknowns next to the
+// boundary, Wb (c0 g0 - u) - Wa c1 g1 over their boundary neighbours.
 // ---------------------------------------------------------------------------
 template <int DIM>
 __global__ __launch_bounds__(256) void k_cn_rhs(Geo g, CnWeights w, const double* __restrict__ u,
+                                                double* __restrict__ guess,
                                                 const double* __restrict__ g0,
                                                 const double* __restrict__ g1,
-                                                const double* __restrict__ f,
+                                                const double* __restrict__ F,
                                                 double* __restrict__ b) {
   const int n = g.n, m = n - 1;
   const int i0 = 1 + blockIdx.x * BX, j0 = 1 + blockIdx.y * BY;
@@ -1558,9 +1575,9 @@ __global__ __launch_bounds__(256) void k_cn_rhs(Geo g, CnWeights w, const double
   const bool inner = i0 > 1 && i0 + BX - 1 < m && j0 > 1 && j0 + BY - 1 < m &&
                      (DIM == 2 || (k > 1 && k < m));
   constexpr int DZ = DIM == 3 ? 1 : 0;
-  double s0[DIM + 1], s1[DIM + 1], sf[DIM + 1];
+  double s0[DIM + 1], s1[DIM + 1];
 #pragma unroll
-  for (int c = 0; c <= DIM; ++c) s0[c] = s1[c] = sf[c] = 0.0;
+  for (int c = 0; c <= DIM; ++c) s0[c] = s1[c] = 0.0;
   if (inner) {
 #pragma unroll
     for (int dz = -DZ; dz <= DZ; ++dz)
@@ -1569,9 +1586,7 @@ __global__ __launch_bounds__(256) void k_cn_rhs(Geo g, CnWeights w, const double
 #pragma unroll
         for (int dx = -1; dx <= 1; ++dx) {
           const int cls = (dx != 0) + (dy != 0) + (dz != 0);
-          const long q = p + dx + dy * g.sy + dz * g.sz;
-          s0[cls] += u[q];
-          if (f) sf[cls] += f[q];
+          s0[cls] += u[p + dx + dy * g.sy + dz * g.sz];
         }
   } else {
 #pragma unroll
@@ -1591,16 +1606,64 @@ __global__ __launch_bounds__(256) void k_cn_rhs(Geo g, CnWeights w, const double
           } else {
             s0[cls] += u[q];
           }
-          if (f) sf[cls] += f[q];
         }
   }
-  double acc = 0.0, accf = 0.0;
+  double acc = 0.0;
 #pragma unroll
-  for (int c = 0; c <= DIM; ++c) {
-    acc += w.wb[c] * s0[c] - w.wa[c] * s1[c];
-    accf += w.wm[c] * sf[c];
+  for (int c = 0; c <= DIM; ++c) acc += w.wb[c] * s0[c] - w.wa[c] * s1[c];
+  b[p] = F ? acc + w.cf * F[p] : acc;
+  if (guess) guess[p] = 2.0 * u[p] - guess[p];
+}
+
+// Boundary terms after a k_sweep3 SW_CN pass (3D): thread t covers one
+// unknown of the layer next to the boundary, enumerated once each: the
+// planes k = 1 and k = m whole, then for 1 < k < m the rows j = 1 and j = m,
+// then the columns i = 1 and i = m of the remaining rows.
+__global__ __launch_bounds__(256) void k_cn_bnd(Geo g, CnWeights w, const double* __restrict__ u,
+                                                const double* __restrict__ g0,
+                                                const double* __restrict__ g1,
+                                                double* __restrict__ b) {
+  const int n = g.n, m = n - 1;
+  const long P = (long)m * m;                 // plane k = 1 or k = m
+  const long R = 2L * m * (m - 2);            // rows j = 1, m of the inner planes
+  const long C = 2L * (m - 2) * (m - 2);      // columns i = 1, m of the rest
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  int i, j, k;
+  if (t < 2 * P) {
+    k = t < P ? 1 : m;
+    const long r = t < P ? t : t - P;
+    i = 1 + (int)(r % m);
+    j = 1 + (int)(r / m);
+  } else if ((t -= 2 * P) < R) {
+    const long half = (long)m * (m - 2);
+    j = t < half ? 1 : m;
+    const long r = t < half ? t : t - half;
+    i = 1 + (int)(r % m);
+    k = 2 + (int)(r / m);
+  } else if ((t -= R) < C) {
+    const long half = (long)(m - 2) * (m - 2);
+    i = t < half ? 1 : m;
+    const long r = t < half ? t : t - half;
+    j = 2 + (int)(r % (m - 2));
+    k = 2 + (int)(r / (m - 2));
+  } else {
+    return;
   }
-  b[p] = acc + w.cf * accf;
+  const long p = i + j * g.sy + (long)k * g.sz;
+  double s0[4] = {0.0, 0.0, 0.0, 0.0}, s1[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        const int qi = i + dx, qj = j + dy, qk = k + dz;
+        if (!(qi == 0 || qi == n || qj == 0 || qj == n || qk == 0 || qk == n)) continue;
+        const int cls = (dx != 0) + (dy != 0) + (dz != 0);
+        const long q = p + dx + dy * g.sy + dz * g.sz;
+        s0[cls] += (g0 ? w.c0 * g0[q] : 0.0) - u[q];
+        if (g1) s1[cls] += w.c1 * g1[q];
+      }
+  double acc = 0.0;
+  for (int c = 0; c <= 3; ++c) acc += w.wb[c] * s0[c] - w.wa[c] * s1[c];
+  b[p] += acc;
 }
 
 // v = 0 on the boundary nodes; thread t covers one node of the 2 dim faces.
@@ -1879,13 +1942,40 @@ void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, 
 #undef L_AD
 }
 
-void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, const double* g0,
-                   const double* g1, const double* f, double* b, hipStream_t s) {
+void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, double* guess,
+                   const double* g0, const double* g1, const double* F, double* b,
+                   hipStream_t s) {
+  if (use_sweep3(g)) {
+    // the interior part with the operator Wb (face-coupled constant kind),
+    // then the boundary terms on the layer next to the boundary
+    StencilParams<double> op{OP_MASS, w.wb[0], w.wb[2], w.wb[3], 0.0, w.wb[1]};
+    Batch B{};
+    B.count = 1;
+    B.it[0].a = u;
+    B.it[0].b = F ? F : u;  // without F: cf = 0 and any readable array
+    B.it[0].c = b;
+    B.it[0].e = guess;
+    launch_sweep3<double, OP_MASS, SW_CN, false, false>(g, op, F ? w.cf : 0.0, B, s);
+    const long m = g.n - 1;
+    const long total = 2 * m * m + 2 * m * (m - 2) + 2 * (m - 2) * (m - 2);
+    hipLaunchKernelGGL(k_cn_bnd, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, w,
+                       u, g0, g1, b);
+    return;
+  }
   const dim3 gr = node_grid(g, 1), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, g0, g1, f, b);
+    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
   else
-    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, g0, g1, f, b);
+    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
+}
+
+void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, const double* g0,
+                         double* b, hipStream_t s) {
+  const dim3 gr = node_grid(g, 1), bl(BX, BY);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
+  else
+    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
 }
 
 void launch_zero_boundary(const Geo& g, double* v, hipStream_t s) {

@@ -116,8 +116,12 @@ struct mg_ctx {
   // one cached graph per iteration kind (plain, first fused, steady fused,
   // first CG, steady CG), valid for the (u, b) it was captured with
   static constexpr int kIterKinds = 5;
-  hipGraphExec_t gexec[kIterKinds] = {};
-  const void* gkey[kIterKinds][2] = {};
+  // two cached graphs per iteration kind, keyed by the (u, b) buffers, so
+  // that solves alternating between two solution buffers replay both
+  static constexpr int kGraphSlots = 2;
+  hipGraphExec_t gexec[kIterKinds][kGraphSlots] = {};
+  const void* gkey[kIterKinds][kGraphSlots][2] = {};
+  int glast[kIterKinds] = {};  // most recently used slot
   // profiling
   int prof_kernel = -1;
   bool prof_on = false;

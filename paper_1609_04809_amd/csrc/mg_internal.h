@@ -242,16 +242,22 @@ template <typename T>
 void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, hipStream_t s);
 
 // Crank-Nicolson right-hand side (FP64) on the unknowns of a level with
-// kappa = 1:  b = (sigma M - K) x0 - (sigma M + K) x1 + cf M f, where x0 is
-// u inside and c0 g0 on the boundary, x1 is c1 g1 on the boundary and 0
-// inside (g0, g1, f may be nullptr: 0).  Weights per neighbour class
-// |dx| + |dy| (+ |dz|): wb of sigma M - K, wa of sigma M + K, wm of M.
+// kappa = 1:  b = Wb x0 - Wa x1 + cf F, where x0 is u inside and c0 g0 on
+// the boundary, x1 is c1 g1 on the boundary and 0 inside, and Wb, Wa are
+// constant 3^dim stencils with weights wb, wa per neighbour class |dx| +
+// |dy| (+ |dz|) (sigma M - K and sigma M + K; with wb = the mass weights,
+// u = g0 = f, c0 = 1 and wa = 0 this is the load M f).  g0, g1, F and
+// guess may be nullptr; guess (in/out) becomes 2 u - guess.
 struct CnWeights {
-  double wb[4], wa[4], wm[4];
+  double wb[4], wa[4];
   double c0, c1, cf;
 };
-void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, const double* g0,
-                   const double* g1, const double* f, double* b, hipStream_t s);
+void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, double* guess,
+                   const double* g0, const double* g1, const double* F, double* b,
+                   hipStream_t s);
+// The same with the node kernel at every size, without x1, F and guess.
+void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, const double* g0,
+                         double* b, hipStream_t s);
 // v = 0 on the boundary nodes of the level (interior untouched).
 void launch_zero_boundary(const Geo& g, double* v, hipStream_t s);
 

@@ -933,14 +933,15 @@ Sink launch_sink(mg_ctx* c, hipStream_t s) {
   };
 }
 
-void drop_graph(mg_ctx* c, int kind) {
-  if (c->gexec[kind]) hipGraphExecDestroy(c->gexec[kind]);
-  c->gexec[kind] = nullptr;
-  c->gkey[kind][0] = c->gkey[kind][1] = nullptr;
+void drop_graph(mg_ctx* c, int kind, int slot) {
+  if (c->gexec[kind][slot]) hipGraphExecDestroy(c->gexec[kind][slot]);
+  c->gexec[kind][slot] = nullptr;
+  c->gkey[kind][slot][0] = c->gkey[kind][slot][1] = nullptr;
 }
 
 void drop_graphs(mg_ctx* c) {
-  for (int k = 0; k < mg_ctx::kIterKinds; ++k) drop_graph(c, k);
+  for (int k = 0; k < mg_ctx::kIterKinds; ++k)
+    for (int q = 0; q < mg_ctx::kGraphSlots; ++q) drop_graph(c, k, q);
 }
 
 // Run one iteration of the given kind: replay the cached graph (captured on
@@ -953,8 +954,13 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s, in
     return MG_OK;
   }
   const void* key[2] = {u, b};
-  if (!c->gexec[kind] || memcmp(key, c->gkey[kind], sizeof key) != 0) {
-    drop_graph(c, kind);
+  int slot = -1;
+  for (int q = 0; q < mg_ctx::kGraphSlots; ++q)
+    if (c->gexec[kind][q] && memcmp(key, c->gkey[kind][q], sizeof key) == 0) slot = q;
+  if (slot < 0) {
+    // replace the slot used less recently
+    slot = (c->glast[kind] + 1) % mg_ctx::kGraphSlots;
+    drop_graph(c, kind, slot);
     hipGraph_t graph = nullptr;
     HIP_TRY(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     emit_iteration(c, launch_sink(c, c->cap), u, b, kind);
@@ -965,15 +971,16 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s, in
       return fail(MG_E_HIP, "graph capture failed: %s / %s", hipGetErrorString(le),
                   hipGetErrorString(ee));
     }
-    hipError_t ie = hipGraphInstantiate(&c->gexec[kind], graph, nullptr, nullptr, 0);
+    hipError_t ie = hipGraphInstantiate(&c->gexec[kind][slot], graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (ie != hipSuccess) {
-      c->gexec[kind] = nullptr;
+      c->gexec[kind][slot] = nullptr;
       return fail(MG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
     }
-    memcpy(c->gkey[kind], key, sizeof key);
+    memcpy(c->gkey[kind][slot], key, sizeof key);
   }
-  HIP_TRY(hipGraphLaunch(c->gexec[kind], s));
+  c->glast[kind] = slot;
+  HIP_TRY(hipGraphLaunch(c->gexec[kind][slot], s));
   return MG_OK;
 }
 
@@ -1294,13 +1301,15 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   return fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, c->o.max_iter);
 }
 
-mg_status mg_cn_rhs(mg_ctx* c, const double* u, const double* g0, double c0, const double* g1,
-                    double c1, const double* f, double cf, double* b, void* stream) {
+mg_status mg_cn_rhs(mg_ctx* c, const double* u, double* guess, const double* g0, double c0,
+                    const double* g1, double c1, const double* F, double cf, double* b,
+                    void* stream) {
   if (!c || !u || !b) return fail(MG_E_ARG, "NULL argument");
   if (c->kappa) return fail(MG_E_ARG, "mg_cn_rhs needs a context with kappa = 1");
-  if ((const double*)b == u || (const double*)b == g0 || (const double*)b == g1 ||
-      (const double*)b == f)
+  if ((const double*)b == u || b == guess || (const double*)b == g0 ||
+      (const double*)b == g1 || (const double*)b == F)
     return fail(MG_E_ARG, "b must not alias an input");
+  if ((const double*)guess == u) return fail(MG_E_ARG, "guess must not alias u");
   if (!(std::isfinite(c0) && std::isfinite(c1) && std::isfinite(cf)))
     return fail(MG_E_ARG, "c0, c1 and cf must be finite");
   const Level& L0 = c->lv[0];
@@ -1311,14 +1320,31 @@ mg_status mg_cn_rhs(mg_ctx* c, const double* u, const double* g0, double c0, con
     const double wm = mass_weight(dim, h, cls), wk = stiff_weight(dim, h, cls);
     w.wb[cls] = sg * wm - wk;
     w.wa[cls] = sg * wm + wk;
-    w.wm[cls] = wm;
   }
   w.c0 = c0;
   w.c1 = c1;
   w.cf = cf;
   hipStream_t s = as_stream(stream);
   launch_zero_boundary(L0.g, b, s);
-  launch_cn_rhs(L0.g, w, u, g0, g1, f, b, s);
+  launch_cn_rhs(L0.g, w, u, guess, g0, g1, F, b, s);
+  HIP_TRY(hipGetLastError());
+  return MG_OK;
+}
+
+mg_status mg_apply_mass(mg_ctx* c, const double* f, double* F, void* stream) {
+  if (!c || !f || !F) return fail(MG_E_ARG, "NULL argument");
+  if ((const double*)F == f) return fail(MG_E_ARG, "F must not alias f");
+  const Level& L0 = c->lv[0];
+  const int dim = c->o.dim;
+  const double h = 1.0 / L0.g.n;
+  // the node kernel of the right-hand side with x0 = f on every node and
+  // the mass weights: F = M f
+  CnWeights w{};
+  for (int cls = 0; cls <= dim; ++cls) w.wb[cls] = mass_weight(dim, h, cls);
+  w.c0 = 1.0;
+  hipStream_t s = as_stream(stream);
+  launch_zero_boundary(L0.g, F, s);
+  launch_cn_rhs_nodes(L0.g, w, f, f, F, s);
   HIP_TRY(hipGetLastError());
   return MG_OK;
 }

@@ -73,8 +73,9 @@ SIGNATURES = {
     "mg_apply_coarse_solve": (_I, [_VP, _I, _VP, _VP, _VP]),
     "mg_vcycle": (_I, [_VP, _I, _VP, _VP, _VP]),
     "mg_norm2": (_I, [_VP, _I, _I, _VP, ctypes.POINTER(ctypes.c_double), _VP]),
-    "mg_cn_rhs": (_I, [_VP, _VP, _VP, ctypes.c_double, _VP, ctypes.c_double, _VP,
+    "mg_cn_rhs": (_I, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, ctypes.c_double, _VP,
                        ctypes.c_double, _VP, _VP]),
+    "mg_apply_mass": (_I, [_VP, _VP, _VP, _VP]),
     "mg_profile_enable": (_I, [_VP, _I, _I]),
     "mg_profile_read": (_I, [_VP, ctypes.POINTER(ctypes.c_long),
                              ctypes.POINTER(ctypes.c_double)]),
@@ -226,15 +227,24 @@ class Solver:
         k = iters.value
         return u, k, list(hist[: k + 1]), STATUS_NAMES[st]
 
-    def cn_rhs(self, u, g0=None, c0=0.0, g1=None, c1=0.0, f=None, cf=0.0, b=None):
+    def cn_rhs(self, u, g0=None, c0=0.0, g1=None, c1=0.0, F=None, cf=0.0, b=None, guess=None):
         """Crank-Nicolson right-hand side b = (sigma M - K) x0 - (sigma M +
-        K) x1 + cf M f (x0 = u inside, c0 g0 on the boundary; x1 = c1 g1 on
-        the boundary); device float64 node tensors, None for absent data."""
+        K) x1 + cf F (x0 = u inside, c0 g0 on the boundary; x1 = c1 g1 on
+        the boundary; F a load vector); with `guess` (the solution one step
+        back) also guess <- 2 u - guess.  Device float64 node tensors, None
+        for absent data."""
         if b is None:
             b = torch.empty_like(u)
-        _check(lib().mg_cn_rhs(self._ctx, _ptr(u), _ptr(g0), float(c0), _ptr(g1), float(c1),
-                               _ptr(f), float(cf), _ptr(b), _stream()))
+        _check(lib().mg_cn_rhs(self._ctx, _ptr(u), _ptr(guess), _ptr(g0), float(c0), _ptr(g1),
+                               float(c1), _ptr(F), float(cf), _ptr(b), _stream()))
         return b
+
+    def mass(self, f, F=None):
+        """Load vector F = M f of nodal values f (device float64 node tensor)."""
+        if F is None:
+            F = torch.empty_like(f)
+        _check(lib().mg_apply_mass(self._ctx, _ptr(f), _ptr(F), _stream()))
+        return F
 
     # -- single steps
     def _prec(self, t):

@@ -127,26 +127,30 @@ def test_warm_start_from_zero_equals_cold_start_bitwise():
 def _cn_inputs(dim, n, seed):
     rng = np.random.default_rng(seed)
     N = (n + 1) ** dim
-    u = W.interior_to_full(dim, n, rng.uniform(-1, 1, (n - 1) ** dim))
-    # boundary data in g0/g1 and junk inside (ignored); f on every node
-    g0, g1, f = rng.uniform(-1, 1, N), rng.uniform(-1, 1, N), rng.uniform(-1, 1, N)
-    return u, g0, g1, f
+    # u with junk on the boundary (ignored), g0/g1 with junk inside
+    # (ignored), F with junk on the boundary (ignored), a guess
+    u, g0, g1, F, guess = (rng.uniform(-1, 1, N) for _ in range(5))
+    return u, g0, g1, F, guess
 
 
-@pytest.mark.parametrize("dim,n,levels,op", [(3, 80, 5, "stencil"), (3, 9, 1, "stencil"),
-                                             (2, 160, 6, "stencil"), (3, 36, 3, "csr"),
+@pytest.mark.parametrize("dim,n,levels,op", [(3, 80, 5, "stencil"), (3, 40, 3, "csr"),
+                                             (3, 9, 1, "stencil"), (2, 160, 6, "stencil"),
                                              (2, 5, 1, "stencil")])
 def test_cn_rhs_matches_oracle(dim, n, levels, op):
-    """Ragged tiles (79 = 64 + 15 unknowns per row), a grid where every
-    block touches the boundary, 2D; also with absent data (NULL g0, g1, f)."""
+    """The plane-marching path with its boundary pass (3D n >= 32: ragged
+    tiles, 79 = 64 + 15 and 39 = 32 + 7 unknowns per row), the node kernel
+    (a grid where every block touches the boundary, 2D); absent data; the
+    extrapolated guess; the load vector M f."""
     torch = torch_cuda()
     from paper_1609_04809_amd.mg import Solver
     sigma = 200.0
-    u, g0, g1, f = _cn_inputs(dim, n, 51)
+    u, g0, g1, F, guess = _cn_inputs(dim, n, 51)
     c0, c1, cf = 0.93, 0.91, 57.3
     KM = O.assemble_full(dim, n)
     K, M = KM
-    want = OH.cn_rhs(dim, n, sigma, W.full_to_interior(dim, n, u), g0, c0, g1, c1, f, cf, KM)
+    ui = W.full_to_interior(dim, n, u)
+    Fi = W.full_to_interior(dim, n, F)
+    want = OH.cn_rhs(dim, n, sigma, ui, g0, c0, g1, c1, Fi, cf, KM)
     # error scale: the terms' magnitudes
     bm = np.ones((n + 1,) * dim, dtype=bool)
     bm[(slice(1, n),) * dim] = False
@@ -154,24 +158,35 @@ def test_cn_rhs_matches_oracle(dim, n, levels, op):
     ax0 = np.where(bm, abs(c0 * g0), abs(u))
     ax1 = np.where(bm, abs(c1 * g1), 0.0)
     absB = abs(sigma * M) + abs(K)
-    scale_full = absB @ ax0 + absB @ ax1 + abs(cf) * (abs(M) @ abs(f))
-    scale = W.full_to_interior(dim, n, scale_full)
+    # (the boundary pass adds and removes u's boundary values: count them)
+    scale_full = absB @ (ax0 + np.where(bm, abs(u), 0.0)) + absB @ ax1
+    scale = W.full_to_interior(dim, n, scale_full) + abs(cf * Fi)
     with Solver(dim, n, levels, op=op, sigma=sigma) as S:
         td = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
-        b = S.cn_rhs(td(u), td(g0), c0, td(g1), c1, td(f), cf)
+        gd = td(guess)
+        b = S.cn_rhs(td(u), td(g0), c0, td(g1), c1, td(F), cf, guess=gd)
         assert_scaled_close(host_int(dim, n, b), want, scale, EPS64, what="cn_rhs")
         assert boundary_is_zero(dim, n, b)
+        np.testing.assert_array_equal(host_int(dim, n, gd),
+                                      2.0 * ui - W.full_to_interior(dim, n, guess))
         b2 = S.cn_rhs(td(u))
-        want2 = OH.cn_rhs(dim, n, sigma, W.full_to_interior(dim, n, u), None, 0, None, 0, None,
-                          0, KM)
+        want2 = OH.cn_rhs(dim, n, sigma, ui, None, 0, None, 0, None, 0, KM)
         assert_scaled_close(host_int(dim, n, b2), want2, scale, EPS64, what="cn_rhs no data")
+        # load vector of nodal values
+        f = np.random.default_rng(52).uniform(-1, 1, (n + 1) ** dim)
+        Fd = S.mass(td(f))
+        assert_scaled_close(host_int(dim, n, Fd), OH.load_vector(dim, n, f, KM),
+                            W.full_to_interior(dim, n, abs(M) @ abs(f)), EPS64, what="mass")
+        assert boundary_is_zero(dim, n, Fd)
 
 
-def test_cn_time_loop_matches_oracle():
+@pytest.mark.parametrize("extrapolate", [False, True])
+def test_cn_time_loop_matches_oracle(extrapolate):
     """Ten Crank-Nicolson steps of the model problem on 64^3 cells
-    (warm-started V(3,3) solves to 1e-10) against the oracle's loop, and
-    the error against the paper's exact solution."""
-    torch = torch_cuda()
+    (warm-started V(3,3) solves to 1e-10, from u^n or from 2 u^n - u^{n-1})
+    against the oracle's loop, and the error against the paper's exact
+    solution."""
+    torch_cuda()
     from paper_1609_04809_amd.heat import HeatRun
     w = W.HEAT_WORKLOADS["heat3d_64_cn"]
     s, u0 = W.heat_inputs(w)
@@ -179,8 +194,8 @@ def test_cn_time_loop_matches_oracle():
     H = O.build_hierarchy(w.dim, w.n, w.levels, sigma=w.sigma, nu_pre=w.nu_pre,
                           nu_post=w.nu_post)
     u_or, its_or, _ = OH.run(H, w.dt, w.steps, u0, s, W.heat_gamma, s,
-                             lambda t: W.heat_lambda(w.dim, t), tol)
-    with HeatRun(w, tol=tol) as R:
+                             lambda t: W.heat_lambda(w.dim, t), tol, extrapolate=extrapolate)
+    with HeatRun(w, tol=tol, extrapolate=extrapolate) as R:
         R.reset()
         its = R.run(w.steps)
         u = host_int(w.dim, w.n, R.u)
@@ -225,9 +240,9 @@ def test_full_size_cn_steps_on_sampled_nodes():
                  [2, 2, 2], [n // 2, n // 2, 1], [255, 256, 257], [64, 192, 511]]
     idx = nodes[:, 0] + (n + 1) * (nodes[:, 1] + (n + 1) * nodes[:, 2])
     sig = w.sigma
-    with HeatRun(w, tol=w.tol) as R:
+    with HeatRun(w, tol=w.tol, extrapolate=True) as R:
         R.reset()
-        for step in range(2):
+        for step in range(3):
             t0, t1 = step * w.dt, (step + 1) * w.dt
             u_prev = host_full(R.u)
             R.step()
