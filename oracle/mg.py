@@ -14,6 +14,13 @@ design notes of the repository):
   values at the start of the half-sweep.  Colour c = (sum of node
   coordinates) mod 2.  Pre-smoothing runs colour 0 then 1; post-smoothing
   runs 1 then 0, so that the cycle is symmetric.
+* Multicolour Gauss-Seidel ("gs"): with the 2^d colours c = sum_d
+  (x_d mod 2) 2^d no two nodes of one colour are coupled, so updating a
+  colour's nodes one after the other or all at once gives the same values:
+  a sweep over the colours in order is an exact Gauss-Seidel sweep in the
+  colour-sorted ordering (Eq. (1) with the colour-wise numbering of
+  Sec. 4.2.6).  Pre-smoothing runs colours 0..2^d-1, post-smoothing the
+  reverse order (symmetric cycle).
 * Damped Jacobi uses omega = 2/3 unless told otherwise.
 * The coarsest level is solved exactly by a dense Cholesky factorisation
   (Algorithm 1 allows a direct solver there, Sec. 5.3).
@@ -43,7 +50,7 @@ class Hierarchy:
     dim: int
     n: int
     levels: int
-    smoother: str = "rbgs"          # "jacobi" or "rbgs"
+    smoother: str = "rbgs"          # "jacobi", "rbgs" or "gs" (2^d colours)
     cycle: str = "V"                # "V", "W" or "F"
     nu_pre: int = 2
     nu_post: int = 2
@@ -53,6 +60,7 @@ class Hierarchy:
     diag: list = field(default_factory=list)
     P: list = field(default_factory=list)       # P[l]: level l+1 -> level l
     mask: list = field(default_factory=list)    # colour-0 boolean mask
+    colours: list = field(default_factory=list) # 2^d-colour number per unknown
     coarse_factor: object = None
     nl: list = field(default_factory=list)
     # float32 copies for the iterative-refinement inner cycle
@@ -65,6 +73,15 @@ def colour_mask(dim, n, colour):
     """Boolean mask over the unknowns: (sum of coordinates) mod 2 == colour."""
     s = sum(interior_coords(dim, n))
     return (s % 2) == colour
+
+
+def colours(dim, n):
+    """2^d-colour number of every unknown: sum_d (x_d mod 2) 2^d."""
+    c = interior_coords(dim, n)
+    out = np.zeros(c[0].size, dtype=np.int64)
+    for d in range(dim):
+        out += (c[d] % 2) << d
+    return out
 
 
 def build_hierarchy(dim, n, levels, kappa=None, smoother="rbgs", nu_pre=2,
@@ -86,6 +103,7 @@ def build_hierarchy(dim, n, levels, kappa=None, smoother="rbgs", nu_pre=2,
         H.A.append(A)
         H.diag.append(A.diagonal().copy())
         H.mask.append(colour_mask(dim, nl, 0))
+        H.colours.append(colours(dim, nl))
         if l < levels - 1:
             H.P.append(prolongation(dim, nl))
     Ac = H.A[-1].toarray()
@@ -113,6 +131,13 @@ def rb_half_sweep(A, diag, x, b, mask):
     return np.where(mask, x + r / diag, x)
 
 
+def gs_colour_step(A, diag, x, b, sel):
+    """Gauss-Seidel update of the unknowns selected by ``sel`` (one colour:
+    no two of them coupled) from the current x."""
+    r = b - A @ x
+    return np.where(sel, x + r / diag, x)
+
+
 def smooth(H, l, x, b, pre, fp32=False):
     A = H.A32[l] if fp32 else H.A[l]
     diag = H.diag32[l] if fp32 else H.diag[l]
@@ -121,6 +146,13 @@ def smooth(H, l, x, b, pre, fp32=False):
         om = np.float32(H.omega) if fp32 else H.omega
         for _ in range(nu):
             x = jacobi_sweep(A, diag, x, b, om)
+        return x
+    if H.smoother == "gs":
+        nc = 2 ** H.dim
+        order = range(nc) if pre else range(nc - 1, -1, -1)
+        for _ in range(nu):
+            for c in order:
+                x = gs_colour_step(A, diag, x, b, H.colours[l] == c)
         return x
     red = H.mask[l]
     order = (red, ~red) if pre else (~red, red)

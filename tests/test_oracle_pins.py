@@ -289,6 +289,22 @@ def test_rb_half_sweep_touches_one_colour_only(rng):
 
 # ---------------------------------------------------------------- the cycle
 
+def _gs_sweep_matrices(A, dim, n):
+    """Error propagation of one forward / backward Gauss-Seidel sweep with
+    the unknowns ordered by 2^d colour (x_d mod 2 bits), stable within a
+    colour: (D + L)^-1 and (D + U)^-1 of the permuted matrix."""
+    coords = np.array(list(itertools.product(range(1, n), repeat=dim)))[:, ::-1]  # x fastest
+    col = sum((coords[:, d] % 2) << d for d in range(dim))
+    perm = np.argsort(col, kind="stable")
+    Ap = A[np.ix_(perm, perm)]
+    N = A.shape[0]
+    Sf_p = np.eye(N) - np.linalg.solve(np.tril(Ap), Ap)
+    Sb_p = np.eye(N) - np.linalg.solve(np.triu(Ap), Ap)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(N)
+    return Sf_p[np.ix_(inv, inv)], Sb_p[np.ix_(inv, inv)]
+
+
 def _cycle_matrix(H, l):
     """Error propagation matrix of one V-cycle on level l, built densely
     from its definition: E = S_post (I - P B_{l+1} P^T A) S_pre, with
@@ -303,6 +319,12 @@ def _cycle_matrix(H, l):
         S = I - H.omega * Dinv @ A
         Spre = np.linalg.matrix_power(S, H.nu_pre)
         Spost = np.linalg.matrix_power(S, H.nu_post)
+    elif H.smoother == "gs":
+        # Gauss-Seidel in the colour-sorted ordering as triangular solves:
+        # forward S = I - (D + L)^-1 A, backward I - (D + U)^-1 A
+        Sf, Sb = _gs_sweep_matrices(A, H.dim, H.nl[l])
+        Spre = np.linalg.matrix_power(Sf, H.nu_pre)
+        Spost = np.linalg.matrix_power(Sb, H.nu_post)
     else:
         m0 = np.diag(H.mask[l].astype(float))
         m1 = I - m0
@@ -318,7 +340,7 @@ def _cycle_matrix(H, l):
 
 
 @pytest.mark.parametrize("dim,n,levels", [(2, 8, 2), (2, 16, 3), (3, 8, 3), (2, 16, 2)])
-@pytest.mark.parametrize("smoother", ["jacobi", "rbgs"])
+@pytest.mark.parametrize("smoother", ["jacobi", "rbgs", "gs"])
 def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, rng):
     H = O.build_hierarchy(dim, n, levels, smoother=smoother)
     N = (n - 1) ** dim
@@ -328,6 +350,29 @@ def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, rng):
     ustar = np.linalg.solve(H.A[0].toarray(), b)
     want = E @ x + (np.eye(N) - E) @ ustar
     np.testing.assert_allclose(O.vcycle(H, 0, x, b), want, rtol=0, atol=1e-12)
+
+
+def test_multicolour_gs_is_exact_gauss_seidel_and_keeps_the_solution(rng):
+    """A sweep over the 2^d colours equals the triangular-solve Gauss-Seidel
+    sweep in the colour-sorted ordering (forward for pre-, backward for
+    post-smoothing); the solution is a fixed point; in 3D no two unknowns of
+    one colour are coupled."""
+    for dim, n in ((2, 12), (3, 6)):
+        H = O.build_hierarchy(dim, n, 2, smoother="gs", nu_pre=1, nu_post=1)
+        A = H.A[0].toarray()
+        N = A.shape[0]
+        x = rng.uniform(-1, 1, N)
+        b = rng.uniform(-1, 1, N)
+        Sf, Sb = _gs_sweep_matrices(A, dim, n)
+        ustar = np.linalg.solve(A, b)
+        for pre, S in ((True, Sf), (False, Sb)):
+            want = S @ x + (np.eye(N) - S) @ ustar
+            np.testing.assert_allclose(O.smooth(H, 0, x, b, pre), want, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(O.smooth(H, 0, ustar, b, True), ustar, rtol=0, atol=1e-12)
+        col = H.colours[0]
+        same = col[:, None] == col[None, :]
+        off = ~np.eye(N, dtype=bool)
+        assert not np.any(A[same & off])
 
 
 def test_h_independent_contraction():
@@ -402,7 +447,8 @@ def test_paper_dof_counts():
 # ---- multigrid-preconditioned conjugate gradients -------------------------
 
 @pytest.mark.parametrize("dim,n,levels,smoother", [(2, 16, 3, "rbgs"), (2, 16, 3, "jacobi"),
-                                                   (3, 8, 3, "rbgs")])
+                                                   (3, 8, 3, "rbgs"), (3, 8, 3, "gs"),
+                                                   (2, 16, 3, "gs")])
 def test_vcycle_preconditioner_is_symmetric_positive_definite(dim, n, levels, smoother, rng):
     """z = V-cycle(0, r) is B r with B = (I - E) A^-1 (E the cycle's error
     propagation matrix, built from the smoother matrices); the symmetric
@@ -491,6 +537,12 @@ def _cycle_matrix_kind(H, l, kind):
         S = I - H.omega * Dinv @ A
         Spre = np.linalg.matrix_power(S, H.nu_pre)
         Spost = np.linalg.matrix_power(S, H.nu_post)
+    elif H.smoother == "gs":
+        # Gauss-Seidel in the colour-sorted ordering as triangular solves:
+        # forward S = I - (D + L)^-1 A, backward I - (D + U)^-1 A
+        Sf, Sb = _gs_sweep_matrices(A, H.dim, H.nl[l])
+        Spre = np.linalg.matrix_power(Sf, H.nu_pre)
+        Spost = np.linalg.matrix_power(Sb, H.nu_post)
     else:
         m0 = np.diag(H.mask[l].astype(float))
         m1 = I - m0
