@@ -55,7 +55,16 @@ typedef enum {
 } mg_status;
 
 typedef enum { MG_OP_STENCIL = 0, MG_OP_CSR = 1 } mg_opfmt;
-typedef enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1 } mg_smoother;
+/* Smoothers (Eq. (1), Sec. 5.3): damped Jacobi; red-black Gauss-Seidel
+ * with the unknowns of one colour (sum of node coordinates mod 2) updated
+ * simultaneously; multicolour Gauss-Seidel with the 2^dim colours
+ * sum_d (x_d mod 2) 2^d, whose unknowns are pairwise uncoupled, so one
+ * in-place pass per colour is an exact Gauss-Seidel sweep in the
+ * colour-sorted numbering (colours in order for pre-, in reverse order for
+ * post-smoothing).  MG_SMOOTH_GS runs on node kernels and CSR rows blocked
+ * by its colours, without the fused head and prolongation steps, and not
+ * in the server. */
+typedef enum { MG_SMOOTH_JACOBI = 0, MG_SMOOTH_RBGS = 1, MG_SMOOTH_GS = 2 } mg_smoother;
 typedef enum { MG_PREC_FP64 = 0, MG_PREC_FP32_IR = 1 } mg_precision;
 /* Cycle shape: how the coarse residual equation of a level is solved --
  * by one coarse cycle (V, Algorithm 1), by two (W), or by an F-cycle
@@ -245,6 +254,9 @@ mg_status mg_apply_residual(mg_ctx* ctx, int level, int prec, const void* x,
  *   step 2: red-black half-sweep on colour 1
  *   step 3: full red-black sweep, colour 0 then 1 (pre-smoothing order)
  *   step 4: full red-black sweep, colour 1 then 0 (post-smoothing order)
+ *   step 5 + c, c < 2^dim: multicolour Gauss-Seidel update of the unknowns
+ *           of colour c (MG_SMOOTH_GS numbering), the others copied; on
+ *           CSR operators only in MG_SMOOTH_GS contexts (MG_E_STATE)
  * A half-sweep updates every node of its colour from the values of x at the
  * start of the half-sweep and copies the other colour.  x_in may be NULL to
  * mean x = 0.  x_out's boundary entries are set to 0. */

@@ -74,6 +74,8 @@ __device__ __forceinline__ V ld_stream(const V* p) {
 //         out, the colour-0 red-black update with colour-1 unknowns copied.
 // MODE 4: over all rows, the residual partial sums and the Jacobi update.
 // MODE 5: out = A x over all rows with partial sums of x.(A x).
+// MODE 6: Gauss-Seidel update of the rows of one colour [r_begin, r_end) in
+//         place (out == xin): no row of the colour reads another's unknown.
 // ZERO: x = 0 (x is not read).
 // Phase 1 issues all column and value loads of a thread before any gather,
 // so that about 2 * PER loads per thread are in flight.  The loads carry no
@@ -151,7 +153,7 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
     } else if (MODE == 5) {
       out[node] = s;
       sq = (double)x0 * (double)s;
-    } else if (MODE >= 3) {
+    } else if (MODE == 3 || MODE == 4) {
       // residual of every row plus the first smoothing step: Jacobi (4)
       // updates every row, red-black (3) the colour-0 rows, which come first
       sq = (double)res * (double)res;
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
       out[node] = upd ? (MODE == 4 ? x0 + omega * q : x0 + q) : x0;
     } else {
       const T q = res / dg;
-      out[node] = MODE == 1 ? x0 + omega * q : x0 + q;
+      out[node] = MODE == 1 ? x0 + omega * q : x0 + q;  // MODE 1, 2, 6
       if (MODE == 2) {
         // Copy the other colour along the grid row: node p+1 (and p-1 for
         // the colour's first node at x = 2).  Every other-colour unknown of
@@ -171,7 +173,7 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
       }
     }
   }
-  if ((MODE == 0 || MODE >= 3) && partials != nullptr) {
+  if ((MODE == 0 || MODE == 3 || MODE == 4 || MODE == 5) && partials != nullptr) {
     const double t = block_sum_1d<NTH>(sq);
     if (tid == 0) partials[blk] = t;
   }
@@ -313,6 +315,9 @@ void launch_csr_smooth(const Geo&, const CsrOp<T>& A, int kind, const T* xin, co
                        T* xout, T omega, hipStream_t s) {
   if (kind == SM_JACOBI) {
     launch_rows<T, 1>(A, 0, A.rows, xin, b, xout, omega, nullptr, s);
+  } else if (kind >= SM_GS0) {
+    const int c = kind - SM_GS0;
+    launch_rows<T, 6>(A, A.coff[c], A.coff[c + 1], xout, b, xout, omega, nullptr, s);
   } else {
     const int c = kind == SM_RB1 ? 1 : 0;
     launch_rows<T, 2>(A, A.coff[c], A.coff[c + 1], xin, b, xout, omega, nullptr, s);

@@ -346,6 +346,19 @@ __device__ __forceinline__ T smooth_node(const StencilParams<T>& op, const T* ka
   return ks == SM_JACOBI ? xin[p] + omega * q : xin[p] + q;
 }
 
+// Gauss-Seidel update of unknown p in place (multicolour Gauss-Seidel: the
+// other unknowns of its colour are not coupled to it, so they may be
+// updated at the same time): x_p + (b_p - (A x)_p) / a_pp.
+template <typename T, int DIM, int KIND>
+__device__ __forceinline__ T gs_node(const StencilParams<T>& op, const T* kappa, const DGeo& g,
+                                     const T* x, const T* __restrict__ b, long p, int i, int j,
+                                     int k) {
+  T ax, dg;
+  Apply<T, DIM, KIND>::at(op, kappa, g, x, p, i, j, k, ax, dg);
+  const T q = (b[p] - ax) / dg;
+  return x[p] + q;
+}
+
 template <typename T, int DIM, int KIND>
 __device__ __forceinline__ T residual_node(const StencilParams<T>& op, const T* kappa,
                                            const DGeo& g, const T* __restrict__ x,
@@ -1152,6 +1165,16 @@ __global__ __launch_bounds__(256) void k_smooth(Geo g, StencilParams<T> op, T om
                                            omega, p, i, j, k);
 }
 
+// Gauss-Seidel update of the unknowns of colour `colour` of c in place.
+template <typename T, int DIM, int KIND>
+__global__ __launch_bounds__(256) void k_smooth_gs(Geo g, StencilParams<T> op, int colour,
+                                                   Batch B) {
+  NODE_INDEX(DIM, g)
+  if (!inside || gs_colour(i, j, k) != colour) return;
+  T* x = (T*)I.c;
+  x[p] = gs_node<T, DIM, KIND>(op, (const T*)I.kappa, dgeo(g), x, (const T*)I.b, p, i, j, k);
+}
+
 // Partial sums of (b - A x)^2 and, written to c, the first smoothing step
 // of x: KS = SM_JACOBI updates every unknown, SM_RB0 those of colour 0.
 template <typename T, int DIM, int KIND, int KS>
@@ -1394,6 +1417,27 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
     const T omega = D.omega;
     const int smoother = D.smoother;
     const int nu = pre ? D.nu_pre : D.nu_post;
+    if (smoother == 2) {
+      // multicolour Gauss-Seidel in place: colours in order (pre) or in
+      // reverse order (post)
+      if (nu == 0) return;
+      T* x = X(l);
+      if (*zero) {
+        for_unknowns<DIM>(n, g, [&](long p, int, int, int) { x[p] = T(0); });
+        __syncthreads();
+        *zero = false;
+      }
+      const int ncol = 1 << DIM;
+      for (int it = 0; it < nu; ++it)
+        for (int q = 0; q < ncol; ++q) {
+          const int col = pre ? q : ncol - 1 - q;
+          for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
+            if (gs_colour(i, j, k) == col) x[p] = gs_node<T, DIM, KIND>(op, kap, g, x, b, p, i, j, k);
+          });
+          __syncthreads();
+        }
+      return;
+    }
     for (int it = 0; it < nu; ++it) {
       for (int h = 0; h < (smoother == 0 ? 1 : 2); ++h) {
         const int ks = smoother == 0 ? SM_JACOBI : ((h == 0) == pre ? SM_RB0 : SM_RB1);
@@ -1828,6 +1872,14 @@ static void launch_sweep3_smooth(const Geo& g, const StencilParams<T>& op, int k
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s) {
+  if (kind >= SM_GS0) {
+    const dim3 gr = node_grid(g, B.count), bl(BX, BY);
+#define L_GS(D, K) \
+  hipLaunchKernelGGL((k_smooth_gs<T, D, K>), gr, bl, 0, s, g, op, kind - SM_GS0, B)
+    DISPATCH_DIM_KIND(g.dim, op.kind, L_GS);
+#undef L_GS
+    return;
+  }
   if (use_sweep3(g)) {
     with_kind3(op.kind, [&](auto k) {
       constexpr int K = decltype(k)::value;

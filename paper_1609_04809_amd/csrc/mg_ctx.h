@@ -33,7 +33,7 @@ struct Level {
   float* val32 = nullptr;
   int rows = 0;
   long nnz = 0;
-  int coff[3] = {0, 0, 0};
+  int coff[9] = {};
   StencilParams<double> st64{};
   StencilParams<float> st32{};
   CsrOp<double> csr64{};

@@ -104,7 +104,8 @@ struct CsrOp {
   const T* val;
   const int* rowmap;
   int rows;
-  int coff[3];  // colour c rows: [coff[c], coff[c+1])
+  int coff[9];  // colour c rows: [coff[c], coff[c+1]) (2 colours, or 2^dim
+                // for multicolour Gauss-Seidel)
   int n;        // cells per direction of the level
   long sy;      // node stride in y
 };
@@ -114,8 +115,15 @@ struct CsrOp {
 // V-cycle.
 enum CycleKind { CYC_V = 0, CYC_W = 1, CYC_F = 2 };
 
-// Smoothing step kinds (mg_apply_smooth "step" 0..2).
-enum SmoothKind { SM_JACOBI = 0, SM_RB0 = 1, SM_RB1 = 2 };
+// Smoothing step kinds (mg_apply_smooth "step" 0..2); SM_GS0 + c, c <
+// 2^dim: the Gauss-Seidel update of the unknowns of colour c (sum_d (x_d mod
+// 2) 2^d) in place -- no two of them are coupled.
+enum SmoothKind { SM_JACOBI = 0, SM_RB0 = 1, SM_RB1 = 2, SM_GS0 = 8 };
+
+// Colour of node (i, j, k) for multicolour Gauss-Seidel.
+__host__ __device__ inline int gs_colour(int i, int j, int k) {
+  return (i & 1) | ((j & 1) << 1) | ((k & 1) << 2);
+}
 
 // Device-resident description of the tail levels l0..L-1 of one request:
 // the V-cycle below level l0 runs inside one workgroup, with every vector
@@ -183,7 +191,8 @@ template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
                      hipStream_t s);
 // One smoothing step (SmoothKind); a == nullptr means x = 0 (then for every
-// item):  a = x_in, b = b, c = x_out, kappa.
+// item):  a = x_in, b = b, c = x_out, kappa.  Gauss-Seidel colour steps
+// (kind >= SM_GS0) update c in place (a is ignored, zero is not allowed).
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s);
@@ -281,6 +290,8 @@ void launch_csr_head(const Geo& g, const CsrOp<T>& A, int kind, const T* x, cons
 template <typename T>
 void launch_csr_apply_dot(const Geo& g, const CsrOp<T>& A, const T* x, T* q, double* partials,
                           hipStream_t s);
+// Gauss-Seidel colour steps (kind >= SM_GS0) need xin == xout (in place)
+// and rows blocked by 2^dim colours.
 template <typename T>
 void launch_csr_smooth(const Geo& g, const CsrOp<T>& A, int kind, const T* xin, const T* b,
                        T* xout, T omega, hipStream_t s);

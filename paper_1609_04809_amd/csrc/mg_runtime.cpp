@@ -90,7 +90,7 @@ bool valid_options(const mg_options* o, std::string& why) {
     return false;
   }
   if (o->op != MG_OP_STENCIL && o->op != MG_OP_CSR) { why = "op must be MG_OP_STENCIL or MG_OP_CSR"; return false; }
-  if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_RBGS) { why = "unknown smoother"; return false; }
+  if (o->smoother != MG_SMOOTH_JACOBI && o->smoother != MG_SMOOTH_RBGS && o->smoother != MG_SMOOTH_GS) { why = "unknown smoother"; return false; }
   if (o->nu_pre < 0 || o->nu_post < 0 || o->nu_pre + o->nu_post > 64) { why = "nu_pre/nu_post out of range"; return false; }
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
@@ -303,22 +303,25 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   }();
   const int T = dim == 3 ? tile : n;
   const int kmin = dim == 3 ? 1 : 0, kmax = dim == 3 ? n - 1 : 0;
-  for (int colour = 0; colour < 2; ++colour) {
-    if (colour == 1) Lv.coff[1] = idx;
+  // two colours (red-black, sum of coordinates mod 2) or, for multicolour
+  // Gauss-Seidel, the 2^dim colours of gs_colour
+  const bool gs = c->o.smoother == MG_SMOOTH_GS;
+  const int ncol = gs ? (1 << dim) : 2;
+  for (int colour = 0; colour < ncol; ++colour) {
+    Lv.coff[colour] = idx;
     for (int k0 = kmin; k0 <= kmax; k0 += T)
       for (int j0 = 1; j0 <= n - 1; j0 += T)
         for (int k = k0; k <= std::min(kmax, k0 + T - 1); ++k)
           for (int j = j0; j <= std::min(n - 1, j0 + T - 1); ++j)
             for (int i = 1; i <= n - 1; ++i) {
-              if (((i + j + k) & 1) != colour) continue;
+              if ((gs ? gs_colour(i, j, k) : ((i + j + k) & 1)) != colour) continue;
               rowmap[idx] = (int)(i + j * Lv.g.sy + (long)k * Lv.g.sz);
               const int len = cnt(i) * cnt(j) * (dim == 3 ? cnt(k) : 1);
               rowptr[idx + 1] = rowptr[idx] + len;
               ++idx;
             }
   }
-  Lv.coff[0] = 0;
-  Lv.coff[2] = rows;
+  Lv.coff[ncol] = rows;
   if (idx != rows || rowptr[rows] != Lv.nnz)
     return fail(MG_E_ARG, "internal: CSR layout mismatch on level %d", l);
   HIP_TRY(hipMemcpyAsync(Lv.rowmap, rowmap.data(), rows * sizeof(int), hipMemcpyHostToDevice, s));
@@ -340,7 +343,7 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
     op.val = val;
     op.rowmap = Lv.rowmap;
     op.rows = rows;
-    for (int q = 0; q < 3; ++q) op.coff[q] = Lv.coff[q];
+    for (int q = 0; q < 9; ++q) op.coff[q] = Lv.coff[q];
     op.n = Lv.g.n;
     op.sy = Lv.g.sy;
   };
@@ -436,7 +439,7 @@ mg_status build_tail(mg_ctx* c, hipStream_t s) {
     D.nlev = c->L - l0;
     D.dim = c->o.dim;
     D.kind = Bufs<T>::st(c->lv[l0]).kind;
-    D.smoother = c->o.smoother == MG_SMOOTH_JACOBI ? 0 : 1;
+    D.smoother = c->o.smoother == MG_SMOOTH_JACOBI ? 0 : (c->o.smoother == MG_SMOOTH_GS ? 2 : 1);
     D.nu_pre = c->o.nu_pre;
     D.nu_post = c->o.nu_post;
     D.omega = (T)c->o.omega;
@@ -581,6 +584,20 @@ template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
                   const T* b, bool skip = false) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
+  if (c->o.smoother == MG_SMOOTH_GS) {
+    // multicolour Gauss-Seidel: one in-place launch per colour, colours in
+    // order for pre-smoothing and in reverse order for post-smoothing
+    if (nu == 0) return;
+    if (*zero) {
+      emit_fill<T>(c, sink, l, *cur);
+      *zero = false;
+    }
+    const int ncol = 1 << c->o.dim;
+    for (int it = 0; it < nu; ++it)
+      for (int q = 0; q < ncol; ++q)
+        emit_smooth<T>(c, sink, l, SM_GS0 + (pre ? q : ncol - 1 - q), *cur, b, *cur);
+    return;
+  }
   std::vector<int> steps;
   for (int it = 0; it < nu; ++it) {
     if (c->o.smoother == MG_SMOOTH_JACOBI) {
@@ -683,7 +700,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     // per-cell kappa the fused kernel's register and LDS use cost more than
     // the pass it saves)
     const bool fuse_pro = !c->csr && !c->kappa && c->o.nu_post >= 1 &&
-                          pair_sweeps(c->lv[l].g) &&
+                          c->o.smoother != MG_SMOOTH_GS && pair_sweeps(c->lv[l].g) &&
                           !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
     bool nz = false;
     if (fuse_pro) {
@@ -719,6 +736,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
 // level-0 pre-smoothing step outside the tail.
 bool head_fusion(const mg_ctx* c) {
   return !c->ir && c->o.nu_pre >= 1 && c->L >= 2 && c->tail0 != 0 &&
+         c->o.smoother != MG_SMOOTH_GS &&
          !(c->o.flags & MG_FLAG_NO_FUSE);
 }
 
@@ -1394,7 +1412,11 @@ mg_status mg_apply_smooth(mg_ctx* c, int level, int prec, int step, const void* 
   mg_status st = check_step(c, level, prec, false);
   if (st != MG_OK) return st;
   if (!b || !x_out) return fail(MG_E_ARG, "NULL vector");
-  if (step < 0 || step > 4) return fail(MG_E_ARG, "step must be 0..4");
+  const int ncol = 1 << c->o.dim;
+  if (step < 0 || step > 4 + ncol) return fail(MG_E_ARG, "step must be 0..%d", 4 + ncol);
+  if (step >= 5 && c->csr && c->o.smoother != MG_SMOOTH_GS)
+    return fail(MG_E_STATE, "CSR colour steps need rows blocked by colour (MG_SMOOTH_GS)");
+  if (step >= 5 && x_in == x_out) return fail(MG_E_ARG, "x_out must not alias x_in");
   const Sink sink = launch_sink(c, as_stream(stream));
   return typed(prec, [&](auto tag) {
     using T = decltype(tag);
@@ -1402,6 +1424,18 @@ mg_status mg_apply_smooth(mg_ctx* c, int level, int prec, int step, const void* 
     const T* in = (const T*)x_in;
     const T* bb = (const T*)b;
     emit_fill<T>(c, sink, level, out);
+    if (step >= 5) {
+      // Gauss-Seidel update of colour step - 5 on a copy of x_in
+      if (in) {
+        OpRec o = base_op<T>(c, OC_COPY, level);
+        o.count = c->lv[level].g.nodes;
+        o.item.a = in;
+        o.item.c = out;
+        sink(o);
+      }
+      emit_smooth<T>(c, sink, level, SM_GS0 + step - 5, out, bb, out);
+      return;
+    }
     if (step <= 2) {
       emit_smooth<T>(c, sink, level, step, in, bb, out);
       return;

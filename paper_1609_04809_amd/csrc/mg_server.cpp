@@ -422,6 +422,7 @@ mg_status mg_server_submit(mg_server* S, const mg_options* o, const double* b_ho
   if (o->flags & MG_FLAG_PCG) return fail(MG_E_ARG, "serving runs the cycle iteration, not CG");
   if (o->flags & MG_FLAG_WARM) return fail(MG_E_ARG, "served solves start from u = 0");
   if (o->sigma != 0.0) return fail(MG_E_ARG, "the server solves sigma = 0 problems only");
+  if (o->smoother == MG_SMOOTH_GS) return fail(MG_E_ARG, "the server runs Jacobi or red-black smoothing");
   if (mg_footprint_bytes(o) == 0) return MG_E_ARG;  // message set by mg_footprint_bytes
   auto r = std::make_unique<Request>();
   r->o = *o;

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "ok", 1: "arg", 2: "nomem", 3: "hip", 4: "not_spd",
                 5: "maxit", 6: "diverged", 7: "nonfinite", 8: "state"}
 
 OP = {"stencil": 0, "csr": 1}
-SMOOTHER = {"jacobi": 0, "rbgs": 1}
+SMOOTHER = {"jacobi": 0, "rbgs": 1, "gs": 2}
 PREC = {"fp64": 0, "fp32_ir": 1}
 CYCLE = {"V": 0, "W": 1, "F": 2}
 FLAG_NO_GRAPH = 1
@@ -33,6 +33,7 @@ FLAG_WARM = 32
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
+STEP_GS0 = 5          # STEP_GS0 + c: multicolour Gauss-Seidel update of colour c
 # mg_profile_enable kernel ids
 PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG, PROF_PAIR, PROF_SMOOTH_PRO = 0, 1, 2, 3, 4, 5
 
