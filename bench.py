@@ -178,17 +178,20 @@ def roofline_stencil(S, w, bd, s):
     return out
 
 
-def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V"):
+def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V",
+                 smoother=None):
     """Time `steps` solves of a workload: the plain cycle iteration, or with
     pcg conjugate gradients preconditioned by one cycle per iteration; cycle
-    V (the workload's), W or F."""
+    V (the workload's), W or F; smoother the workload's or another one
+    ("gs": multicolour Gauss-Seidel)."""
     import torch
     from paper_1609_04809_amd import workloads as W
     from paper_1609_04809_amd.mg import FLAG_PCG, Solver
     w = W.WORKLOADS[name]
     b, kappa, bd = _device_rhs(w)
     t0 = time.perf_counter()
-    S = Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=w.smoother,
+    sm = smoother or w.smoother
+    S = Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=sm,
                nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision=w.precision,
                flags=FLAG_PCG if pcg else 0, cycle=cycle)
     torch.cuda.synchronize()
@@ -198,9 +201,9 @@ def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V")
            "MDOF_per_s": round(w.dofs / t / 1e6, 1), "ms_per_solve": round(t * 1e3, 3),
            "cycles": k, "final_rel_residual": hist[-1], "setup_s": round(setup_s, 3),
            "precision": w.precision, "op": w.op, "method": "pcg" if pcg else "cycle",
-           "cycle": cycle}
+           "cycle": cycle, "smoother": sm}
     roof = None
-    if pcg or cycle != "V":
+    if pcg or cycle != "V" or sm != w.smoother:
         pass
     elif w.op == "csr":
         if with_roofline:
@@ -397,6 +400,12 @@ def main():
                 log(f"[bench] {other} ({kind}-cycle): {r['MDOF_per_s']} MDOF/s, "
                     f"{r['cycles']} cycles, {r['ms_per_solve']} ms/solve")
                 extra.append(r)
+        # multicolour Gauss-Seidel in place of the red-black smoother
+        for other in ("poisson3d_128_csr_rbgs", "poisson3d_256_rbgs_fp64"):
+            r, _, _ = run_workload(other, max(3, args.steps // 4), 1, smoother="gs")
+            log(f"[bench] {other} (multicolour GS): {r['MDOF_per_s']} MDOF/s, "
+                f"{r['cycles']} cycles, {r['ms_per_solve']} ms/solve")
+            extra.append(r)
     heat = None
     if not args.no_extra and not args.no_heat:
         heat = []
