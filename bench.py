@@ -175,6 +175,8 @@ def roofline_stencil(S, w, bd, s):
         out[key] = {"launches": launches, "avg_us": round(avg_s * 1e6, 2),
                     "achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
                     "bytes_per_launch": int(per)}
+        if key == "halfsweep":
+            out[key]["traffic"] = measured_traffic(w.name)
     return out
 
 
@@ -280,7 +282,8 @@ def run_heat(name, steps=None, precision=None, extrapolate=False):
     if hs:
         ach = per / (hs["avg_us"] * 1e-6) / 1e9
         hs.update({"achieved_GBs": round(ach, 1), "frac": round(ach / HBM_PEAK_GBS, 4),
-                   "bytes_per_launch": int(per)})
+                   "bytes_per_launch": int(per),
+                   "traffic": measured_traffic(f"{name}_{precision or w.precision}")})
     R.close()
     return {"workload": name, "dofs": w.dofs, "steps": steps, "dt": w.dt,
             "t_end": round(steps * w.dt, 6), "seconds": round(t, 3),
