@@ -658,10 +658,11 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   T bpf[2] = {T(0), T(0)};
   T* const ge = MODE == SW_CN ? (T*)const_cast<void*>(I.e) : nullptr;
   T gpf[2] = {T(0), T(0)};
+  const long blay = I.lay;  // b colour-split (see Item::lay) or natural
   auto prefetch_b = [&](int k) {
     const long p = pb0 + (long)min(k, n) * sz;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) bpf[u] = b[p + u];
+    for (int u = 0; u < 2; ++u) bpf[u] = b[lay_idx(p + u, blay)];
     if (MODE == SW_CN && ge != nullptr) {
 #pragma unroll
       for (int u = 0; u < 2; ++u) gpf[u] = ge[p + u];
@@ -834,7 +835,9 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       if (RB && (up == 0 ? ok0 : ok1)) store(k, up, xo1);  // the other unknown keeps its value
     };
     // red-black: b of the unknown updated at plane p, for the next plane
-    auto prefetch_b1 = [&](int up) { bpf[0] = b[pb0 + (long)min(p, n) * sz + up]; };
+    auto prefetch_b1 = [&](int up) {
+      bpf[0] = b[lay_idx(pb0 + (long)min(p, n) * sz + up, blay)];
+    };
     if (!RB || ((colour + 1 + j + p) & 1) == 0) {  // i is odd
       if (RB) prefetch_b1(0);
       step(std::integral_constant<int, 0>{});
@@ -1217,7 +1220,7 @@ template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_restrict(Geo gf, Geo gc, Batch B) {
   NODE_INDEX(DIM, gc)
   if (!inside) return;
-  ((T*)I.c)[p] = restrict_node<T, DIM>(dgeo(gf), (const T*)I.a, i, j, k);
+  ((T*)I.c)[lay_idx(p, I.lay)] = restrict_node<T, DIM>(dgeo(gf), (const T*)I.a, i, j, k);
 }
 
 template <typename T, int DIM>
@@ -1247,7 +1250,7 @@ __global__ __launch_bounds__(256) void k_scale_cast(Geo g, Batch B) {
   NODE_INDEX(DIM, g)
   if (!inside) return;
   const double s = sqrt(*I.scal);
-  ((float*)I.c)[p] = (float)(((const double*)I.a)[p] / s);
+  ((float*)I.c)[lay_idx(p, I.lay)] = (float)(((const double*)I.a)[p] / s);
 }
 
 // u += ||r|| * double(c) on the unknowns.
@@ -1710,6 +1713,13 @@ __global__ __launch_bounds__(256) void k_cn_bnd(Geo g, CnWeights w, const double
   b[p] += acc;
 }
 
+__global__ void k_split_copy(const double* __restrict__ src, double* __restrict__ dst, long count,
+                             long lay) {
+  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (; t < count; t += stride) dst[lay_idx(t, lay)] = src[t];
+}
+
 // v = 0 on the boundary nodes; thread t covers one node of the 2 dim faces.
 template <int DIM>
 __global__ void k_zero_boundary(Geo g, double* __restrict__ v) {
@@ -2019,6 +2029,11 @@ void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, double* gu
     hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
   else
     hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
+}
+
+void launch_split_copy(const double* src, double* dst, long count, long lay, hipStream_t s) {
+  hipLaunchKernelGGL(k_split_copy, dim3(flat_blocks(count)), dim3(256), 0, s, src, dst, count,
+                     lay);
 }
 
 void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, const double* g0,

@@ -99,6 +99,11 @@ struct mg_ctx {
   bool ir = false;
   bool csr = false;
   int tail0 = -1;  // first level cycled by the one-workgroup tail kernel (-1: none)
+  // ops emitted for the single-step entry points (caller buffers in the
+  // natural layout) keep every right-hand side in the natural layout
+  bool natural = false;
+  // mg_solve keeps a colour-split copy of the caller's FP64 b (level 0)
+  bool b0_split = false;
   std::vector<mg::Level> lv;
   char* arena = nullptr;
   size_t arena_bytes = 0;

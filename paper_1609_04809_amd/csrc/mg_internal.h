@@ -87,7 +87,18 @@ struct Item {
   const double* L;
   const void* e;  // coarse correction (prolongation fused into a sweep)
   int flag;
+  // Colour-split layout of the level's right-hand side read by a sweep (or
+  // of the vector a restriction / FP32 cast writes): node p is stored at
+  // p / 2 (even p) or lay + p / 2 (odd p); 0 = the natural layout.
+  long lay;
 };
+
+// Index of node p in a vector stored colour-split with odd half at `lay`
+// (lay = 0: natural).  For even n the parity of p is the red-black colour
+// of the node, so a half-sweep reads its colour's half contiguously.
+__host__ __device__ inline long lay_idx(long p, long lay) {
+  return lay ? (p >> 1) + (p & 1) * lay : p;
+}
 
 struct Batch {
   Item it[kMaxBatch];
@@ -269,6 +280,8 @@ void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, cons
                          double* b, hipStream_t s);
 // v = 0 on the boundary nodes of the level (interior untouched).
 void launch_zero_boundary(const Geo& g, double* v, hipStream_t s);
+// dst[lay_idx(p, lay)] = src[p] for every node p (natural -> colour-split).
+void launch_split_copy(const double* src, double* dst, long count, long lay, hipStream_t s);
 
 // ---- CSR kernels (kernels_csr.hip) ----------------------------------------
 // Entries of K + sigma M: s_elem scales the stiffness element factors,

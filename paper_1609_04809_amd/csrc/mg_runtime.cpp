@@ -95,7 +95,7 @@ bool valid_options(const mg_options* o, std::string& why) {
   if (o->smoother == MG_SMOOTH_JACOBI && !(o->omega > 0.0 && o->omega <= 1.0)) { why = "omega must be in (0, 1]"; return false; }
   if (o->precision != MG_PREC_FP64 && o->precision != MG_PREC_FP32_IR) { why = "unknown precision"; return false; }
   if (o->max_iter < 1) { why = "max_iter must be >= 1"; return false; }
-  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG | MG_FLAG_PAIR | MG_FLAG_WARM)) { why = "unknown flags"; return false; }
+  if (o->flags & ~(MG_FLAG_NO_GRAPH | MG_FLAG_NO_TAIL | MG_FLAG_NO_FUSE | MG_FLAG_PCG | MG_FLAG_PAIR | MG_FLAG_WARM | MG_FLAG_NO_SPLIT)) { why = "unknown flags"; return false; }
   if (!(std::isfinite(o->sigma) && o->sigma >= 0.0)) { why = "sigma must be finite and >= 0"; return false; }
   if (o->sigma > 0.0 && (o->flags & MG_FLAG_PAIR)) { why = "MG_FLAG_PAIR needs sigma == 0"; return false; }
   if (o->cycle != MG_CYCLE_V && o->cycle != MG_CYCLE_W && o->cycle != MG_CYCLE_F) { why = "cycle must be V, W or F"; return false; }
@@ -138,6 +138,36 @@ int tail_start(const mg_options& o, bool kappa) {
   return l0;
 }
 
+// Whether the right-hand sides of a level with n_l cells, in elements of
+// `elem` bytes, are stored colour-split (Item::lay): 3D matrix-free levels
+// swept by k_sweep3 with red-black or Jacobi smoothing on single
+// half-sweeps, even n_l (then a node's index parity is its colour), and
+// vectors of at least 128 MB, which stream from HBM (smaller levels stay in
+// the 256 MB last-level cache, where the split layout measured no gain and
+// its index arithmetic cost 1-3%).
+constexpr long kSplitMinBytes = 128L << 20;
+bool split_level(const mg_options& o, int nl, int elem) {
+  const long nodes = (long)(nl + 1) * (nl + 1) * (nl + 1);
+  return o.op == MG_OP_STENCIL && o.dim == 3 && nl >= 32 && nl % 2 == 0 &&
+         nodes * elem >= kSplitMinBytes && o.smoother != MG_SMOOTH_GS &&
+         !(o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_SPLIT));
+}
+
+// FP64 solves without CG keep a colour-split copy of the caller's b.
+bool split_b0(const mg_options& o) {
+  return o.precision == MG_PREC_FP64 && !(o.flags & MG_FLAG_PCG) && split_level(o, o.n, 8);
+}
+
+// Odd-half offset (Item::lay) of level l's right-hand side in precision
+// prec (0 FP64, 1 FP32), 0 for the natural layout.  Level 0 in FP64 is the
+// caller's b (or, in mg_solve without CG, its split copy); in FP32 the
+// cast of the scaled residual, written split.
+long b_split_half(const mg_ctx* c, int l, int prec) {
+  if (c->natural || !split_level(c->o, c->lv[l].g.n, prec == 0 ? 8 : 4)) return 0;
+  if (l == 0 && prec == 0 && !c->b0_split) return 0;
+  return (c->lv[l].g.nodes + 1) / 2;
+}
+
 // Lay out every buffer of a context; with base == nullptr only sizes.
 size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
   Planner P(base);
@@ -153,6 +183,8 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     if (l > 0) {
       L.x64 = P.take<double>(g.nodes);
       L.b64 = P.take<double>(g.nodes);
+    } else if (split_b0(o)) {
+      L.b64 = P.take<double>(g.nodes);  // colour-split copy of the caller's b
     }
     L.t64 = P.take<double>(g.nodes);
     L.r64 = P.take<double>(g.nodes);
@@ -511,6 +543,7 @@ OpRec base_op(mg_ctx* c, int code, int l) {
   o.omega = (T)c->o.omega;
   o.m = c->m;
   o.item.kappa = Bufs<T>::kap(Lv);
+  o.item.lay = b_split_half(c, l, Bufs<T>::prec);
   return o;
 }
 
@@ -687,6 +720,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, l);
+    o.item.lay = b_split_half(c, l + 1, Bufs<T>::prec);  // the coarse b it writes
     o.item.a = Bufs<T>::r(c->lv[l]);
     o.item.c = Bufs<T>::b(c->lv[l + 1]);
     sink(o);
@@ -777,6 +811,7 @@ void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
   double* S = c->scal;
   if (c->ir) {
     OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+    o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
     o.item.a = L0.rk64;
     o.item.c = L0.b32;
     o.item.scal = S + 0;
@@ -845,6 +880,7 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
   if (c->ir) {
     // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c
     OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+    o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
     o.item.a = L0.r64;
     o.item.c = L0.b32;
     o.item.scal = c->scal + 0;
@@ -868,12 +904,13 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
 // for a warm-started solve with head fusion in one pass with the first
 // smoothing step of the first cycle (into the level-0 spare, as at the end
 // of an IT_FUSED_FIRST iteration), else with the residual in r64.
+// bn: b in the natural layout for its norm (default: b itself).
 void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool warm = false,
-                   bool fuse = false) {
+                   bool fuse = false, const double* bn = nullptr) {
   Level& L0 = c->lv[0];
   emit_start(c, sink, u, warm);
   OpRec o = base_op<double>(c, OC_NORM2, 0);
-  o.item.a = b;
+  o.item.a = bn ? bn : b;
   o.item.partials = c->partials;
   sink(o);
   emit_reduce(c, sink, norm2_blocks(L0.g), c->scal + 1);
@@ -1076,7 +1113,7 @@ bool same_key(const OpRec& a, const OpRec& b) {
   return a.code == b.code && a.prec == b.prec && a.sub == b.sub && a.g.dim == b.g.dim &&
          a.g.n == b.g.n && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
          a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.wf == b.wf && a.omega == b.omega &&
-         a.m == b.m &&
+         a.m == b.m && a.item.lay == b.item.lay &&
          a.count == b.count && batchable(a) && batchable(b);
 }
 
@@ -1271,13 +1308,22 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   hipStream_t s = as_stream(stream);
   *iters = 0;
   if (hist) hist[0] = 1.0;
+  c->natural = false;
+  c->b0_split = split_b0(c->o);
   const bool pcg = (c->o.flags & MG_FLAG_PCG) != 0;
   const bool warm = (c->o.flags & MG_FLAG_WARM) != 0;
   const bool fuse = head_fusion(c);
+  const double* bc = b;  // b as the cycles read it
+  if (c->b0_split) {
+    // the level-0 right-hand side colour-split (each half-sweep then reads
+    // its colour's half)
+    launch_split_copy(b, c->lv[0].b64, c->lv[0].g.nodes, b_split_half(c, 0, 0), s);
+    bc = c->lv[0].b64;
+  }
   if (pcg)
     emit_pcg_prologue(c, launch_sink(c, s), u, b, warm);
   else
-    emit_prologue(c, launch_sink(c, s), u, b, warm, fuse);
+    emit_prologue(c, launch_sink(c, s), u, bc, warm, fuse, b);
   HIP_TRY(hipGetLastError());
   double nb2 = 0.0;
   mg_status st = read_scalar(c, 1, &nb2, s);
@@ -1303,7 +1349,7 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   for (int k = 1; k <= c->o.max_iter; ++k) {
     const int kind = pcg ? (k == 1 ? IT_PCG_FIRST : IT_PCG)
                          : (!fuse ? IT_PLAIN : (k == 1 && !warm ? IT_FUSED_FIRST : IT_FUSED));
-    st = run_iteration(c, u, b, s, kind);
+    st = run_iteration(c, u, bc, s, kind);
     if (st != MG_OK) return st;
     double n2 = 0.0;
     st = read_scalar(c, 0, &n2, s);
@@ -1373,6 +1419,7 @@ mg_status mg_apply_mass(mg_ctx* c, const double* f, double* F, void* stream) {
 namespace {
 mg_status check_step(mg_ctx* c, int level, int prec, bool need_next) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
+  c->natural = true;  // caller buffers: natural layout throughout
   if (level < 0 || level >= c->L || (need_next && level >= c->L - 1))
     return fail(MG_E_ARG, "level %d out of range", level);
   if (prec != MG_PREC_FP64 && prec != MG_PREC_FP32_IR) return fail(MG_E_ARG, "bad precision");
@@ -1458,6 +1505,7 @@ mg_status mg_apply_restrict(mg_ctx* c, int level, int prec, const void* r, void*
     using T = decltype(tag);
     emit_fill<T>(c, sink, level + 1, (T*)bc);
     OpRec o = base_op<T>(c, OC_RESTRICT, level);
+    o.item.lay = b_split_half(c, level + 1, Bufs<T>::prec);
     o.item.a = r;
     o.item.c = bc;
     sink(o);
@@ -1476,6 +1524,7 @@ mg_status mg_apply_residual_restrict(mg_ctx* c, int level, int prec, const void*
     emit_fill<T>(c, sink, level + 1, (T*)bc);
     emit_residual<T>(c, sink, level, (const T*)x, (const T*)b, r, nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, level);
+    o.item.lay = b_split_half(c, level + 1, Bufs<T>::prec);
     o.item.a = r;
     o.item.c = bc;
     sink(o);

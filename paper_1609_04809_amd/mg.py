@@ -30,6 +30,7 @@ FLAG_NO_FUSE = 4
 FLAG_PCG = 8
 FLAG_PAIR = 16
 FLAG_WARM = 32
+FLAG_NO_SPLIT = 64
 
 # mg_apply_smooth steps
 STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4

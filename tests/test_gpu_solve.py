@@ -272,3 +272,33 @@ def test_paired_half_sweeps_agree_bitwise(dim, n, levels, kap, prec, nu):
             outs.append((k, hist, host_full(u)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("dim,n,levels,kap,prec,smoother,sigma,flags", [
+    # sizes whose finest vectors reach the 128 MB above which b is split
+    (3, 256, 8, False, "fp64", "rbgs", 0.0, 0),
+    (3, 256, 8, True, "fp64", "jacobi", 0.0, 0),
+    (3, 256, 8, False, "fp64", "rbgs", 200.0, "warm"),
+    (3, 384, 8, False, "fp32_ir", "rbgs", 0.0, 0),
+    (3, 384, 8, False, "fp32_ir", "rbgs", 0.0, "pcg"),
+])
+def test_colour_split_right_hand_sides_agree_bitwise(dim, n, levels, kap, prec, smoother, sigma,
+                                                     flags):
+    """Right-hand sides stored colour-split (the default on large 3D stencil
+    levels) give bitwise the results of the natural layout."""
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_SPLIT, FLAG_PCG, FLAG_WARM, Solver
+    kappa = W.kappa_lognormal(dim, n, 14) if kap else None
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 15))
+    fl = {0: 0, "warm": FLAG_WARM, "pcg": FLAG_PCG}[flags]
+    u0 = dev_full(dim, n, 0.01 * W.rhs_uniform(dim, n, 16))
+    outs = []
+    for extra in (0, FLAG_NO_SPLIT):
+        with Solver(dim, n, levels, kappa=kappa, precision=prec, smoother=smoother, sigma=sigma,
+                    flags=fl | extra) as S:
+            u = u0.clone() if flags == "warm" else None
+            u, k, hist, st = S.solve(b, 1e-9, u=u)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])

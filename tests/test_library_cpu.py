@@ -64,7 +64,7 @@ def test_options_validation_and_footprint():
                 dict(dim=3, n=64, levels=1), dict(dim=2, n=1, levels=1),
                 dict(dim=3, n=16, levels=3, omega=0.0, smoother="jacobi"),
                 dict(dim=3, n=16, levels=3, max_iter=0),
-                dict(dim=3, n=16, levels=3, flags=64),
+                dict(dim=3, n=16, levels=3, flags=128),
                 dict(dim=3, n=16, levels=3, sigma=-1.0),
                 dict(dim=3, n=16, levels=3, sigma=float("nan")),
                 dict(dim=3, n=16, levels=3, sigma=float("inf")),
@@ -106,8 +106,9 @@ def test_paper_dof_counts_through_the_library():
 def test_pcg_footprint_adds_five_finest_vectors():
     mg = _lib()
     L = mg.lib()
-    o = mg.make_options(3, 64, 6)
-    o_pcg = mg.make_options(3, 64, 6, flags=mg.FLAG_PCG)
+    # (FP64 contexts without CG also hold a colour-split copy of b)
+    o = mg.make_options(3, 64, 6, flags=mg.FLAG_NO_SPLIT)
+    o_pcg = mg.make_options(3, 64, 6, flags=mg.FLAG_PCG | mg.FLAG_NO_SPLIT)
     extra = L.mg_footprint_bytes(ctypes.byref(o_pcg)) - L.mg_footprint_bytes(ctypes.byref(o))
     assert extra >= 5 * 8 * 65 ** 3
     assert extra <= 5 * 8 * 65 ** 3 + 2 * 8 * 1024 + 4096
