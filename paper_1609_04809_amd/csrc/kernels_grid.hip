@@ -659,6 +659,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   T* const ge = MODE == SW_CN ? (T*)const_cast<void*>(I.e) : nullptr;
   T gpf[2] = {T(0), T(0)};
   const long blay = I.lay;  // b colour-split (see Item::lay) or natural
+  // Red-black on a colour-split b: every unknown a half-sweep updates has
+  // parity `colour`, so its b is element p / 2 of that colour's half.  A
+  // lane clamped onto node (n, n, n) (parity 0) in a colour-1 sweep reads
+  // the one padding element past the odd half; its value is not used.
+  const int bsh = blay ? 1 : 0;
+  const T* const bq = b + (blay && colour ? blay : 0);
   auto prefetch_b = [&](int k) {
     const long p = pb0 + (long)min(k, n) * sz;
 #pragma unroll
@@ -836,7 +842,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     };
     // red-black: b of the unknown updated at plane p, for the next plane
     auto prefetch_b1 = [&](int up) {
-      bpf[0] = b[lay_idx(pb0 + (long)min(p, n) * sz + up, blay)];
+      bpf[0] = bq[(pb0 + (long)min(p, n) * sz + up) >> bsh];
     };
     if (!RB || ((colour + 1 + j + p) & 1) == 0) {  // i is odd
       if (RB) prefetch_b1(0);

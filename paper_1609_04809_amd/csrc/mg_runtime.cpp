@@ -180,11 +180,13 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     Level tmp;
     Level& L = c ? c->lv[l] : tmp;
     L.g = g;
+    // right-hand sides: one element past the nodes pads the odd half of a
+    // colour-split b (read, unused, by a red-black half-sweep's clamped lanes)
     if (l > 0) {
       L.x64 = P.take<double>(g.nodes);
-      L.b64 = P.take<double>(g.nodes);
+      L.b64 = P.take<double>(g.nodes + 1);
     } else if (split_b0(o)) {
-      L.b64 = P.take<double>(g.nodes);  // colour-split copy of the caller's b
+      L.b64 = P.take<double>(g.nodes + 1);  // colour-split copy of the caller's b
     }
     L.t64 = P.take<double>(g.nodes);
     L.r64 = P.take<double>(g.nodes);
@@ -198,7 +200,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     }
     if (ir) {
       L.x32 = P.take<float>(g.nodes);
-      L.b32 = P.take<float>(g.nodes);
+      L.b32 = P.take<float>(g.nodes + 1);
       L.t32 = P.take<float>(g.nodes);
       L.r32 = P.take<float>(g.nodes);
     }
