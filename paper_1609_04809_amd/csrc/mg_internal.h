@@ -39,6 +39,11 @@ __device__ __forceinline__ int xcd_remap(int bid, int nb) {
   return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
+// Entries past the last nonzero of a CSR level's column and value arrays,
+// set to column 0 and value 0 at setup: a row kernel loads the nonzeros in
+// aligned groups of 4 and may read up to 3 past the end (never summed).
+constexpr int kCsrPad = 4;
+
 // Largest coarsest system (unknowns) solved by the one-block Cholesky kernel.
 constexpr int kCoarseMaxUnknowns = 4096;
 

@@ -215,10 +215,10 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
       L.rows = (int)rows;
       L.nnz = nnz;
       L.rowptr = P.take<int>(rows + 1);
-      L.col = P.take<int>(nnz);
+      L.col = P.take<int>(nnz + kCsrPad);
       L.rowmap = P.take<int>(rows);
-      L.val64 = P.take<double>(nnz);
-      if (ir) L.val32 = P.take<float>(nnz);
+      L.val64 = P.take<double>(nnz + kCsrPad);
+      if (ir) L.val32 = P.take<float>(nnz + kCsrPad);
       maxpart = std::max(maxpart, csr_residual_blocks_max((int)rows));
     }
     maxpart = std::max(maxpart, std::max(grid_blocks(g), norm2_blocks(g)));
@@ -363,6 +363,9 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
                          hipMemcpyHostToDevice, s));
   const double selem = dim == 3 ? (1.0 / n) / 12.0 : 1.0 / 6.0;
   const double smass = c->o.sigma * std::pow((1.0 / n) / 6.0, dim);
+  HIP_TRY(hipMemsetAsync(Lv.col + Lv.nnz, 0, kCsrPad * sizeof(int), s));
+  HIP_TRY(hipMemsetAsync(Lv.val64 + Lv.nnz, 0, kCsrPad * sizeof(double), s));
+  if (Lv.val32) HIP_TRY(hipMemsetAsync(Lv.val32 + Lv.nnz, 0, kCsrPad * sizeof(float), s));
   launch_csr_build<double>(Lv.g, Lv.kap64, selem, smass, rows, Lv.rowmap, Lv.rowptr, Lv.col,
                            Lv.val64, s);
   if (Lv.val32)
