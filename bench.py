@@ -376,6 +376,9 @@ def main():
     log(f"[bench] headline {name}: {args.warmup} warmup + {args.steps} timed solves")
     res, roof, (b, kappa, u, k) = run_workload(name, args.steps, args.warmup,
                                                with_roofline=True)
+    if roof is not None and copy_gbs:
+        # the same rate against the copy this GPU attains (read + write)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
     log(f"[bench] {name}: {res['MDOF_per_s']} MDOF/s, {res['cycles']} cycles, "
         f"{res['ms_per_solve']} ms/solve; roofline {roof}")
     extra = []
