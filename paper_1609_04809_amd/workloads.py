@@ -46,8 +46,9 @@ class Workload:
         return (self.n - 1) ** self.dim
 
 
-# The five workloads of the benchmark.  Coarsest levels: 2D n_c = 4,
-# 3D n_c = 2 (or 3 for n = 192).
+# The workloads of the benchmark.  Coarsest levels: 2D n_c = 4, 3D n_c = 2
+# (or 3 for n = 192).  The variable-coefficient system is also solved in
+# FP64 for comparison with its FP32-inner form.
 WORKLOADS = {
     "poisson2d_64_jacobi": Workload(
         "poisson2d_64_jacobi", 2, 64, 5, "jacobi", "stencil", "fp64", 1e-10,
@@ -63,6 +64,9 @@ WORKLOADS = {
         "uniform", "none"),
     "kappa3d_192_rbgs_ir": Workload(
         "kappa3d_192_rbgs_ir", 3, 192, 7, "rbgs", "stencil", "fp32_ir", 1e-8,
+        "ones", "lognormal"),
+    "kappa3d_192_rbgs_fp64": Workload(
+        "kappa3d_192_rbgs_fp64", 3, 192, 7, "rbgs", "stencil", "fp64", 1e-8,
         "ones", "lognormal"),
 }
 
