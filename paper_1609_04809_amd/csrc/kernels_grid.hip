@@ -457,14 +457,19 @@ template <typename T> struct Vec2;
 template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
-// sweep3 launch shape: planes per block for a level (MG_SWEEP3_KZ overrides)
+// sweep3 launch shape: planes per block for a level with m unknowns per
+// direction (MG_SWEEP3_KZ overrides).  Levels below 255 are too small to
+// fill the chip with long z-marches, so their blocks march fewer planes
+// (more workgroups, less time per block); measured on MI355X, 1 plane at
+// 31, 2 at 63 and 4 at 127 took 3-4% off the 256^3 solves, while the
+// 191-wide variable-coefficient level keeps 8.
 inline int sweep3_kz(int m) {
   static const int forced = [] {
     const char* e = getenv("MG_SWEEP3_KZ");
     return e ? atoi(e) : 0;
   }();
   if (forced > 0) return forced;
-  return m >= 255 ? 16 : (m >= 127 ? 8 : 4);
+  return m >= 255 ? 16 : (m >= 191 ? 8 : (m >= 127 ? 4 : (m >= 63 ? 2 : 1)));
 }
 
 // PRO (smoothing modes): the coarse correction e of the next coarser level
