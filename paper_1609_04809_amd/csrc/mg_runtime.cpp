@@ -110,7 +110,7 @@ bool valid_options(const mg_options* o, std::string& why) {
   }
   const long nodes = ipow(o->n + 1L, o->dim);
   if (nodes >= (1L << 31)) { why = "grid too large for 32-bit node indices"; return false; }
-  if (o->op == MG_OP_CSR && csr_nnz(o->dim, o->n) >= (1L << 31)) {
+  if (o->op == MG_OP_CSR && csr_nnz(o->dim, o->n) + kCsrPad >= (1L << 31)) {
     why = "CSR matrix too large for 32-bit offsets";
     return false;
   }
