@@ -4,7 +4,7 @@ benchmark times.
 * 3D 128^3 CSR red-black FP64 (7 levels): the whole oracle solve (cycle
   count +-1, solution after the same cycles within 1e-8, histories).
 * 3D 256^3 stencil FP64 and FP32-IR (8 levels), 3D 192^3 variable kappa
-  FP32-IR (7 levels): the oracle cycle is too slow at these sizes, so the
+  FP32-IR and FP64 (7 levels): the oracle cycle is too slow at these sizes, so the
   solves are checked through properties that hold at any size -- the
   residual of the returned u recomputed by the oracle's cell-by-cell
   matrix-free operator is <= tol, and (Poisson) the distance to the exact
@@ -57,7 +57,7 @@ def _residual_matfree(dim, n, kappa, b_int, u_full):
 
 
 @pytest.mark.parametrize("name", ["poisson3d_256_rbgs_fp64", "poisson3d_256_rbgs_ir",
-                                  "kappa3d_192_rbgs_ir"])
+                                  "kappa3d_192_rbgs_ir", "kappa3d_192_rbgs_fp64"])
 def test_full_size_solve_meets_tolerance(name):
     torch_cuda()
     w = W.WORKLOADS[name]
