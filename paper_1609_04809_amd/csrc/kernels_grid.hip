@@ -476,11 +476,27 @@ inline int sweep3_kz(int m) {
 // (Item::e) is prolongated and added to x as x is staged, so the launch
 // smooths x + P e -- the prolongation step fused into the first
 // post-smoothing step, bitwise as k_prolong_add followed by the sweep.
-template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false>
+// XL (red-black half-sweeps only): layout of the iterate, for a run of
+// half-sweeps on a level with even n whose iterate is kept colour-split (the
+// even-index nodes, which are the red ones, at p / 2 of one half, the odd
+// ones at p / 2 of another; Item::a / Item::a2 are the halves read,
+// Item::c the half written).  0: natural in and out.  1: natural in, split
+// out -- the updated colour to Item::c, the other colour copied to
+// Item::c2.  2: split in and out, only the updated colour written.  3: split
+// in, natural out (both colours).  The arithmetic per node is the same in
+// every layout.
+template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false, int XL = 0>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
                                                 int nzc, int remap, Batch B) {
   using V2 = typename Vec2<T>::type;
   constexpr bool HEAD = MODE == SW_HEAD_RB0 || MODE == SW_HEAD_JAC;
+  static_assert(XL == 0 || ((MODE == SM_RB0 || MODE == SM_RB1) && !NORM) ||
+                    (MODE == SW_HEAD_RB0 && XL == 1),
+                "split iterates are for red-black half-sweeps");
+  static_assert(!PRO || XL <= 1, "the prolongation reads a natural iterate");
+  static_assert(!(ZERO && (XL == 2 || XL == 3)), "x = 0 is read in no layout");
+  constexpr bool XIN = XL == 2 || XL == 3;   // x read colour-split
+  constexpr bool XOUT = XL == 1 || XL == 2;  // updated unknowns written colour-split
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
@@ -498,9 +514,11 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   }
   const int item = bz / nzc, zc = bz % nzc;
   const Item& I = B.it[item];
-  const T* __restrict__ x = (const T*)I.a;
+  const T* __restrict__ x = (const T*)I.a;  // natural x, or its even half (XIN)
+  const T* __restrict__ xodd = XIN ? (const T*)I.a2 : nullptr;
   const T* __restrict__ b = (const T*)I.b;
-  T* __restrict__ out = (T*)I.c;
+  T* __restrict__ out = (T*)I.c;  // natural, or the updated colour's half (XOUT)
+  T* __restrict__ out2 = XL == 1 ? (T*)I.c2 : nullptr;
   const T* __restrict__ kap = (const T*)I.kappa;
   const int i0 = 1 + bx * SW_TX, j0 = 1 + by * SW_TY, k0 = 1 + zc * kz;
   const int k1 = min(k0 + kz - 1, m);
@@ -532,9 +550,18 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   // only the stencils of unknowns beyond m, which are never written, see
   // such a value.  The same holds for b and the cell coefficients below.
   auto prefetch_x = [&](int z) {
-    const T* __restrict__ xz = x + (long)min(z, n) * sz;
+    if constexpr (XIN) {
+      const long zb = (long)min(z, n) * sz;
 #pragma unroll
-    for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
+      for (int q = 0; q < NX; ++q) {
+        const long p = zb + xoff[q];
+        xpf[q] = ((p & 1) ? xodd : x)[p >> 1];
+      }
+    } else {
+      const T* __restrict__ xz = x + (long)min(z, n) * sz;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
+    }
   };
   // Coarse planes of e (PRO) for the tile and its halo: coarse columns
   // 64 bx .. 64 bx + 65, rows 2 by .. 2 by + 3, plane K in slot K % 3,
@@ -680,6 +707,19 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     }
   };
   auto store = [&](int k, int u, T v) { out[i + u + j * sy + (long)k * sz] = v; };
+  // red-black: an updated unknown, and one of the other colour (its old
+  // value, or 0 from x = 0), in the layout XL writes
+  auto store_upd = [&](int k, int u, T v) {
+    const long p = i + u + j * sy + (long)k * sz;
+    out[XOUT ? p >> 1 : p] = v;
+  };
+  auto store_oth = [&](int k, int u, T v) {
+    const long p = i + u + j * sy + (long)k * sz;
+    if (XL == 1)
+      out2[p >> 1] = v;
+    else if (!XOUT)
+      out[p] = v;
+  };
   double sq = 0.0;
   T kwp[2][3];  // cell window of layer p-1
 #pragma unroll
@@ -712,7 +752,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         if (!ok) continue;
         T dg = op.wc;
         if (KAP) dg = op.s * T(4) * kappa_cell_sum<T>(kwp, kwc, u);
-        store(k, u, !upd ? T(0) : (MODE == SM_JACOBI ? omega * (bpf[u] / dg) : bpf[u] / dg));
+        if (MODE == SM_JACOBI)
+          store(k, u, omega * (bpf[u] / dg));
+        else if (upd)
+          store_upd(k, u, bpf[u] / dg);
+        else
+          store_oth(k, u, T(0));
       }
       if (KAP) {
 #pragma unroll
@@ -837,13 +882,21 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
           sq += (double)res * (double)res;
           const T d = res / dg;
           const bool c0 = ((i + u + j + k) & 1) == 0;
-          store(k, u, MODE == SW_HEAD_JAC ? x1[q] + omega * d : (c0 ? x1[q] + d : x1[q]));
+          if (MODE == SW_HEAD_JAC)
+            store(k, u, x1[q] + omega * d);
+          else if (c0)
+            store_upd(k, u, x1[q] + d);
+          else
+            store_oth(k, u, x1[q]);
         } else {
           const T d = res / dg;
-          store(k, u, MODE == SM_JACOBI ? x1[q] + omega * d : x1[q] + d);
+          if (RB)
+            store_upd(k, u, x1[q] + d);
+          else
+            store(k, u, x1[q] + omega * d);
         }
       }
-      if (RB && (up == 0 ? ok0 : ok1)) store(k, up, xo1);  // the other unknown keeps its value
+      if (RB && (up == 0 ? ok0 : ok1)) store_oth(k, up, xo1);  // the other unknown keeps its value
     };
     // red-black: b of the unknown updated at plane p, for the next plane
     auto prefetch_b1 = [&](int up) {
@@ -1785,13 +1838,13 @@ inline int sweep3_remap() {
   return v;
 }
 
-template <typename T, int K, int MODE, bool ZERO, bool NORM>
+template <typename T, int K, int MODE, bool ZERO, bool NORM, int XL = 0>
 void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batch& B,
                    hipStream_t s) {
   int kz, nzc;
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
-  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM>), gr, dim3(64, SW_TY), 0, s, g, op, omega,
-                     kz, nzc, sweep3_remap(), B);
+  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM, false, XL>), gr, dim3(64, SW_TY), 0, s, g,
+                     op, omega, kz, nzc, sweep3_remap(), B);
 }
 }  // namespace
 
@@ -1890,9 +1943,44 @@ static void launch_sweep3_smooth(const Geo& g, const StencilParams<T>& op, int k
     launch_sweep3<T, K, SM_RB1, Z, false>(g, op, omega, B, s);
 }
 
+// red-black half-sweeps with a colour-split iterate (constant-coefficient
+// and mass-shifted kinds)
+template <typename T, int K, int M>
+static void launch_sweep3_split(const Geo& g, const StencilParams<T>& op, bool zero, int xl,
+                                const Batch& B, hipStream_t s) {
+  if (xl == XL_TO_SPLIT) {
+    if (zero)
+      launch_sweep3<T, K, M, true, false, XL_TO_SPLIT>(g, op, T(0), B, s);
+    else
+      launch_sweep3<T, K, M, false, false, XL_TO_SPLIT>(g, op, T(0), B, s);
+  } else if (xl == XL_SPLIT) {
+    launch_sweep3<T, K, M, false, false, XL_SPLIT>(g, op, T(0), B, s);
+  } else {
+    launch_sweep3<T, K, M, false, false, XL_TO_NATURAL>(g, op, T(0), B, s);
+  }
+}
+
+bool use_split_x(const Geo& g) { return use_sweep3(g); }
+
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s) {
+                   const Batch& B, hipStream_t s, int xl) {
+  if (xl != XL_NATURAL) {
+    // (the runtime splits iterates only for red-black on k_sweep3 levels
+    // of the constant-coefficient and mass-shifted kinds)
+    if (op.kind == OP_MASS) {
+      if (kind == SM_RB0)
+        launch_sweep3_split<T, OP_MASS, SM_RB0>(g, op, zero, xl, B, s);
+      else
+        launch_sweep3_split<T, OP_MASS, SM_RB1>(g, op, zero, xl, B, s);
+    } else {
+      if (kind == SM_RB0)
+        launch_sweep3_split<T, OP_CONST, SM_RB0>(g, op, zero, xl, B, s);
+      else
+        launch_sweep3_split<T, OP_CONST, SM_RB1>(g, op, zero, xl, B, s);
+    }
+    return;
+  }
   if (kind >= SM_GS0) {
     const dim3 gr = node_grid(g, B.count), bl(BX, BY);
 #define L_GS(D, K) \
@@ -1926,11 +2014,25 @@ bool pair_sweeps(const Geo& g) { return use_sweep3(g); }
 
 template <typename T>
 void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T omega,
-                           const Batch& B, hipStream_t s) {
+                           const Batch& B, hipStream_t s, int xl) {
   int kz, nzc;
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
   const dim3 bl(64, SW_TY);
   const int rm = sweep3_remap();
+  if (xl == XL_TO_SPLIT) {
+    // (red-black on split-iterate levels: constant-coefficient and
+    // mass-shifted kinds)
+#define L_SPX(K, M)                                                                        \
+  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true, XL_TO_SPLIT>), gr, bl, 0, s, g, op, \
+                     omega, kz, nzc, rm, B)
+    if (op.kind == OP_MASS) {
+      if (kind == SM_RB0) L_SPX(OP_MASS, SM_RB0); else L_SPX(OP_MASS, SM_RB1);
+    } else {
+      if (kind == SM_RB0) L_SPX(OP_CONST, SM_RB0); else L_SPX(OP_CONST, SM_RB1);
+    }
+#undef L_SPX
+    return;
+  }
 #define L_SP(K, M) \
   hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true>), gr, bl, 0, s, g, op, omega, kz, nzc, rm, B)
 #define L_SP_K(K)                                          \
@@ -1977,8 +2079,17 @@ void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, boo
 
 template <typename T>
 void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
-                 hipStream_t s) {
+                 hipStream_t s, int xl) {
   const bool jac = kind == SM_JACOBI;
+  if (xl == XL_TO_SPLIT) {
+    // (red-black heads on split-iterate levels: constant-coefficient and
+    // mass-shifted kinds)
+    if (op.kind == OP_MASS)
+      launch_sweep3<T, OP_MASS, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
+    else
+      launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
+    return;
+  }
   if (use_sweep3(g)) {
     with_kind3(op.kind, [&](auto k) {
       constexpr int K = decltype(k)::value;
@@ -2164,11 +2275,11 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_smooth_pair<T>(const Geo&, const StencilParams<T>&, int, bool,      \
                                       const Batch&, hipStream_t);                           \
   template void launch_smooth_prolong<T>(const Geo&, const StencilParams<T>&, int, T,       \
-                                         const Batch&, hipStream_t);                        \
+                                         const Batch&, hipStream_t, int);                   \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
-                                 const Batch&, hipStream_t);                                \
+                                 const Batch&, hipStream_t, int);                           \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \
-                               hipStream_t);                                                \
+                               hipStream_t, int);                                           \
   template void launch_apply_dot<T>(const Geo&, const StencilParams<T>&, const Batch&,      \
                                     hipStream_t);                                           \
   template void launch_restrict<T>(const Geo&, const Geo&, const Batch&, hipStream_t);      \

@@ -24,6 +24,10 @@ struct Level {
   double *p64 = nullptr, *q64 = nullptr, *z64 = nullptr, *rk64 = nullptr, *ro64 = nullptr;
   // FP32 vectors (FP32_IR contexts)
   float *x32 = nullptr, *b32 = nullptr, *t32 = nullptr, *r32 = nullptr;
+  // two colour-split iterates (even half, then odd half from (nodes+1)/2),
+  // zero on the boundary, on levels whose red-black runs keep x split
+  double* xs64[2] = {nullptr, nullptr};
+  float* xs32[2] = {nullptr, nullptr};
   // coefficients per cell
   double* kap64 = nullptr;
   float* kap32 = nullptr;

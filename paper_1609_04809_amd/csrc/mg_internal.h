@@ -91,6 +91,8 @@ struct Item {
   double* scal;
   const double* L;
   const void* e;  // coarse correction (prolongation fused into a sweep)
+  const void* a2;  // colour-split iterate: the odd half read (a: the even half)
+  void* c2;        // colour-split iterate: the other colour's half written
   int flag;
   // Colour-split layout of the level's right-hand side read by a sweep (or
   // of the vector a restriction / FP32 cast writes): node p is stored at
@@ -209,9 +211,16 @@ void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const 
 // One smoothing step (SmoothKind); a == nullptr means x = 0 (then for every
 // item):  a = x_in, b = b, c = x_out, kappa.  Gauss-Seidel colour steps
 // (kind >= SM_GS0) update c in place (a is ignored, zero is not allowed).
+// xl (red-black on levels where use_split_x(g), XLayout): the iterate's
+// layout in and out -- split halves are a (even) / a2 (odd) when read, c
+// (the updated colour) and c2 (the other colour, XL_TO_SPLIT) when written.
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s);
+                   const Batch& B, hipStream_t s, int xl = 0);
+enum XLayout { XL_NATURAL = 0, XL_TO_SPLIT = 1, XL_SPLIT = 2, XL_TO_NATURAL = 3 };
+// Whether k_sweep3 runs the level (3D, n >= 32), which is where split
+// iterates are possible.
+bool use_split_x(const Geo& g);
 // Two red-black half-sweeps in one pass, colour `first` (SM_RB0 / SM_RB1)
 // then the other; bitwise the result of two launch_smooth calls.  Only on
 // levels where pair_sweeps(g):  a = x_in (nullptr: x = 0), b = b, c = x_out.
@@ -219,10 +228,11 @@ bool pair_sweeps(const Geo& g);
 // x + P e, then one smoothing step (SM_JACOBI / SM_RB0 / SM_RB1) of it, in
 // one pass; bitwise launch_prolong_add followed by launch_smooth.  Only on
 // levels where pair_sweeps(g):  a = x (the level's iterate before the
-// correction), e = e (coarse correction), b = b, c = x_out.
+// correction), e = e (coarse correction), b = b, c = x_out (with xl =
+// XL_TO_SPLIT, red-black: c the updated colour's half, c2 the other's).
 template <typename T>
 void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T omega,
-                           const Batch& B, hipStream_t s);
+                           const Batch& B, hipStream_t s, int xl = 0);
 template <typename T>
 void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
                         const Batch& B, hipStream_t s);
@@ -237,10 +247,12 @@ template <typename T>
 void launch_coarse_solve(const Geo& gc, int m, const Batch& B, hipStream_t s);
 // In one pass over x: per-block partial sums of (b - A x)^2 (as the residual
 // launch writes them) and the first smoothing step of the next cycle, kind
-// SM_JACOBI or SM_RB0:  a = x, b = b, c = x_out, kappa, partials.
+// SM_JACOBI or SM_RB0:  a = x, b = b, c = x_out, kappa, partials.  With xl =
+// XL_TO_SPLIT (red-black on split-iterate levels) x_out is written
+// colour-split: c = the even half, c2 = the odd half.
 template <typename T>
 void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
-                 hipStream_t s);
+                 hipStream_t s, int xl = 0);
 // Per-block partial sums of v^2:  a = v, partials.
 template <typename T>
 void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s);

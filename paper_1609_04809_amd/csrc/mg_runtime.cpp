@@ -19,6 +19,7 @@
 #include <functional>
 #include <initializer_list>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -168,6 +169,14 @@ long b_split_half(const mg_ctx* c, int l, int prec) {
   return (c->lv[l].g.nodes + 1) / 2;
 }
 
+// Whether the red-black half-sweeps of a level (elements of elem bytes)
+// keep the iterate colour-split between the first and the last half-sweep
+// of a smoothing run: matrix-free constant-coefficient or mass-shifted
+// levels where the right-hand side is split too.
+bool split_x_level(const mg_options& o, bool has_kappa, int nl, int elem) {
+  return !has_kappa && o.smoother == MG_SMOOTH_RBGS && split_level(o, nl, elem);
+}
+
 // Lay out every buffer of a context; with base == nullptr only sizes.
 size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
   Planner P(base);
@@ -203,6 +212,16 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
       L.b32 = P.take<float>(g.nodes + 1);
       L.t32 = P.take<float>(g.nodes);
       L.r32 = P.take<float>(g.nodes);
+    }
+    // colour-split iterates for the red-black runs of the cycles (FP64
+    // cycles, or the FP32 inner cycles)
+    if (split_x_level(o, has_kappa, nl, ir ? 4 : 8)) {
+      for (int q = 0; q < 2; ++q) {
+        if (ir)
+          L.xs32[q] = P.take<float>(g.nodes + 1);
+        else
+          L.xs64[q] = P.take<double>(g.nodes + 1);
+      }
     }
     const long cells = ipow(nl, o.dim);
     if (has_kappa) {
@@ -455,6 +474,7 @@ template <> struct Bufs<double> {
   static const StencilParams<double>& st(Level& L) { return L.st64; }
   static const CsrOp<double>* csr(Level& L) { return &L.csr64; }
   static void* tail(mg_ctx* c) { return c->tail64; }
+  static double* xs(Level& L, int q) { return L.xs64[q]; }
 };
 template <> struct Bufs<float> {
   static constexpr int prec = 1;
@@ -466,6 +486,7 @@ template <> struct Bufs<float> {
   static const StencilParams<float>& st(Level& L) { return L.st32; }
   static const CsrOp<float>* csr(Level& L) { return &L.csr32; }
   static void* tail(mg_ctx* c) { return c->tail32; }
+  static float* xs(Level& L, int q) { return L.xs32[q]; }
 };
 
 template <typename T>
@@ -552,6 +573,16 @@ OpRec base_op(mg_ctx* c, int code, int l) {
   return o;
 }
 
+// Whether the red-black runs on level l keep the iterate colour-split (the
+// level has split-iterate buffers of this precision).
+template <typename T>
+bool split_iterate(const mg_ctx* c, int l) {
+  const Level& Lv = c->lv[l];
+  return !c->csr && c->o.smoother == MG_SMOOTH_RBGS && !(c->o.flags & MG_FLAG_PAIR) &&
+         use_split_x(Lv.g) && (std::is_same<T, double>::value ? (void*)Lv.xs64[0]
+                                                               : (void*)Lv.xs32[0]) != nullptr;
+}
+
 template <typename T>
 void emit_smooth(mg_ctx* c, const Sink& sink, int l, int kind, const T* xin, const T* b,
                  T* xout) {
@@ -589,6 +620,13 @@ void emit_head(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* xo
   o.item.c = xout;
   o.item.partials = partials;
   if (c->csr) o.csr = Bufs<T>::csr(c->lv[l]);
+  if (split_iterate<T>(c, l)) {
+    // the next cycle's smoothing run continues from the split halves
+    Level& Lv = c->lv[l];
+    o.sub |= XL_TO_SPLIT << 5;
+    o.item.c = Bufs<T>::xs(Lv, 0);
+    o.item.c2 = Bufs<T>::xs(Lv, 0) + (Lv.g.nodes + 1) / 2;
+  }
   sink(o);
 }
 
@@ -612,6 +650,54 @@ void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
   sink(o);
 }
 
+// A run of red-black half-sweeps (steps) on a level with colour-split
+// iterate buffers xs[0..1]: the first step reads *cur (or x = 0) and writes
+// both halves of xs[0] (from_split: a fused step before the run -- the
+// head or the prolongation -- has already written them); each middle step reads the current even and odd
+// halves and writes only the updated colour's half, into the buffer that
+// does not hold that colour's current half; the last step writes the
+// natural iterate where the ping-pong of natural steps would have left it
+// (*cur after an even number of steps, else *spare).  Every node gets the
+// arithmetic of the natural steps, so the result is bitwise theirs; the
+// middle steps do not copy the other colour.
+template <typename T>
+void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& steps, T** cur,
+                    T** spare, bool* zero, const T* b, bool from_split = false) {
+  Level& Lv = c->lv[l];
+  T* xs[2] = {Bufs<T>::xs(Lv, 0), Bufs<T>::xs(Lv, 1)};
+  const long lay = (Lv.g.nodes + 1) / 2;  // start of the odd half
+  int at[2] = {0, 0};                      // buffer holding the even / odd half
+  const size_t last = steps.size() - 1;
+  const bool back = steps.size() % 2 == 0;
+  for (size_t q = 0; q <= last; ++q) {
+    const int col = steps[q] == SM_RB1 ? 1 : 0;  // parity of the updated nodes
+    const bool first = q == 0 && !from_split;
+    const bool z = first && *zero;
+    const int xl = first ? XL_TO_SPLIT : (q == last ? XL_TO_NATURAL : XL_SPLIT);
+    OpRec o = base_op<T>(c, OC_SMOOTH, l);
+    o.sub = steps[q] | ((z ? 1 : 0) << 4) | (xl << 5);
+    o.item.b = b;
+    if (first) {
+      o.item.a = z ? nullptr : *cur;
+      o.item.c = xs[0] + (col ? lay : 0);
+      o.item.c2 = xs[0] + (col ? 0 : lay);
+    } else {
+      o.item.a = xs[at[0]];
+      o.item.a2 = xs[at[1]] + lay;
+      if (q == last) {
+        o.item.c = back ? *cur : *spare;
+      } else {
+        const int dst = 1 - at[col];
+        o.item.c = xs[dst] + (col ? lay : 0);
+        at[col] = dst;
+      }
+    }
+    sink(o);
+  }
+  if (!back) std::swap(*cur, *spare);
+  *zero = false;
+}
+
 // Smoothing on level l from *cur (or from 0 if *zero), ping-ponging between
 // *cur and *spare; on return *cur holds the smoothed iterate.  With
 // `skip`, the first step is not emitted: it has already been done, from
@@ -620,7 +706,7 @@ void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
 // the same result).
 template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
-                  const T* b, bool skip = false) {
+                  const T* b, bool skip = false, bool from_split = false) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
   if (c->o.smoother == MG_SMOOTH_GS) {
     // multicolour Gauss-Seidel: one in-place launch per colour, colours in
@@ -648,6 +734,14 @@ void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spa
   if (skip && !steps.empty()) steps.erase(steps.begin());
   const bool pairs = !c->csr && c->o.smoother == MG_SMOOTH_RBGS &&
                      pair_sweeps(c->lv[l].g) && (c->o.flags & MG_FLAG_PAIR);
+  if (from_split) {
+    emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b, true);
+    return;
+  }
+  if (!pairs && steps.size() >= 3 && split_iterate<T>(c, l)) {
+    emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b);
+    return;
+  }
   for (size_t q = 0; q < steps.size();) {
     if (pairs && q + 1 < steps.size()) {
       OpRec o = base_op<T>(c, OC_SMOOTH2, l);
@@ -721,7 +815,8 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       return;
     }
     bool z = zero;
-    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done);
+    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
+                    l == 0 && head_done && split_iterate<T>(c, 0));
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, l);
@@ -749,9 +844,17 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       o.item.e = cur[l + 1];
       o.item.b = bb[l];
       o.item.c = spare[l];
+      const bool sx = split_iterate<T>(c, l);
+      if (sx) {
+        // colour 1 updated into the odd half, colour 0 copied to the even one
+        Level& Lv = c->lv[l];
+        o.sub |= XL_TO_SPLIT << 5;
+        o.item.c = Bufs<T>::xs(Lv, 0) + (Lv.g.nodes + 1) / 2;
+        o.item.c2 = Bufs<T>::xs(Lv, 0);
+      }
       sink(o);
       std::swap(cur[l], spare[l]);
-      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true);
+      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true, sx);
     } else {
       OpRec pr = base_op<T>(c, OC_PROLONG, l);
       pr.item.a = cur[l + 1];
@@ -1064,7 +1167,8 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
   const Item& it = B.it[0];
   switch (o.code) {
     case OC_SMOOTH:
-      launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, (T)o.omega, B, s);
+      launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, ((o.sub >> 4) & 1) != 0, (T)o.omega, B,
+                       s, (o.sub >> 5) & 3);
       break;
     case OC_RESID: launch_residual<T>(o.g, params_of<T>(o), o.sub != 0, B, s); break;
     case OC_RESTRICT: launch_restrict<T>(o.g, o.gc, B, s); break;
@@ -1083,11 +1187,16 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
       launch_csr_residual<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (const T*)it.b,
                              (T*)it.c, it.partials, s);
       break;
-    case OC_HEAD: launch_head<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
+    case OC_HEAD:
+      launch_head<T>(o.g, params_of<T>(o), o.sub & 15, (T)o.omega, B, s, (o.sub >> 5) & 3);
+      break;
     case OC_SMOOTH2:
       launch_smooth_pair<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, B, s);
       break;
-    case OC_SMOOTH_PRO: launch_smooth_prolong<T>(o.g, params_of<T>(o), o.sub, (T)o.omega, B, s); break;
+    case OC_SMOOTH_PRO:
+      launch_smooth_prolong<T>(o.g, params_of<T>(o), o.sub & 15, (T)o.omega, B, s,
+                               (o.sub >> 5) & 3);
+      break;
     case OC_APPLY_DOT: launch_apply_dot<T>(o.g, params_of<T>(o), B, s); break;
     case OC_CSR_APPLY_DOT:
       launch_csr_apply_dot<T>(o.g, *(const CsrOp<T>*)o.csr, (const T*)it.a, (T*)it.c,

@@ -302,3 +302,33 @@ def test_colour_split_right_hand_sides_agree_bitwise(dim, n, levels, kap, prec, 
             outs.append((k, hist, host_full(u)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+@pytest.mark.parametrize("prec,nu,sigma,cycle,flags", [
+    # the runs of red-black half-sweeps keep the iterate colour-split on
+    # these levels; every schedule gives bitwise the natural-layout result
+    ("fp64", (2, 2), 0.0, "V", 0),
+    ("fp64", (2, 2), 0.0, "V", "nofuse"),
+    ("fp64", (3, 3), 200.0, "V", "warm"),
+    ("fp64", (3, 1), 0.0, "W", 0),
+    ("fp64", (1, 2), 0.0, "F", "nograph"),
+    ("fp32_ir", (3, 3), 0.0, "V", 0),
+])
+def test_colour_split_iterates_agree_bitwise(prec, nu, sigma, cycle, flags):
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import (FLAG_NO_FUSE, FLAG_NO_GRAPH, FLAG_NO_SPLIT, FLAG_WARM,
+                                         Solver)
+    n, levels = (256, 8) if prec == "fp64" else (384, 8)
+    b = dev_full(3, n, W.rhs_uniform(3, n, 25))
+    fl = {0: 0, "warm": FLAG_WARM, "nofuse": FLAG_NO_FUSE, "nograph": FLAG_NO_GRAPH}[flags]
+    u0 = dev_full(3, n, 0.01 * W.rhs_uniform(3, n, 26))
+    outs = []
+    for extra in (0, FLAG_NO_SPLIT):
+        with Solver(3, n, levels, precision=prec, sigma=sigma, nu_pre=nu[0], nu_post=nu[1],
+                    cycle=cycle, flags=fl | extra) as S:
+            u = u0.clone() if flags == "warm" else None
+            u, k, hist, st = S.solve(b, 1e-9, u=u)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
