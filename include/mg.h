@@ -107,15 +107,21 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 updated residual.  V- or W-cycles only (the
                                 F-cycle is not symmetric).  Not for the
                                 server. */
-#define MG_FLAG_NO_SPLIT 64  /* keep every right-hand side in the natural
-                                layout.  By default the right-hand sides of
-                                the 3D matrix-free levels with even n whose
-                                vectors reach 128 MB are stored colour-split
-                                -- even-indexed nodes first, then odd-indexed
+#define MG_FLAG_NO_SPLIT 64  /* keep every vector in the natural layout.
+                                By default the right-hand sides of the 3D
+                                matrix-free levels with even n whose vectors
+                                reach 128 MB are stored colour-split --
+                                even-indexed nodes first, then odd-indexed
                                 ones, which for even n are the two red-black
                                 colours -- so a half-sweep reads its colour's
                                 half only (mg_solve without CG keeps a split
-                                copy of an FP64 b).  Same results bitwise. */
+                                copy of an FP64 b); with red-black smoothing
+                                and no kappa the iterate is also kept split
+                                between the first and the last half-sweep of
+                                each smoothing run (two more vectors per such
+                                level), so the middle half-sweeps write only
+                                the colour they update.  Same results
+                                bitwise. */
 #define MG_FLAG_WARM 32      /* mg_solve starts from the u it is given (a
                                 warm start, e.g. the previous time step)
                                 instead of u = 0: it sets u's boundary
