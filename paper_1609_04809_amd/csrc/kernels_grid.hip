@@ -1308,6 +1308,23 @@ __global__ __launch_bounds__(256) void k_norm2_partial(Geo g, Batch B) {
     I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * plane)] = t;
 }
 
+// The partial sums of k_norm2_partial (same grid, same order) for v = I.a,
+// and the colour-split copy of v on the unknowns into I.c (odd half at
+// I.lay) in the same pass.  The copy's boundary entries are not written.
+template <int DIM>
+__global__ __launch_bounds__(256) void k_split_norm(Geo g, Batch B) {
+  NODE_INDEX(DIM, g)
+  double sq = 0.0;
+  if (inside) {
+    const double a = ((const double*)I.a)[p];
+    ((double*)I.c)[lay_idx(p, I.lay)] = a;
+    sq = a * a;
+  }
+  const double t = block_sum(sq);
+  if (threadIdx.x == 0 && threadIdx.y == 0)
+    I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * plane)] = t;
+}
+
 // b32 = float(r / ||r||) on the unknowns, ||r||^2 read from device memory.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_scale_cast(Geo g, Batch B) {
@@ -1777,13 +1794,6 @@ __global__ __launch_bounds__(256) void k_cn_bnd(Geo g, CnWeights w, const double
   b[p] += acc;
 }
 
-__global__ void k_split_copy(const double* __restrict__ src, double* __restrict__ dst, long count,
-                             long lay) {
-  long t = blockIdx.x * (long)blockDim.x + threadIdx.x;
-  const long stride = (long)gridDim.x * blockDim.x;
-  for (; t < count; t += stride) dst[lay_idx(t, lay)] = src[t];
-}
-
 // v = 0 on the boundary nodes; thread t covers one node of the 2 dim faces.
 template <int DIM>
 __global__ void k_zero_boundary(Geo g, double* __restrict__ v) {
@@ -2153,11 +2163,6 @@ void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, double* gu
     hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
 }
 
-void launch_split_copy(const double* src, double* dst, long count, long lay, hipStream_t s) {
-  hipLaunchKernelGGL(k_split_copy, dim3(flat_blocks(count)), dim3(256), 0, s, src, dst, count,
-                     lay);
-}
-
 void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, const double* g0,
                          double* b, hipStream_t s) {
   const dim3 gr = node_grid(g, 1), bl(BX, BY);
@@ -2207,6 +2212,21 @@ void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s) {
     hipLaunchKernelGGL((k_norm2_partial<T, 2>), gr, bl, 0, s, g, B);
   else
     hipLaunchKernelGGL((k_norm2_partial<T, 3>), gr, bl, 0, s, g, B);
+}
+
+void launch_split_norm(const Geo& g, const double* src, double* dst, long lay,
+                       double* partials, hipStream_t s) {
+  Batch B{};
+  B.count = 1;
+  B.it[0].a = src;
+  B.it[0].c = dst;
+  B.it[0].lay = lay;
+  B.it[0].partials = partials;
+  const dim3 gr = node_grid(g, 1), bl(BX, BY);
+  if (g.dim == 2)
+    hipLaunchKernelGGL(k_split_norm<2>, gr, bl, 0, s, g, B);
+  else
+    hipLaunchKernelGGL(k_split_norm<3>, gr, bl, 0, s, g, B);
 }
 
 void launch_reduce_final(long count, const Batch& B, hipStream_t s) {

@@ -297,8 +297,12 @@ void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, cons
                          double* b, hipStream_t s);
 // v = 0 on the boundary nodes of the level (interior untouched).
 void launch_zero_boundary(const Geo& g, double* v, hipStream_t s);
-// dst[lay_idx(p, lay)] = src[p] for every node p (natural -> colour-split).
-void launch_split_copy(const double* src, double* dst, long count, long lay, hipStream_t s);
+// dst[lay_idx(p, lay)] = src[p] on the unknowns p (natural -> colour-split;
+// the boundary entries of dst are not written), with the per-block partial
+// sums of src^2 that launch_norm2_partial writes (same grid and order, so
+// the same bits), in one pass.
+void launch_split_norm(const Geo& g, const double* src, double* dst, long lay,
+                       double* partials, hipStream_t s);
 
 // ---- CSR kernels (kernels_csr.hip) ----------------------------------------
 // Entries of K + sigma M: s_elem scales the stiffness element factors,

@@ -1012,15 +1012,17 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
 // for a warm-started solve with head fusion in one pass with the first
 // smoothing step of the first cycle (into the level-0 spare, as at the end
 // of an IT_FUSED_FIRST iteration), else with the residual in r64.
-// bn: b in the natural layout for its norm (default: b itself).
+// norm_ready: the partial sums of ||b||^2 are already in c->partials.
 void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool warm = false,
-                   bool fuse = false, const double* bn = nullptr) {
+                   bool fuse = false, bool norm_ready = false) {
   Level& L0 = c->lv[0];
   emit_start(c, sink, u, warm);
-  OpRec o = base_op<double>(c, OC_NORM2, 0);
-  o.item.a = bn ? bn : b;
-  o.item.partials = c->partials;
-  sink(o);
+  if (!norm_ready) {
+    OpRec o = base_op<double>(c, OC_NORM2, 0);
+    o.item.a = b;
+    o.item.partials = c->partials;
+    sink(o);
+  }
   emit_reduce(c, sink, norm2_blocks(L0.g), c->scal + 1);
   if (warm && fuse) {
     emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
@@ -1430,14 +1432,14 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   const double* bc = b;  // b as the cycles read it
   if (c->b0_split) {
     // the level-0 right-hand side colour-split (each half-sweep then reads
-    // its colour's half)
-    launch_split_copy(b, c->lv[0].b64, c->lv[0].g.nodes, b_split_half(c, 0, 0), s);
+    // its colour's half), with the partial sums of ||b||^2 in the same pass
+    launch_split_norm(c->lv[0].g, b, c->lv[0].b64, b_split_half(c, 0, 0), c->partials, s);
     bc = c->lv[0].b64;
   }
   if (pcg)
     emit_pcg_prologue(c, launch_sink(c, s), u, b, warm);
   else
-    emit_prologue(c, launch_sink(c, s), u, bc, warm, fuse, b);
+    emit_prologue(c, launch_sink(c, s), u, bc, warm, fuse, c->b0_split);
   HIP_TRY(hipGetLastError());
   double nb2 = 0.0;
   mg_status st = read_scalar(c, 1, &nb2, s);
