@@ -536,10 +536,17 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   constexpr int NK = ((SW_TX + 1) * (SW_TY + 1) + 255) / 256;
   int xoff[NX];  // node offsets within a plane (grids have < 2^31 nodes)
   T xpf[NX];
+  // A split iterate (XIN) is staged with the columns of each row sorted by
+  // parity -- element c of a row takes column 2c (c < SW_LX / 2) or column
+  // 2 (c - SW_LX / 2) + 1 -- so that neighbouring lanes read neighbouring
+  // entries of one half.
+  auto xcol = [&](int cc) {
+    return XIN ? (cc < SW_LX / 2 ? 2 * cc : 2 * (cc - SW_LX / 2) + 1) : cc;
+  };
 #pragma unroll
   for (int q = 0; q < NX; ++q) {
     const int e = tid + 256 * q;
-    const int r = e / SW_LX, c = e - r * SW_LX;
+    const int r = e / SW_LX, c = xcol(e - r * SW_LX);
     const int gi = i0 - 1 + c, gj = j0 - 1 + r;
     xoff[q] = min(gi, n) + min(gj, n) * (int)sy;  // always inside the grid
   }
@@ -620,6 +627,9 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         if (PRO) {
           const int r = e / SW_LX, c = e - r * SW_LX;
           dst[e] = xpf[q] + pe(i0 - 1 + c, j0 - 1 + r, min(z, n));
+        } else if (XIN) {
+          const int r = e / SW_LX;
+          dst[r * SW_LX + xcol(e - r * SW_LX)] = xpf[q];
         } else {
           dst[e] = xpf[q];
         }
