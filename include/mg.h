@@ -153,9 +153,9 @@ typedef struct {
  * sigma = 0. */
 void mg_options_default(mg_options* o);
 
-/* Device bytes that mg_setup(o, kappa_dev != NULL, ...) allocates for its
- * arena (an upper bound when kappa_dev is NULL); 0 if the options are
- * invalid. */
+/* Device bytes that mg_setup(o, ...) allocates for its arena: the larger of
+ * the footprints with and without a kappa_dev, so an upper bound either
+ * way; 0 if the options are invalid. */
 size_t mg_footprint_bytes(const mg_options* o);
 
 /* Build the level hierarchy (Sec. 5.1): coefficients per level, operators

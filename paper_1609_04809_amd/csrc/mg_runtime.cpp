@@ -1312,7 +1312,8 @@ size_t mg_footprint_bytes(const mg_options* o) {
     fail(MG_E_ARG, "%s", why.c_str());
     return 0;
   }
-  return plan(*o, true, nullptr, nullptr);
+  // with or without per-cell kappa (the split iterates exist only without)
+  return std::max(plan(*o, true, nullptr, nullptr), plan(*o, false, nullptr, nullptr));
 }
 
 mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, mg_ctx** out) {

@@ -112,3 +112,47 @@ def test_pcg_footprint_adds_five_finest_vectors():
     extra = L.mg_footprint_bytes(ctypes.byref(o_pcg)) - L.mg_footprint_bytes(ctypes.byref(o))
     assert extra >= 5 * 8 * 65 ** 3
     assert extra <= 5 * 8 * 65 ** 3 + 2 * 8 * 1024 + 4096
+
+
+def _aligned(nbytes):
+    return (nbytes + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("kw,split_b,split_x", [
+    # 257^3 FP64 vectors (136 MB) are split; 129^3 ones (17 MB) are not
+    (dict(dim=3, n=256, levels=8), True, 2),
+    # FP32-inner cycles: the FP32 iterate of 385^3 (228 MB) is split, and
+    # there is no FP64 copy of b
+    (dict(dim=3, n=384, levels=8, precision="fp32_ir"), False, 2),
+    # CG keeps b natural (its residual is separate) but the cycles' iterate split
+    (dict(dim=3, n=256, levels=8, flags=8), False, 2),
+    # the mass-shifted operator of the heat equation, two levels above 128 MB
+    (dict(dim=3, n=512, levels=9, sigma=200.0), True, 4),
+    # below 128 MB nothing is split
+    (dict(dim=3, n=128, levels=7), False, 0),
+    # multicolour Gauss-Seidel and 2D grids keep every vector natural
+    (dict(dim=3, n=256, levels=8, smoother="gs"), False, 0),
+    (dict(dim=2, n=8192, levels=10), False, 0),
+])
+def test_split_layout_footprint(kw, split_b, split_x):
+    """The colour-split vectors MG_FLAG_NO_SPLIT turns off: a split copy of
+    the FP64 right-hand side and two split iterates per large level (only
+    without kappa; the footprint is the larger of the plans with and
+    without kappa)."""
+    mg = _lib()
+    L = mg.lib()
+    kw = dict(kw)
+    flags = kw.pop("flags", 0)
+    dim, n, levels = kw["dim"], kw["n"], kw["levels"]
+    ir = kw.get("precision") == "fp32_ir"
+    elem = 4 if ir else 8
+    f = L.mg_footprint_bytes(ctypes.byref(mg.make_options(flags=flags, **kw)))
+    f_nat = L.mg_footprint_bytes(ctypes.byref(mg.make_options(flags=flags | mg.FLAG_NO_SPLIT,
+                                                               **kw)))
+    nodes = lambda l: ((n >> l) + 1) ** dim
+    d_b = _aligned((nodes(0) + 1) * 8) if split_b else 0
+    # split iterates on the first split_x / 2 levels
+    d_x = sum(2 * _aligned((nodes(l) + 1) * elem) for l in range(split_x // 2))
+    kap = sum(_aligned((n >> l) ** dim * 8) + (_aligned((n >> l) ** dim * 4) if ir else 0)
+              for l in range(levels))
+    assert f - f_nat == max(d_b, d_b + d_x - kap), (f - f_nat, d_b, d_x, kap)
