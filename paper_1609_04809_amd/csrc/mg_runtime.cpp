@@ -144,8 +144,7 @@ int tail_start(const mg_options& o, bool kappa) {
 // swept by k_sweep3 with red-black or Jacobi smoothing on single
 // half-sweeps, even n_l (then a node's index parity is its colour), and
 // vectors of at least 128 MB, which stream from HBM (smaller levels stay in
-// the 256 MB last-level cache, where the split layout measured no gain and
-// its index arithmetic cost 1-3%).
+// the 256 MB last-level cache, where the split layout measured no gain).
 constexpr long kSplitMinBytes = 128L << 20;
 bool split_level(const mg_options& o, int nl, int elem) {
   const long nodes = (long)(nl + 1) * (nl + 1) * (nl + 1);
