@@ -59,6 +59,21 @@ def time_solves(S, bd, tol, steps, warmup):
     return (t1 - t0) / steps, k, hist, u
 
 
+def solve_spread(S, bd, tol, steps):
+    """Median and minimum of `steps` single solves, each bracketed by
+    device synchronisations (after the timed loop, outside it)."""
+    import torch
+    u = torch.empty_like(bd)
+    ts = []
+    for _ in range(steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.solve(bd, tol, u=u)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), float(np.min(ts))
+
+
 def reference_copy(mib):
     """Attainable bandwidth: a plain device-to-device copy of `mib` MiB
     (read + write bytes / time), 1 warm-up + up to 10 timed copies."""
@@ -204,6 +219,10 @@ def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V",
            "cycles": k, "final_rel_residual": hist[-1], "setup_s": round(setup_s, 3),
            "precision": w.precision, "op": w.op, "method": "pcg" if pcg else "cycle",
            "cycle": cycle, "smoother": sm}
+    if with_roofline:
+        med, mn = solve_spread(S, bd, w.tol, steps)
+        res["ms_per_solve_median"] = round(med * 1e3, 3)
+        res["ms_per_solve_min"] = round(mn * 1e3, 3)
     roof = None
     if pcg or cycle != "V" or sm != w.smoother:
         pass
@@ -453,6 +472,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": res["ms_per_solve"],
+        "ms_per_step_median_single": res.get("ms_per_solve_median"),
+        "ms_per_step_min_single": res.get("ms_per_solve_min"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
