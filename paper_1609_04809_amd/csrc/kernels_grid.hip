@@ -458,18 +458,21 @@ template <> struct Vec2<double> { using type = double2; };
 template <> struct Vec2<float> { using type = float2; };
 
 // sweep3 launch shape: planes per block for a level with m unknowns per
-// direction (MG_SWEEP3_KZ overrides).  Levels below 255 are too small to
-// fill the chip with long z-marches, so their blocks march fewer planes
-// (more workgroups, less time per block); measured on MI355X, 1 plane at
-// 31, 2 at 63 and 4 at 127 took 3-4% off the 256^3 solves, while the
-// 191-wide variable-coefficient level keeps 8.
-inline int sweep3_kz(int m) {
+// direction and elements of elem bytes (MG_SWEEP3_KZ overrides).  Long
+// z-marches re-read fewer halo planes; short ones give the small levels
+// enough workgroups to fill the chip.  Measured on MI355X: FP64 levels take
+// 32 planes from 255 up (16 cost 2-3% on the 256^3 and 512^3 solves, 24
+// leaves an unbalanced last chunk) and 24 at 191; FP32 levels 32 from 511,
+// 16 at 255 and 12 at 191; every kind 4, 2 and 1 at 127, 63 and 31.
+inline int sweep3_kz(int m, int elem) {
   static const int forced = [] {
     const char* e = getenv("MG_SWEEP3_KZ");
     return e ? atoi(e) : 0;
   }();
   if (forced > 0) return forced;
-  return m >= 255 ? 16 : (m >= 191 ? 8 : (m >= 127 ? 4 : (m >= 63 ? 2 : 1)));
+  if (m >= 255) return elem == 8 || m >= 511 ? 32 : 16;
+  if (m >= 191) return elem == 8 ? 24 : 12;
+  return m >= 127 ? 4 : (m >= 63 ? 2 : 1);
 }
 
 // PRO (smoothing modes): the coarse correction e of the next coarser level
@@ -1842,9 +1845,9 @@ namespace {
 // 3D levels with at least 31 unknowns per direction use k_sweep3.
 inline bool use_sweep3(const Geo& g) { return g.dim == 3 && g.n >= 32; }
 
-inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc) {
+inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc, int elem) {
   const int m = g.n - 1;
-  *kz = sweep3_kz(m);
+  *kz = sweep3_kz(m, elem);
   *nzc = (int)cdiv(m, *kz);
   return dim3(cdiv(m, SW_TX), cdiv(m, SW_TY), (unsigned)(*nzc * count));
 }
@@ -1862,7 +1865,7 @@ template <typename T, int K, int MODE, bool ZERO, bool NORM, int XL = 0>
 void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batch& B,
                    hipStream_t s) {
   int kz, nzc;
-  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
   hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM, false, XL>), gr, dim3(64, SW_TY), 0, s, g,
                      op, omega, kz, nzc, sweep3_remap(), B);
 }
@@ -1875,8 +1878,9 @@ long norm2_blocks(const Geo& g) {
 
 long grid_blocks(const Geo& g) {
   if (use_sweep3(g)) {
+    // (the launches that write partial sums are FP64)
     int kz, nzc;
-    const dim3 gr = sweep3_grid(g, 1, &kz, &nzc);
+    const dim3 gr = sweep3_grid(g, 1, &kz, &nzc, (int)sizeof(double));
     return (long)gr.x * gr.y * gr.z;
   }
   dim3 gr = node_grid(g, 1);
@@ -2036,7 +2040,7 @@ template <typename T>
 void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T omega,
                            const Batch& B, hipStream_t s, int xl) {
   int kz, nzc;
-  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
   const dim3 bl(64, SW_TY);
   const int rm = sweep3_remap();
   if (xl == XL_TO_SPLIT) {
@@ -2075,7 +2079,7 @@ template <typename T>
 void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, bool zero,
                         const Batch& B, hipStream_t s) {
   int kz, nzc;
-  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc);
+  const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
   const dim3 bl(64, SW_TY);
   const int rm = sweep3_remap();
 #define L_PAIR(K, CA, Z) \
