@@ -1450,6 +1450,29 @@ __device__ __forceinline__ void for_unknowns(int n, const DGeo& g, F f) {
   }
 }
 
+// A red-black pass over the unknowns of a level: thread q takes, in one
+// grid row, the h-th unknown of colour `colour` (f_upd) and the h-th of the
+// other colour (f_oth), so that every lane of a wave computes a stencil
+// (enumerating all unknowns would leave every other lane idle in it).
+template <int DIM, typename F, typename G>
+__device__ __forceinline__ void for_colour_pairs(int n, const DGeo& g, int colour, F f_upd,
+                                                 G f_oth) {
+  const int mi = n - 1;
+  const int half = (mi + 1) / 2;
+  const int rows = DIM == 3 ? mi * mi : mi;
+  const int total = rows * half;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int h = q % half, row = q / half;
+    const int j = row % mi + 1;
+    const int k = DIM == 3 ? row / mi + 1 : 0;
+    const int iu = ((1 + j + k) & 1) == colour ? 1 : 2;  // first unknown of the colour
+    const int i1 = iu + 2 * h, i2 = (3 - iu) + 2 * h;
+    const long rb = j * g.sy + (long)k * g.sz;
+    if (i1 <= mi) f_upd(i1 + rb, i1, j, k);
+    if (i2 <= mi) f_oth(i2 + rb, i2, j, k);
+  }
+}
+
 // The tail keeps every vector of its levels in the launch's dynamic LDS
 // (element offsets in TailDesc): iterate, spare, right-hand side, residual
 // and, for OP_KAPPA, the cell coefficients.  The region is zeroed first, so
@@ -1543,10 +1566,14 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
         // the step kind is a constant in each instance, as in the grid
         // kernels, so both contract the update the same way
         auto sweep = [&](auto kind) {
-          for_unknowns<DIM>(n, g, [&](long p, int i, int j, int k) {
-            xout[p] = smooth_node<T, DIM, KIND>(op, kap, g, decltype(kind)::value, xin, b, omega,
-                                                p, i, j, k);
-          });
+          constexpr int KS = decltype(kind)::value;
+          auto node = [&](long p, int i, int j, int k) {
+            xout[p] = smooth_node<T, DIM, KIND>(op, kap, g, KS, xin, b, omega, p, i, j, k);
+          };
+          if (KS == SM_JACOBI)
+            for_unknowns<DIM>(n, g, node);
+          else
+            for_colour_pairs<DIM>(n, g, KS == SM_RB1 ? 1 : 0, node, node);
         };
         if (ks == SM_JACOBI)
           sweep(std::integral_constant<int, SM_JACOBI>{});
