@@ -352,6 +352,36 @@ void scheduler(mg_server* S) {
       S->st.in_flight = (int)S->active.size();
       S->st.queued = (int)S->queue.size();
     }
+    if (ops.size() == 1) {
+      // a lone runnable request has nothing to be batched with: queue the
+      // rest of its list at once rather than one launch per step, which
+      // would leave the GPU waiting for the scheduler between its small
+      // kernels
+      Request* r = owners[0];
+      const std::vector<OpRec>& list = r->phase == 0 ? r->pro : r->it;
+      hipEvent_t& slot_ev = S->step_ev[S->step_head];
+      if (slot_ev) hipEventSynchronize(slot_ev);
+      const size_t n = list.size() - r->pc;
+      for (size_t q = r->pc; q < list.size(); ++q) {
+        const OpRec* one = &list[q];
+        launch_ops(&one, 1, S->stream);
+      }
+      if (!slot_ev) hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
+      hipEventRecord(slot_ev, S->stream);
+      S->step_head = (S->step_head + 1) % mg_server::kStepsAhead;
+      {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->st.launches += n;
+        S->st.fused_ops += n;
+        S->st.steps += 1;
+      }
+      r->pc = list.size();
+      hipMemcpyAsync(r->pin, r->slot.ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                     S->stream);
+      hipEventRecord(r->ev, S->stream);
+      r->waiting = true;
+      continue;
+    }
     // group equal launches (first-come order), at most kMaxBatch per group
     groups.clear();
     for (const OpRec* o : ops) {
