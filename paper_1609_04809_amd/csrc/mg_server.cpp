@@ -5,12 +5,16 @@
 // budget allow.  Every admitted request holds a context (its hierarchy and
 // vectors stay resident until it finishes; Poisson contexts are pooled by
 // shape) and the recorded kernel launches of its prologue and of one
-// iteration.  Each scheduler step takes the next launch of every request
-// that is not waiting for a norm read-back, groups launches with the same
-// kernel, level shape and precision, and issues each group as one batched
-// launch.  A request that finishes an iteration (or its prologue) copies its
-// norms to pinned host memory behind an event and waits for that event
-// alone; the other requests keep the GPU busy meanwhile.
+// iteration.  Requests are spread over a few streams (lanes), so that the
+// small kernels of different lanes can run side by side.  Each scheduler
+// step takes, lane by lane, the next launch of every request that is not
+// waiting for a norm read-back, groups launches with the same kernel, level
+// shape and precision, and issues each group as one batched launch on the
+// lane's stream (a lane's lone runnable request queues the rest of its
+// iteration at once).  A request that finishes an iteration (or its
+// prologue) copies its norms to pinned host memory behind an event and
+// waits for that event alone; the other requests keep the GPU busy
+// meanwhile.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -73,6 +77,7 @@ struct Request {
   double nb = 0;
   double rho = 1.0;
   bool waiting = false;
+  int lane = 0;  // the stream its launches and read-backs go to
   hipEvent_t ev = nullptr;
   double* pin = nullptr;  // 2 pinned doubles: ||r||^2, ||b||^2
 };
@@ -106,9 +111,14 @@ struct mg_server {
   size_t in_use = 0;       // bytes of active requests and pooled contexts
   std::vector<double*> pinned_free;
   double busy_since = -1;
+  // Requests are spread over kLanes streams; launches are batched within a
+  // lane, and the lanes' small kernels can run side by side on the GPU.
+  // `stream` serves admissions and result copies.
+  static constexpr int kLanes = 4;
+  hipStream_t lanes[kLanes] = {};
   static constexpr int kStepsAhead = 8;
-  hipEvent_t step_ev[kStepsAhead] = {};
-  int step_head = 0;
+  hipEvent_t step_ev[kLanes][kStepsAhead] = {};
+  int step_head[kLanes] = {};
 };
 
 namespace {
@@ -264,6 +274,12 @@ void admit(mg_server* S) {
     }
     hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
     {
+      // the lane with the fewest active requests
+      int load[mg_server::kLanes] = {};
+      for (auto& a : S->active) ++load[a->lane];
+      r->lane = (int)(std::min_element(load, load + mg_server::kLanes) - load);
+    }
+    {
       std::lock_guard<std::mutex> lk(S->mu);
       ++S->st.admitted;
     }
@@ -299,6 +315,90 @@ void after_readback(mg_server* S, std::list<std::unique_ptr<Request>>::iterator 
   }
 }
 
+// One scheduler step of one lane: the next launch of each of its runnable
+// requests, equal launches batched.
+void step_lane(mg_server* S, int lane, std::vector<const OpRec*>& ops,
+               std::vector<Request*>& owners, std::vector<std::vector<const OpRec*>>& groups) {
+  hipStream_t stream = S->lanes[lane];
+  ops.clear();
+  owners.clear();
+  for (auto& rp : S->active) {
+    Request& r = *rp;
+    if (r.waiting || r.lane != lane) continue;
+    const std::vector<OpRec>& list = r.phase == 0 ? r.pro : r.it;
+    ops.push_back(&list[r.pc]);
+    owners.push_back(&r);
+  }
+  if (ops.empty()) return;
+  if (ops.size() == 1) {
+    // a lone runnable request has nothing to be batched with: queue the
+    // rest of its list at once rather than one launch per step, which
+    // would leave the GPU waiting for the scheduler between its small
+    // kernels
+    Request* r = owners[0];
+    const std::vector<OpRec>& list = r->phase == 0 ? r->pro : r->it;
+    hipEvent_t& slot_ev = S->step_ev[lane][S->step_head[lane]];
+    if (slot_ev) hipEventSynchronize(slot_ev);
+    const size_t n = list.size() - r->pc;
+    for (size_t q = r->pc; q < list.size(); ++q) {
+      const OpRec* one = &list[q];
+      launch_ops(&one, 1, stream);
+    }
+    if (!slot_ev) hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
+    hipEventRecord(slot_ev, stream);
+    S->step_head[lane] = (S->step_head[lane] + 1) % mg_server::kStepsAhead;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->st.launches += n;
+      S->st.fused_ops += n;
+      S->st.steps += 1;
+    }
+    r->pc = list.size();
+    hipMemcpyAsync(r->pin, r->slot.ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                   stream);
+    hipEventRecord(r->ev, stream);
+    r->waiting = true;
+    return;
+  }
+  // group equal launches (first-come order), at most kMaxBatch per group
+  groups.clear();
+  for (const OpRec* o : ops) {
+    bool placed = false;
+    if (batchable(*o)) {
+      for (auto& g : groups)
+        if ((int)g.size() < kMaxBatch && same_key(*g[0], *o)) {
+          g.push_back(o);
+          placed = true;
+          break;
+        }
+    }
+    if (!placed) groups.push_back({o});
+  }
+  // at most kStepsAhead steps queued on the GPU, so that a read-back is
+  // never stuck behind a long queue
+  hipEvent_t& slot_ev = S->step_ev[lane][S->step_head[lane]];
+  if (slot_ev) hipEventSynchronize(slot_ev);
+  for (auto& g : groups) launch_ops(g.data(), (int)g.size(), stream);
+  if (!slot_ev) hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
+  hipEventRecord(slot_ev, stream);
+  S->step_head[lane] = (S->step_head[lane] + 1) % mg_server::kStepsAhead;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->st.launches += groups.size();
+    S->st.fused_ops += ops.size();
+    S->st.steps += 1;
+  }
+  // advance; requests at the end of a list read their norms back
+  for (Request* r : owners) {
+    const std::vector<OpRec>& list = r->phase == 0 ? r->pro : r->it;
+    if (++r->pc < list.size()) continue;
+    hipMemcpyAsync(r->pin, r->slot.ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                   stream);
+    hipEventRecord(r->ev, stream);
+    r->waiting = true;
+  }
+}
+
 void scheduler(mg_server* S) {
   hipSetDevice(S->device);
   std::vector<const OpRec*> ops;
@@ -312,16 +412,9 @@ void scheduler(mg_server* S) {
       if ((*itr)->waiting && hipEventQuery((*itr)->ev) == hipSuccess) after_readback(S, itr);
       itr = nxt;
     }
-    ops.clear();
-    owners.clear();
-    for (auto& rp : S->active) {
-      Request& r = *rp;
-      if (r.waiting) continue;
-      const std::vector<OpRec>& list = r.phase == 0 ? r.pro : r.it;
-      ops.push_back(&list[r.pc]);
-      owners.push_back(&r);
-    }
-    if (ops.empty()) {
+    int runnable = 0;
+    for (auto& rp : S->active) runnable += !rp->waiting;
+    if (runnable == 0) {
       bool any_waiting = false;
       for (auto& rp : S->active) any_waiting |= rp->waiting;
       if (any_waiting) {
@@ -352,75 +445,11 @@ void scheduler(mg_server* S) {
       S->st.in_flight = (int)S->active.size();
       S->st.queued = (int)S->queue.size();
     }
-    if (ops.size() == 1) {
-      // a lone runnable request has nothing to be batched with: queue the
-      // rest of its list at once rather than one launch per step, which
-      // would leave the GPU waiting for the scheduler between its small
-      // kernels
-      Request* r = owners[0];
-      const std::vector<OpRec>& list = r->phase == 0 ? r->pro : r->it;
-      hipEvent_t& slot_ev = S->step_ev[S->step_head];
-      if (slot_ev) hipEventSynchronize(slot_ev);
-      const size_t n = list.size() - r->pc;
-      for (size_t q = r->pc; q < list.size(); ++q) {
-        const OpRec* one = &list[q];
-        launch_ops(&one, 1, S->stream);
-      }
-      if (!slot_ev) hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
-      hipEventRecord(slot_ev, S->stream);
-      S->step_head = (S->step_head + 1) % mg_server::kStepsAhead;
-      {
-        std::lock_guard<std::mutex> lk(S->mu);
-        S->st.launches += n;
-        S->st.fused_ops += n;
-        S->st.steps += 1;
-      }
-      r->pc = list.size();
-      hipMemcpyAsync(r->pin, r->slot.ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                     S->stream);
-      hipEventRecord(r->ev, S->stream);
-      r->waiting = true;
-      continue;
-    }
-    // group equal launches (first-come order), at most kMaxBatch per group
-    groups.clear();
-    for (const OpRec* o : ops) {
-      bool placed = false;
-      if (batchable(*o)) {
-        for (auto& g : groups)
-          if ((int)g.size() < kMaxBatch && same_key(*g[0], *o)) {
-            g.push_back(o);
-            placed = true;
-            break;
-          }
-      }
-      if (!placed) groups.push_back({o});
-    }
-    // at most kStepsAhead steps queued on the GPU, so that a read-back is
-    // never stuck behind a long queue
-    hipEvent_t& slot_ev = S->step_ev[S->step_head];
-    if (slot_ev) hipEventSynchronize(slot_ev);
-    for (auto& g : groups) launch_ops(g.data(), (int)g.size(), S->stream);
-    if (!slot_ev) hipEventCreateWithFlags(&slot_ev, hipEventDisableTiming);
-    hipEventRecord(slot_ev, S->stream);
-    S->step_head = (S->step_head + 1) % mg_server::kStepsAhead;
-    {
-      std::lock_guard<std::mutex> lk(S->mu);
-      S->st.launches += groups.size();
-      S->st.fused_ops += ops.size();
-      S->st.steps += 1;
-    }
-    // advance; requests at the end of a list read their norms back
-    for (Request* r : owners) {
-      const std::vector<OpRec>& list = r->phase == 0 ? r->pro : r->it;
-      if (++r->pc < list.size()) continue;
-      hipMemcpyAsync(r->pin, r->slot.ctx->scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
-                     S->stream);
-      hipEventRecord(r->ev, S->stream);
-      r->waiting = true;
-    }
+    for (int lane = 0; lane < mg_server::kLanes; ++lane)
+      step_lane(S, lane, ops, owners, groups);
   }
 }
+
 
 }  // namespace
 
@@ -434,10 +463,16 @@ mg_status mg_server_create(size_t hbm_budget, int max_slots, mg_server** out) {
   mg_server* S = new mg_server();
   S->budget = hbm_budget;
   S->max_slots = max_slots;
-  if (hipGetDevice(&S->device) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+  bool ok = hipGetDevice(&S->device) == hipSuccess &&
+            hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) == hipSuccess;
+  for (int q = 0; ok && q < mg_server::kLanes; ++q)
+    ok = hipStreamCreateWithFlags(&S->lanes[q], hipStreamNonBlocking) == hipSuccess;
+  if (!ok) {
+    for (hipStream_t l : S->lanes)
+      if (l) hipStreamDestroy(l);
+    if (S->stream) hipStreamDestroy(S->stream);
     delete S;
-    return fail(MG_E_HIP, "could not create the server stream");
+    return fail(MG_E_HIP, "could not create the server streams");
   }
   S->th = std::thread(scheduler, S);
   *out = S;
@@ -522,8 +557,11 @@ void mg_server_destroy(mg_server* S) {
   if (S->th.joinable()) S->th.join();
   for (auto& p : S->pool) free_slot(p);
   for (double* p : S->pinned_free) hipHostFree(p);
-  for (hipEvent_t e : S->step_ev)
-    if (e) hipEventDestroy(e);
+  for (auto& lane : S->step_ev)
+    for (hipEvent_t e : lane)
+      if (e) hipEventDestroy(e);
+  for (hipStream_t l : S->lanes)
+    if (l) hipStreamDestroy(l);
   if (S->stream) hipStreamDestroy(S->stream);
   delete S;
 }
