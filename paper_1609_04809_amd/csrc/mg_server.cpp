@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -55,6 +56,7 @@ struct Slot {  // a context plus device b and u of its finest level
   mg_ctx* ctx = nullptr;
   double* b = nullptr;
   double* u = nullptr;
+  double* host = nullptr;  // pinned staging of b in and u out
   size_t bytes = 0;
   mg_options o{};
   bool poisson = true;
@@ -80,6 +82,18 @@ struct Request {
   int lane = 0;  // the stream its launches and read-backs go to
   hipEvent_t ev = nullptr;
   double* pin = nullptr;  // 2 pinned doubles: ||r||^2, ||b||^2
+  // b: host copy to the pinned staging (copy thread), then one DMA; u: DMA
+  // to the staging, then host copy to u_host (copy thread)
+  enum { STAGE_IN, RUN, COPY_OUT, HOST_OUT } stage = STAGE_IN;
+  std::atomic<bool> host_done{false};
+  int final_status = 0;
+};
+
+struct CopyJob {
+  void* dst;
+  const void* src;
+  size_t bytes;
+  std::atomic<bool>* done;
 };
 
 struct Done {
@@ -119,6 +133,14 @@ struct mg_server {
   static constexpr int kStepsAhead = 8;
   hipEvent_t step_ev[kLanes][kStepsAhead] = {};
   int step_head[kLanes] = {};
+  // host copies between pageable request memory and the pinned staging run
+  // on their own threads, so the scheduler keeps launching meanwhile
+  static constexpr int kCopyThreads = 2;
+  std::thread copiers[kCopyThreads];
+  std::mutex copy_mu;
+  std::condition_variable copy_cv;
+  std::deque<CopyJob> copy_jobs;
+  bool copy_stop = false;
 };
 
 namespace {
@@ -138,7 +160,33 @@ void free_slot(Slot& s) {
   if (s.ctx) mg_destroy(s.ctx);
   if (s.b) hipFree(s.b);
   if (s.u) hipFree(s.u);
+  if (s.host) hipHostFree(s.host);
   s = Slot{};
+}
+
+void copier(mg_server* S) {
+  for (;;) {
+    CopyJob j;
+    {
+      std::unique_lock<std::mutex> lk(S->copy_mu);
+      S->copy_cv.wait(lk, [&] { return S->copy_stop || !S->copy_jobs.empty(); });
+      if (S->copy_jobs.empty()) return;  // stopping
+      j = S->copy_jobs.front();
+      S->copy_jobs.pop_front();
+    }
+    std::memcpy(j.dst, j.src, j.bytes);
+    j.done->store(true, std::memory_order_release);
+    S->cv.notify_all();  // wake the scheduler
+  }
+}
+
+void post_copy(mg_server* S, void* dst, const void* src, size_t bytes, std::atomic<bool>* done) {
+  done->store(false, std::memory_order_relaxed);
+  {
+    std::lock_guard<std::mutex> lk(S->copy_mu);
+    S->copy_jobs.push_back(CopyJob{dst, src, bytes, done});
+  }
+  S->copy_cv.notify_one();
 }
 
 // Get a context for r: a pooled one of the same shape or a new one.
@@ -158,7 +206,8 @@ mg_status acquire_slot(mg_server* S, Request& r) {
   s.bytes = r.bytes;
   const size_t nodes = (size_t)ipow_l(r.o.n + 1L, r.o.dim);
   if (hipMalloc(&s.b, nodes * sizeof(double)) != hipSuccess ||
-      hipMalloc(&s.u, nodes * sizeof(double)) != hipSuccess) {
+      hipMalloc(&s.u, nodes * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&s.host, nodes * sizeof(double), hipHostMallocDefault) != hipSuccess) {
     (void)hipGetLastError();
     free_slot(s);
     return fail(MG_E_NOMEM, "device allocation for a request failed");
@@ -204,14 +253,8 @@ bool make_room(mg_server* S, size_t need) {
   return S->in_use + need <= S->budget;
 }
 
+// Report r done (its u, if any, is already in u_host) and free what it holds.
 void finish(mg_server* S, Request& r, int status) {
-  const size_t nodes = (size_t)ipow_l(r.o.n + 1L, r.o.dim);
-  if (r.slot.u && r.u_host) {
-    if (hipMemcpyAsync(r.u_host, r.slot.u, nodes * sizeof(double), hipMemcpyDeviceToHost,
-                       S->stream) != hipSuccess ||
-        hipStreamSynchronize(S->stream) != hipSuccess)
-      status = MG_E_HIP;
-  }
   const double t = now_s();
   if (r.ev) hipEventDestroy(r.ev);
   r.ev = nullptr;
@@ -252,15 +295,6 @@ void admit(mg_server* S) {
       finish(S, *r, st);
       continue;
     }
-    const size_t nodes = (size_t)ipow_l(r->o.n + 1L, r->o.dim);
-    if (hipMemcpyAsync(r->slot.b, r->b.data(), nodes * sizeof(double), hipMemcpyHostToDevice,
-                       S->stream) != hipSuccess) {
-      finish(S, *r, MG_E_HIP);
-      continue;
-    }
-    // the host copy must stay valid until the transfer completes
-    hipStreamSynchronize(S->stream);
-    std::vector<double>().swap(r->b);
     std::vector<double>().swap(r->kappa);
     record_prologue(r->slot.ctx, r->slot.u, r->slot.b, r->pro);
     record_iteration(r->slot.ctx, r->slot.u, r->slot.b, r->it);
@@ -279,6 +313,10 @@ void admit(mg_server* S) {
       for (auto& a : S->active) ++load[a->lane];
       r->lane = (int)(std::min_element(load, load + mg_server::kLanes) - load);
     }
+    // b goes to the slot's pinned staging on a copy thread, then by DMA
+    r->stage = Request::STAGE_IN;
+    const size_t nodes = (size_t)ipow_l(r->o.n + 1L, r->o.dim);
+    post_copy(S, r->slot.host, r->b.data(), nodes * sizeof(double), &r->host_done);
     {
       std::lock_guard<std::mutex> lk(S->mu);
       ++S->st.admitted;
@@ -310,8 +348,42 @@ void after_readback(mg_server* S, std::list<std::unique_ptr<Request>>::iterator 
     else if (r.k >= r.o.max_iter) st = MG_E_MAXIT;
   }
   if (st >= 0) {
-    finish(S, r, st);
-    S->active.erase(itr);
+    // u to the pinned staging by DMA, then to u_host on a copy thread
+    r.final_status = st;
+    const size_t nodes = (size_t)ipow_l(r.o.n + 1L, r.o.dim);
+    if (r.slot.u && r.u_host) {
+      hipStream_t ls = S->lanes[r.lane];
+      hipMemcpyAsync(r.slot.host, r.slot.u, nodes * sizeof(double), hipMemcpyDeviceToHost, ls);
+      hipEventRecord(r.ev, ls);
+      r.stage = Request::COPY_OUT;
+    } else {
+      finish(S, r, st);
+      S->active.erase(itr);
+    }
+  }
+}
+
+// Advance the requests whose copies have landed: staged b goes to the
+// device, u staged from the device goes to u_host, a request whose u is in
+// u_host is done.
+void progress_copies(mg_server* S) {
+  for (auto itr = S->active.begin(); itr != S->active.end();) {
+    auto nxt = std::next(itr);
+    Request& r = **itr;
+    const size_t bytes = (size_t)ipow_l(r.o.n + 1L, r.o.dim) * sizeof(double);
+    if (r.stage == Request::STAGE_IN && r.host_done.load(std::memory_order_acquire)) {
+      // (the request's launches follow on the same stream)
+      hipMemcpyAsync(r.slot.b, r.slot.host, bytes, hipMemcpyHostToDevice, S->lanes[r.lane]);
+      std::vector<double>().swap(r.b);
+      r.stage = Request::RUN;
+    } else if (r.stage == Request::COPY_OUT && hipEventQuery(r.ev) == hipSuccess) {
+      r.stage = Request::HOST_OUT;
+      post_copy(S, r.u_host, r.slot.host, bytes, &r.host_done);
+    } else if (r.stage == Request::HOST_OUT && r.host_done.load(std::memory_order_acquire)) {
+      finish(S, r, r.final_status);
+      S->active.erase(itr);
+    }
+    itr = nxt;
   }
 }
 
@@ -324,7 +396,7 @@ void step_lane(mg_server* S, int lane, std::vector<const OpRec*>& ops,
   owners.clear();
   for (auto& rp : S->active) {
     Request& r = *rp;
-    if (r.waiting || r.lane != lane) continue;
+    if (r.stage != Request::RUN || r.waiting || r.lane != lane) continue;
     const std::vector<OpRec>& list = r.phase == 0 ? r.pro : r.it;
     ops.push_back(&list[r.pc]);
     owners.push_back(&r);
@@ -409,21 +481,32 @@ void scheduler(mg_server* S) {
     // read-backs that have landed
     for (auto itr = S->active.begin(); itr != S->active.end();) {
       auto nxt = std::next(itr);
-      if ((*itr)->waiting && hipEventQuery((*itr)->ev) == hipSuccess) after_readback(S, itr);
+      if ((*itr)->stage == Request::RUN && (*itr)->waiting &&
+          hipEventQuery((*itr)->ev) == hipSuccess)
+        after_readback(S, itr);
       itr = nxt;
     }
+    progress_copies(S);
     int runnable = 0;
-    for (auto& rp : S->active) runnable += !rp->waiting;
+    bool host_wait = false;
+    Request* gpu_wait = nullptr;
+    for (auto& rp : S->active) {
+      Request& r = *rp;
+      runnable += r.stage == Request::RUN && !r.waiting;
+      host_wait |= r.stage == Request::STAGE_IN || r.stage == Request::HOST_OUT;
+      if (!gpu_wait && ((r.stage == Request::RUN && r.waiting) || r.stage == Request::COPY_OUT))
+        gpu_wait = &r;
+    }
     if (runnable == 0) {
-      bool any_waiting = false;
-      for (auto& rp : S->active) any_waiting |= rp->waiting;
-      if (any_waiting) {
-        // nothing to launch: block on the oldest outstanding read-back
-        for (auto& rp : S->active)
-          if (rp->waiting) {
-            hipEventSynchronize(rp->ev);
-            break;
-          }
+      if (host_wait) {
+        // nothing to launch: a copy thread will wake us (or the timeout)
+        std::unique_lock<std::mutex> lk(S->mu);
+        S->cv.wait_for(lk, std::chrono::microseconds(200));
+        continue;
+      }
+      if (gpu_wait) {
+        // nothing to launch: block on the oldest outstanding read-back or copy
+        hipEventSynchronize(gpu_wait->ev);
         continue;
       }
       std::unique_lock<std::mutex> lk(S->mu);
@@ -474,6 +557,7 @@ mg_status mg_server_create(size_t hbm_budget, int max_slots, mg_server** out) {
     delete S;
     return fail(MG_E_HIP, "could not create the server streams");
   }
+  for (auto& t : S->copiers) t = std::thread(copier, S);
   S->th = std::thread(scheduler, S);
   *out = S;
   return MG_OK;
@@ -555,6 +639,13 @@ void mg_server_destroy(mg_server* S) {
   }
   S->cv.notify_all();
   if (S->th.joinable()) S->th.join();
+  {
+    std::lock_guard<std::mutex> lk(S->copy_mu);
+    S->copy_stop = true;
+  }
+  S->copy_cv.notify_all();
+  for (auto& t : S->copiers)
+    if (t.joinable()) t.join();
   for (auto& p : S->pool) free_slot(p);
   for (double* p : S->pinned_free) hipHostFree(p);
   for (auto& lane : S->step_ev)

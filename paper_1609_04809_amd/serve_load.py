@@ -2,7 +2,9 @@
 mg_server_* and reports latency percentiles and throughput.
 
 Each request's right-hand side is generated (seeded, U[-1, 1]) on a
-background thread ahead of its arrival time; submission follows the trace's
+background thread ahead of its arrival time -- for a trace whose requests
+all arrive at once, all of them before the clock starts, so that the
+generator does not pace the submissions; submission follows the trace's
 arrival times on the wall clock; results are collected as they finish.
 Latency is measured by the server from submission to the result being in
 host memory.
@@ -30,10 +32,13 @@ def run_trace(trace, hbm_budget_bytes, max_slots=64, tol=1e-8, precision="fp32_i
               smoother="rbgs", log=None):
     """Replay `trace` (see workloads.serving_trace).  Returns a summary dict."""
     from .mg import Server
-    q = queue.Queue(maxsize=64)
+    burst = all(r["t_arrival"] == 0.0 for r in trace)
+    q = queue.Queue(maxsize=0 if burst else 64)
     stop = threading.Event()
     th = threading.Thread(target=_producer, args=(trace, q, stop), daemon=True)
     th.start()
+    if burst:
+        th.join()  # every right-hand side ready before the clock starts
     results = []
     dofs = {}
     failed = []
