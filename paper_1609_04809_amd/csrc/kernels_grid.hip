@@ -1308,6 +1308,67 @@ __global__ __launch_bounds__(256) void k_prolong_add(Geo gf, Geo gc, Batch B) {
   x[p] += prolong_node<T, DIM>(dgeo(gc), (const T*)I.a, i, j, k);
 }
 
+// 3D prolongation + add marching in z: a block of 64 x 4 threads owns a
+// 64 x 4 tile of fine (i, j) columns over PZ (even) consecutive fine planes
+// starting at an odd plane 2K+1.  Those read the coarse planes K .. K + PZ/2
+// only, and within a plane the 33 x 3 coarse nodes under the tile: the
+// block stages them in LDS with one coalesced pass (about 0.4 coarse loads
+// per thread and coarse plane instead of up to 4 gathers), then every
+// thread forms the in-plane interpolant of each coarse plane once (plane(K)
+// in prolong_node serves fine planes 2K-1, 2K and 2K+1).  The values
+// combined are those of prolong_node, in its order, so the result is
+// bitwise that of k_prolong_add.
+template <typename T, int PZ>
+__global__ __launch_bounds__(256) void k_prolong_add_z(Geo gf, Geo gc, Batch B, int chunks) {
+  static_assert(PZ % 2 == 0 && BX == 64 && BY == 4, "tile of 64 x 4 columns, odd first plane");
+  constexpr int NC = PZ / 2 + 1, CX = BX / 2 + 1, CY = BY / 2 + 1;
+  __shared__ T sc[NC][CY][CX];
+  const int m = gf.n - 1, nc = gc.n;
+  const int item = (int)blockIdx.z / chunks;
+  const int kb = 1 + ((int)blockIdx.z % chunks) * PZ;
+  const int nk = min(PZ, m - kb + 1);  // fine planes kb .. kb + nk - 1
+  const int cl = (kb + nk) >> 1;       // last coarse plane they read (<= nc)
+  const int ci = BX / 2 * blockIdx.x, cj = BY / 2 * blockIdx.y, ck = kb >> 1;
+  const int i = 1 + blockIdx.x * BX + threadIdx.x;
+  const int j = 1 + blockIdx.y * BY + threadIdx.y;
+  const bool inside = i <= m && j <= m;
+  const Item& I = B.it[item];
+  const T* __restrict__ e = (const T*)I.a;
+  T* __restrict__ x = (T*)I.c;
+  const long fz = gf.sz;
+  const long p = i + j * gf.sy + (long)kb * fz;
+  T xv[PZ];
+#pragma unroll
+  for (int q = 0; q < PZ; ++q) xv[q] = inside && q < nk ? x[p + q * fz] : T(0);
+  const int tid = threadIdx.x + BX * threadIdx.y;
+  for (int t = tid; t < NC * CY * CX; t += BX * BY) {
+    const int c = t / (CY * CX), r = (t / CX) % CY, a = t % CX;
+    const int gi = ci + a, gj = cj + r, gk = ck + c;
+    T v = T(0);
+    if (gi <= nc && gj <= nc && gk <= cl) v = e[gi + gj * gc.sy + (long)gk * gc.sz];
+    (&sc[0][0][0])[t] = v;
+  }
+  __syncthreads();
+  if (!inside) return;
+  const int a0 = (i >> 1) - ci, a1 = ((i + 1) >> 1) - ci;
+  const int r0 = (j >> 1) - cj, r1 = ((j + 1) >> 1) - cj;
+  const T wi = (i & 1) ? T(0.5) : T(1);
+  const T wj = (j & 1) ? T(0.5) : T(1);
+  auto line = [&](int rr, int c) -> T {
+    return (i & 1) ? wi * (sc[c][rr][a0] + sc[c][rr][a1]) : sc[c][rr][a0];
+  };
+  T pl[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) pl[c] = (j & 1) ? wj * (line(r0, c) + line(r1, c)) : line(r0, c);
+#pragma unroll
+  for (int q = 0; q < PZ; ++q) {
+    // fine plane kb + q: odd for even q (parents ck + q/2 and the next),
+    // even for odd q (parent ck + (q + 1)/2)
+    const T v = (q & 1) ? pl[(q + 1) / 2] : T(0.5) * (pl[q / 2] + pl[q / 2 + 1]);
+    if (q < nk) x[p + q * fz] = xv[q] + v;
+  }
+}
+
 template <typename T, int DIM>
 __global__ __launch_bounds__(256) void k_norm2_partial(Geo g, Batch B) {
   NODE_INDEX(DIM, g)
@@ -2232,8 +2293,34 @@ void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s
     hipLaunchKernelGGL((k_restrict<T, 3>), gr, bl, 0, s, gf, gc, B);
 }
 
+// Fine planes per thread of the z-marching 3D prolongation: 1 (one thread
+// per node), 2, 4 or 8.  MG_PROLONG_PZ overrides it for launch-shape sweeps.
+int prolong_pz(const Geo& gf) {
+  static const int env = [] {
+    const char* v = std::getenv("MG_PROLONG_PZ");
+    const int z = v ? std::atoi(v) : 0;
+    return z == 1 || z == 2 || z == 4 || z == 8 ? z : 0;
+  }();
+  if (gf.dim != 3) return 1;
+  if (env > 0) return env;
+  const int m = gf.n - 1;
+  return m >= 191 ? 8 : m >= 95 ? 4 : m >= 47 ? 2 : 1;
+}
+
 template <typename T>
 void launch_prolong_add(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s) {
+  const int pz = prolong_pz(gf);
+  if (pz > 1) {
+    const long m = gf.n - 1, chunks = cdiv(m, pz);
+    const dim3 gr(cdiv(m, BX), cdiv(m, BY), (unsigned)(chunks * B.count)), bl(BX, BY);
+    if (pz == 2)
+      hipLaunchKernelGGL((k_prolong_add_z<T, 2>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+    else if (pz == 4)
+      hipLaunchKernelGGL((k_prolong_add_z<T, 4>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+    else
+      hipLaunchKernelGGL((k_prolong_add_z<T, 8>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+    return;
+  }
   const dim3 gr = node_grid(gf, B.count), bl(BX, BY);
   if (gf.dim == 2)
     hipLaunchKernelGGL((k_prolong_add<T, 2>), gr, bl, 0, s, gf, gc, B);
