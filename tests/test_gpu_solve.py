@@ -181,6 +181,27 @@ def test_fused_stopping_residual_agrees_bitwise(dim, n, levels, op, smoother, ka
     assert abs(outs[0][0] - ko) <= 1
 
 
+@pytest.mark.parametrize("n,levels", [(128, 7), (192, 7)])
+def test_prolongation_chunks_agree_bitwise(n, levels):
+    """The z-marching prolongation (2, 4 and 8 fine planes per block on the
+    levels with 47, 95 and 191 or more unknowns per direction) gives
+    bitwise the iterate and residual history of the prolongation fused
+    into the first post-smoothing half-sweep, whose interpolation is the
+    per-node form."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    b = W.rhs_uniform(3, n, 21)
+    bd = dev_full(3, n, b)
+    outs = []
+    for flags in (0, FLAG_NO_FUSE):
+        with Solver(3, n, levels, op="stencil", smoother="rbgs", flags=flags) as S:
+            u, k, hist, st = S.solve(bd, 1e-8)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
 def test_repeated_solves_with_new_buffers_recapture():
     torch = torch_cuda()
     from paper_1609_04809_amd.mg import Solver
