@@ -25,7 +25,10 @@ What it computes, and where the paper defines it:
   Crank-Nicolson time loop of the heat-equation model problem (Sec. 6.2;
   module ``oracle.heat``);
 * independent exact references (dense Cholesky, DST-I diagonalisation,
-  sparse LU) used only to pin the rest.
+  sparse LU) used only to pin the rest;
+* the same cycle and outer iterations matrix-free on full-grid arrays
+  (module ``oracle.matfree``: A applied cell by cell, never assembled), for
+  the 256^3 and 192^3 systems whose assembled matrices do not fit.
 
 Everything is plain NumPy/SciPy in float64 (float32 only inside the
 iterative-refinement inner cycle, by definition of that mode).

@@ -339,10 +339,15 @@ def _cycle_matrix(H, l):
     return Spost @ (I - P @ B @ P.T @ A) @ Spre
 
 
+@pytest.mark.parametrize("kap", [False, True])
 @pytest.mark.parametrize("dim,n,levels", [(2, 8, 2), (2, 16, 3), (3, 8, 3), (2, 16, 2)])
 @pytest.mark.parametrize("smoother", ["jacobi", "rbgs", "gs"])
-def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, rng):
-    H = O.build_hierarchy(dim, n, levels, smoother=smoother)
+def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, kap, rng):
+    """With kappa = 1 and with a lognormal per-cell kappa (rediscretised,
+    geometric-mean coarse coefficients): the operators the dense matrix is
+    built from are the hierarchy's own, each pinned separately."""
+    kappa = W.kappa_lognormal(dim, n, 11) if kap else None
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother)
     N = (n - 1) ** dim
     x = rng.uniform(-1, 1, N)
     b = rng.uniform(-1, 1, N)
@@ -350,6 +355,29 @@ def test_vcycle_equals_dense_cycle_operator(dim, n, levels, smoother, rng):
     ustar = np.linalg.solve(H.A[0].toarray(), b)
     want = E @ x + (np.eye(N) - E) @ ustar
     np.testing.assert_allclose(O.vcycle(H, 0, x, b), want, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,n,levels,kap", [(2, 16, 3, False), (3, 8, 3, True)])
+@pytest.mark.parametrize("smoother", ["jacobi", "rbgs"])
+def test_fp32_cycle_equals_dense_cycle_operator_of_rounded_matrices(dim, n, levels, kap,
+                                                                    smoother, rng):
+    """The float32 inner cycle is the cycle of the float32-rounded operators:
+    its result equals E x + (I - E) A32^-1 b with E built densely (in FP64)
+    from the rounded matrices, up to float32 rounding of the arithmetic."""
+    kappa = W.kappa_lognormal(dim, n, 13) if kap else None
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother, fp32=True)
+    R = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother)
+    R.A = [A.astype(np.float32).astype(np.float64) for A in H.A]
+    R.P = [P.astype(np.float32).astype(np.float64) for P in H.P]
+    N = (n - 1) ** dim
+    x = rng.uniform(-1, 1, N).astype(np.float32)
+    b = rng.uniform(-1, 1, N).astype(np.float32)
+    E = _cycle_matrix(R, 0)
+    ustar = np.linalg.solve(R.A[0].toarray(), b.astype(np.float64))
+    want = E @ x + (np.eye(N) - E) @ ustar
+    got = O.vcycle(H, 0, x, b, fp32=True)
+    assert got.dtype == np.float32
+    assert np.abs(got - want).max() <= 1e-5 * np.abs(want).max()
 
 
 def test_multicolour_gs_is_exact_gauss_seidel_and_keeps_the_solution(rng):
@@ -562,10 +590,14 @@ def _cycle_matrix_kind(H, l, kind):
 
 
 @pytest.mark.parametrize("kind", ["V", "W", "F"])
-@pytest.mark.parametrize("dim,n,levels,smoother", [(2, 16, 3, "rbgs"), (2, 32, 4, "jacobi"),
-                                                   (3, 16, 4, "rbgs")])
-def test_cycle_kinds_equal_dense_cycle_operators(kind, dim, n, levels, smoother, rng):
-    H = O.build_hierarchy(dim, n, levels, smoother=smoother, cycle=kind)
+@pytest.mark.parametrize("dim,n,levels,smoother,kap", [(2, 16, 3, "rbgs", False),
+                                                       (2, 32, 4, "jacobi", False),
+                                                       (3, 16, 4, "rbgs", False),
+                                                       (3, 8, 3, "rbgs", True),
+                                                       (2, 16, 3, "jacobi", True)])
+def test_cycle_kinds_equal_dense_cycle_operators(kind, dim, n, levels, smoother, kap, rng):
+    kappa = W.kappa_lognormal(dim, n, 12) if kap else None
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother, cycle=kind)
     N = (n - 1) ** dim
     x = rng.uniform(-1, 1, N)
     b = rng.uniform(-1, 1, N)
