@@ -4,12 +4,13 @@ MI355X, with the dominant kernel's HBM roofline fraction and the CPU oracle
 timed beside it.
 
 A step is one complete solve (V(2,2) cycles from u = 0 until the relative
-residual is <= 1e-8) of the 3D Poisson problem on 128^3 Q1 hexahedra with the
-27-point CSR operator, red-black smoothing, FP64, 7 levels, right-hand side
+residual is <= 1e-8) of the 3D Poisson problem on 256^3 Q1 hexahedra
+(16,974,593 nodes, the largest single-GPU configuration) with the matrix-free
+27-point stencil, red-black smoothing, FP64, 8 levels, right-hand side
 U[-1, 1] from seed 0 -- inputs resident in device memory before timing.
 The same JSON line also carries the other workloads (2D 64^2 Jacobi,
-3D 256^3 stencil FP64 and FP32-IR, 3D 192^3 variable kappa FP32-IR) as
-"extra" entries, each timed the same way.
+3D 128^3 CSR FP64, 3D 256^3 FP32-inner refinement, 3D 192^3 variable kappa
+FP64 and FP32-inner) as "extra" entries, each timed the same way.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
 Prints one JSON line on stdout; progress goes to stderr.
@@ -241,7 +242,20 @@ def run_workload(name, steps, warmup, with_roofline=False, pcg=False, cycle="V",
                                "k_sweep3 (red-black half-sweep, finest level)"),
                     "achieved": hs["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": hs["frac"], "traffic": measured_traffic(w.name),
-                    "avg_us": hs["avg_us"], "bytes_per_launch": hs["bytes_per_launch"]}
+                    "avg_us": hs["avg_us"], "launches": hs["launches"],
+                    "bytes_per_launch": hs["bytes_per_launch"],
+                    "bytes_per_launch_basis": "x of every unknown, b and the new x of "
+                                              "the colour's unknowns: 2 s N_I"
+                                              + (" + s n^3 (kappa)" if w.kappa != "none"
+                                                 else ""),
+                    "model_bytes_3s_per_sweep": int(
+                        1.5 * (8 if w.precision == "fp64" else 4) * w.unknowns
+                        + ((8 if w.precision == "fp64" else 4) * w.n ** 3
+                           if w.kappa != "none" else 0)),
+                    "frac_of_model_bytes": None}
+            m = roof["model_bytes_3s_per_sweep"]
+            roof["frac_of_model_bytes"] = round(m / (hs["avg_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                                4)
     S.close()
     if w.precision == "fp32_ir":
         # error of the FP32-inner / FP64-outer result against the FP64 V-cycle
@@ -316,39 +330,77 @@ def run_heat(name, steps=None, precision=None, extrapolate=False):
             "max_nodal_error_vs_exact": err, "setup_s": round(setup_s, 3), **prof}
 
 
-def cpu_baseline(name):
-    """The oracle (test infrastructure) on the same workload: one full solve,
-    assembly excluded from the timed region."""
-    import oracle as O
-    from paper_1609_04809_amd import workloads as W
-    try:
-        from threadpoolctl import threadpool_info
-        blas_threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
-    except Exception:
-        blas_threads = None
-    w = W.WORKLOADS[name]
-    b, kappa = W.workload_inputs(w)
-    t0 = time.perf_counter()
-    H = O.build_hierarchy(w.dim, w.n, w.levels, kappa=kappa, smoother=w.smoother,
-                          nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega)
-    t_build = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    u, k, hist, st = O.solve(H, b, w.tol)
-    t_solve = time.perf_counter() - t0
-    cpu_model = ""
+def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
             if line.startswith("model name"):
-                cpu_model = line.split(":", 1)[1].strip()
-                break
+                return line.split(":", 1)[1].strip()
     except OSError:
         pass
+    return ""
+
+
+def cpu_baseline(name, gpu_cycles):
+    """The oracle (test infrastructure) on the same workload, on one host
+    thread.  Assembled (CSR) workloads: one full solve.  Matrix-free
+    workloads (256^3, 192^3): one cycle of the matrix-free oracle plus its
+    stopping residual, timed and scaled by the GPU's cycle count (a full
+    solve takes minutes).  Setup excluded from the timed region.  Returns
+    (record, u_oracle_full_or_None, cycles_timed)."""
+    import oracle as O
+    from oracle import matfree as MF
+    from paper_1609_04809_amd import workloads as W
+    from threadpoolctl import threadpool_limits
+    w = W.WORKLOADS[name]
+    b, kappa = W.workload_inputs(w)
+    with threadpool_limits(limits=1):
+        if w.op == "csr":
+            t0 = time.perf_counter()
+            H = O.build_hierarchy(w.dim, w.n, w.levels, kappa=kappa, smoother=w.smoother,
+                                  nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega)
+            t_build = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            u, k, hist, st = O.solve(H, b, w.tol)
+            t_solve = time.perf_counter() - t0
+            sample = (f"one full solve of {name} ({k} cycles, SciPy CSR matvec, one thread); "
+                      f"assembly {t_build:.1f} s excluded")
+            u_full, timed = W.interior_to_full(w.dim, w.n, u), k
+        else:
+            fp32 = w.precision == "fp32_ir"
+            t0 = time.perf_counter()
+            H = MF.build(w.dim, w.n, w.levels, kappa=kappa, smoother=w.smoother,
+                         nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, fp32=fp32)
+            t_build = time.perf_counter() - t0
+            bf = W.interior_to_full(w.dim, w.n, b).reshape((w.n + 1,) * w.dim)
+            t0 = time.perf_counter()
+            _, u1, rho1 = next(MF.iterate(H, bf, fp32=fp32, max_iter=1))
+            t_cycle = time.perf_counter() - t0
+            t_solve = t_cycle * gpu_cycles
+            k = gpu_cycles
+            sample = (f"one cycle of {name} with its stopping residual (matrix-free NumPy "
+                      f"oracle, one thread, {t_cycle:.1f} s) scaled by the {gpu_cycles} "
+                      f"cycles of the solve; setup {t_build:.1f} s excluded")
+            u_full, timed = u1.ravel(), 1
     return {"value": round(w.dofs / t_solve / 1e6, 3), "unit": "MDOF/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"one full solve of {name} ({k} cycles, SciPy CSR matvec, "
-                      f"single-threaded); assembly {t_build:.1f} s excluded",
-            "solve_s": round(t_solve, 2), "cycles": k, "os_cpu_count": os.cpu_count(),
-            "blas_threads_available": blas_threads, "cpu_model": cpu_model}, u, k
+            "kind": "oracle", "sample": sample, "solve_s": round(t_solve, 2), "cycles": k,
+            "os_cpu_count": os.cpu_count(), "threads_used": 1,
+            "cpu_model": _cpu_model()}, u_full, timed
+
+
+def gpu_after_cycles(name, cycles):
+    """The GPU iterate after exactly `cycles` cycles (device full-grid tensor)."""
+    import torch
+    from paper_1609_04809_amd import workloads as W
+    from paper_1609_04809_amd.mg import Solver
+    w = W.WORKLOADS[name]
+    b, kappa, bd = _device_rhs(w)
+    with Solver(w.dim, w.n, w.levels, kappa=kappa, op=w.op, smoother=w.smoother,
+                nu_pre=w.nu_pre, nu_post=w.nu_post, omega=w.omega, precision=w.precision,
+                max_iter=cycles) as S:
+        u, k, _, st = S.solve(bd, 1e-300)
+        torch.cuda.synchronize()
+    assert k == cycles, (k, st)
+    return u
 
 
 def main():
@@ -360,7 +412,7 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline workload")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving runs")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--workload", default="poisson3d_128_csr_rbgs")
+    ap.add_argument("--workload", default="poisson3d_256_rbgs_fp64")
     ap.add_argument("--heat-steps", type=int, default=0,
                     help="Crank-Nicolson steps of the heat workload (0: all 500)")
     ap.add_argument("--no-heat", action="store_true", help="skip the heat-equation time loop")
@@ -459,10 +511,11 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")
-        cpu, u_or, k_or = cpu_baseline(name)
-        ug = W.full_to_interior(w.dim, w.n, u.cpu().numpy())
-        if k_or == k:
-            cpu["gpu_vs_oracle_rel_err"] = float(np.linalg.norm(ug - u_or) / np.linalg.norm(u_or))
+        cpu, u_or, k_or = cpu_baseline(name, res["cycles"])
+        ug = u.cpu().numpy() if k_or == res["cycles"] else \
+            gpu_after_cycles(name, k_or).cpu().numpy()
+        cpu["gpu_vs_oracle_rel_err"] = float(np.linalg.norm(ug - u_or) / np.linalg.norm(u_or))
+        cpu["gpu_vs_oracle_after_cycles"] = k_or
         log(f"[bench] CPU oracle: {cpu}")
     out = {
         "metric": "MDOF/s solved to 1e-8 rel. residual",
@@ -481,7 +534,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": name, "dim": w.dim, "n": w.n, "levels": w.levels,
                    "dofs": w.dofs, "operator": w.op, "smoother": f"{w.smoother} V(2,2)",
-                   "precision": w.precision, "tol": w.tol, "rhs": "U[-1,1] seed 0",
+                   "precision": w.precision, "tol": w.tol,
+                   "rhs": {"uniform": f"U[-1,1] seed {w.seed}", "ones": "f = 1 (b = h^3)",
+                           "manufactured": "exact load of u = sin(pi x) sin(pi y)"}[w.rhs],
+                   "kappa": "exp(N(0,1)) per cell" if w.kappa != "none" else "1",
                    "cycles": res["cycles"]},
         "roofline": roof,
         "cpu_baseline": cpu,

@@ -1539,15 +1539,14 @@ __device__ __forceinline__ void for_colour_pairs(int n, const DGeo& g, int colou
 // and, for OP_KAPPA, the cell coefficients.  The region is zeroed first, so
 // boundary entries read 0; the first level's right-hand side and iterate
 // (unless it starts at 0) and the coefficients are copied in, the iterate
-// is copied out at the end.  Bit l of `par` tells whether level l's
-// iterate currently sits in its spare buffer.
+// is copied out at the end.
+
+// Copies the descriptor at `desc` into D, zeroes the LDS region and copies
+// the cell coefficients in.
 template <typename T, int DIM, int KIND>
-__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
-  extern __shared__ __align__(16) char tail_lds[];
-  __shared__ TailDesc<T> D;
-  const Item& I = B.it[blockIdx.x];
+__device__ void tail_load(TailDesc<T>& D, char* tail_lds, const void* desc) {
   {
-    const int* src = reinterpret_cast<const int*>(I.a);
+    const int* src = reinterpret_cast<const int*>(desc);
     int* dst = reinterpret_cast<int*>(&D);
     for (int q = threadIdx.x; q < (int)(sizeof(TailDesc<T>) / sizeof(int)); q += blockDim.x)
       dst[q] = src[q];
@@ -1560,11 +1559,8 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
   }
   __syncthreads();
   T* const sm = reinterpret_cast<T*>(tail_lds);
-  const int nl = D.nlev;
-  T* const x0g = (T*)I.c;
-  const T* const b0g = (const T*)I.b;
   if (KIND == OP_KAPPA) {
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l < D.nlev; ++l) {
       const int n = D.lv[l].n;
       const int cells = DIM == 3 ? n * n * n : n * n;
       T* dst = sm + D.lv[l].ok;
@@ -1572,17 +1568,23 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
       for (int q = threadIdx.x; q < cells; q += blockDim.x) dst[q] = src[q];
     }
   }
-  {
-    T* xd = sm + D.lv[0].ox;
-    T* bd = sm + D.lv[0].ob;
-    const bool cx = !(I.flag & 1);
-    for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n), [&](long p, int, int, int) {
-      bd[p] = b0g[p];
-      if (cx) xd[p] = x0g[p];
-    });
-  }
-  __syncthreads();
-  int par = 0;
+}
+
+// The first tail level's current iterate (bit 0 of par: in the spare).
+template <typename T>
+__device__ __forceinline__ T* tail_x0(const TailDesc<T>& D, char* tail_lds, int par) {
+  return reinterpret_cast<T*>(tail_lds) + ((par & 1) ? D.lv[0].ot : D.lv[0].ox);
+}
+
+// One cycle over the tail levels, every vector in LDS: from the first
+// level's iterate (or from 0 when bit 0 of `flag` is set) to the new one,
+// in tail_x0 afterwards.  Bits 1-2 of `flag`: the cycle kind (CycleKind).
+// Bit l of `par` tells whether level l's iterate currently sits in its
+// spare buffer.
+template <typename T, int DIM, int KIND>
+__device__ void tail_cycle(const TailDesc<T>& D, char* tail_lds, int& par, int flag) {
+  T* const sm = reinterpret_cast<T*>(tail_lds);
+  const int nl = D.nlev;
   auto X = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ot : D.lv[l].ox); };
   auto S = [&](int l) { return sm + (((par >> l) & 1) ? D.lv[l].ox : D.lv[l].ot); };
   auto params = [&](int l) {
@@ -1706,11 +1708,11 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
   if (nl == 1) {
     coarse();
   } else {
-    unsigned kinds = (unsigned)(I.flag >> 1) & 3u, starts = 0;
+    unsigned kinds = (unsigned)(flag >> 1) & 3u, starts = 0;
     auto kind_of = [&](int l) { return (int)((kinds >> (2 * l)) & 3u); };
     auto started = [&](int l) { return (int)((starts >> (2 * l)) & 3u); };
     int l = 0;
-    down(0, (I.flag & 1) != 0);
+    down(0, (flag & 1) != 0);
     for (;;) {
       const int kd = kind_of(l);
       const int nsub = kd == CYC_V ? 1 : 2;
@@ -1730,9 +1732,120 @@ __global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
       --l;
     }
   }
-  const T* src = X(0);
+}
+
+template <typename T, int DIM, int KIND>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail(Batch B) {
+  extern __shared__ __align__(16) char tail_lds[];
+  __shared__ TailDesc<T> D;
+  const Item& I = B.it[blockIdx.x];
+  tail_load<T, DIM, KIND>(D, tail_lds, I.a);
+  T* const sm = reinterpret_cast<T*>(tail_lds);
+  T* const x0g = (T*)I.c;
+  const T* const b0g = (const T*)I.b;
+  {
+    T* xd = sm + D.lv[0].ox;
+    T* bd = sm + D.lv[0].ob;
+    const bool cx = !(I.flag & 1);
+    for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n), [&](long p, int, int, int) {
+      bd[p] = b0g[p];
+      if (cx) xd[p] = x0g[p];
+    });
+  }
+  __syncthreads();
+  int par = 0;
+  tail_cycle<T, DIM, KIND>(D, tail_lds, par, I.flag);
+  const T* src = tail_x0(D, tail_lds, par);
   for_unknowns<DIM>(D.lv[0].n, dgeo(DIM, D.lv[0].n),
                     [&](long p, int, int, int) { x0g[p] = src[p]; });
+}
+
+// Sum of v over the TAIL_THREADS threads of a tail block, in a fixed order
+// (wave butterflies, then the wave sums in wave order); every thread gets
+// the sum.  ws: TAIL_THREADS / 64 doubles of shared memory.
+__device__ __forceinline__ double tail_block_sum(double v, double* ws) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < TAIL_THREADS / 64; ++w) t += ws[w];
+  __syncthreads();
+  return t;
+}
+
+// A whole FP64 solve of a hierarchy the tail holds from its finest level
+// on, in one workgroup: u_0 = 0, then cycles of the descriptor's kind until
+// ||b - A u_k||_2 / ||b||_2 <= tol (the outer iteration of Sec. 5.5.1, the
+// stopping rule of the cycle-by-cycle solve), with the iterate kept in LDS
+// between cycles.  Item: a = TailDesc<double>* (device), b = b (every node
+// of the finest level, boundary entries ignored), c = u (every node
+// written, boundary 0), scal = results: [0] status (TailSolveStatus),
+// [1] cycles done, [2 + k] the relative residual after cycle k ([2] = 1).
+// flag: the cycle kind in bits 1-2.
+
+template <int DIM, int KIND>
+__global__ __launch_bounds__(TAIL_THREADS) void k_tail_solve(Batch B, double tol, int max_iter) {
+  extern __shared__ __align__(16) char tail_lds[];
+  __shared__ TailDesc<double> D;
+  __shared__ double ws[TAIL_THREADS / 64];
+  const Item& I = B.it[blockIdx.x];
+  tail_load<double, DIM, KIND>(D, tail_lds, I.a);
+  double* const sm = reinterpret_cast<double*>(tail_lds);
+  double* const ug = (double*)I.c;
+  const double* const bg = (const double*)I.b;
+  double* const res = I.scal;
+  const int n0 = D.lv[0].n;
+  const DGeo g0 = dgeo(DIM, n0);
+  double* const bd = sm + D.lv[0].ob;
+  double sb = 0.0;
+  for_unknowns<DIM>(n0, g0, [&](long p, int, int, int) {
+    const double v = bg[p];
+    bd[p] = v;
+    sb += v * v;
+  });
+  const double nb2 = tail_block_sum(sb, ws);  // also orders the stores to bd
+  const StencilParams<double> op{KIND, D.lv[0].wc, D.lv[0].w1, D.lv[0].w2, D.lv[0].s,
+                                 D.lv[0].wf};
+  const double* kap = sm + D.lv[0].ok;
+  int status = TS_MAXIT, k = 0, par = 0;
+  if (!isfinite(nb2)) {
+    status = TS_NONFINITE_B;
+  } else if (nb2 == 0.0) {
+    status = TS_OK;  // u = 0 (the LDS iterate is zero)
+  } else {
+    const double nb = sqrt(nb2);
+    if (threadIdx.x == 0) res[kTailSolveHead] = 1.0;
+    while (k < max_iter) {
+      tail_cycle<double, DIM, KIND>(D, tail_lds, par, (k == 0 ? 1 : 0) | (I.flag & 6));
+      ++k;
+      const double* x = tail_x0(D, tail_lds, par);
+      double sr = 0.0;
+      for_unknowns<DIM>(n0, g0, [&](long p, int i, int j, int kk) {
+        const double r = residual_node<double, DIM, KIND>(op, kap, g0, x, bd, p, i, j, kk);
+        sr += r * r;
+      });
+      const double rho = sqrt(tail_block_sum(sr, ws)) / nb;
+      if (threadIdx.x == 0) res[kTailSolveHead + k] = rho;
+      if (!isfinite(rho) || rho > 1e3) {
+        status = TS_DIVERGED;
+        break;
+      }
+      if (rho <= tol) {
+        status = TS_OK;
+        break;
+      }
+    }
+  }
+  // every node of u: the iterate's boundary entries in LDS are 0
+  const double* src = tail_x0(D, tail_lds, par);
+  const long nodes = DIM == 3 ? g0.sz * (n0 + 1) : g0.sy * (n0 + 1);
+  for (long q = threadIdx.x; q < nodes; q += blockDim.x) ug[q] = src[q];
+  if (threadIdx.x == 0) {
+    res[0] = (double)status;
+    res[1] = (double)k;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -2393,6 +2506,26 @@ void launch_tail(int dim, int kind, int lds_bytes, const Batch& B, hipStream_t s
 #define L_TAIL(D, K) launch_tail_k<T, D, K>(lds_bytes, B, s)
   DISPATCH_DIM_KIND(dim, kind, L_TAIL);
 #undef L_TAIL
+}
+
+template <int D, int K>
+static void launch_tail_solve_k(int lds_bytes, const Batch& B, double tol, int max_iter,
+                                hipStream_t s) {
+  static const bool attr = [] {
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tail_solve<D, K>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize,
+                               kTailLdsBytes) == hipSuccess;
+  }();
+  (void)attr;
+  hipLaunchKernelGGL((k_tail_solve<D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B,
+                     tol, max_iter);
+}
+
+void launch_tail_solve(int dim, int kind, int lds_bytes, const Batch& B, double tol, int max_iter,
+                       hipStream_t s) {
+#define L_TSOLVE(D, K) launch_tail_solve_k<D, K>(lds_bytes, B, tol, max_iter, s)
+  DISPATCH_DIM_KIND(dim, kind, L_TSOLVE);
+#undef L_TSOLVE
 }
 
 void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s) {

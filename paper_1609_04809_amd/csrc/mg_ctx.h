@@ -117,6 +117,9 @@ struct mg_ctx {
   long npart = 0;
   double* scal = nullptr;       // device scalars: [0] residual norm^2, [1] ||b||^2, [2] scratch
   int* ibuf = nullptr;          // device ints (setup checks)
+  double* tres = nullptr;       // results of a one-workgroup whole solve (status,
+                                // cycles, history), kTailSolveHead + max_iter + 1
+  int npinned = 0;              // doubles at `pinned`
   void* tail64 = nullptr;       // TailDesc<double> (device)
   void* tail32 = nullptr;       // TailDesc<float> (device)
   int tail_lds[2] = {0, 0};     // dynamic LDS bytes of the tail launch (FP64, FP32)

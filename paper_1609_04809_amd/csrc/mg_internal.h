@@ -268,6 +268,19 @@ void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s);
 template <typename T>
 void launch_tail(int dim, int kind, int lds_bytes, const Batch& B, hipStream_t s);
 
+// A whole FP64 solve by one workgroup per request, for hierarchies the
+// tail holds from their finest level on (TailDesc from level 0):  a =
+// TailDesc<double>* (device), b = b (finest level, natural layout), c = u
+// (out: every node), scal = results (kTailSolveHead + max_iter + 1
+// doubles: status (TailSolveStatus), cycles done, then the relative
+// residual history from cycle 0), flag = cycle kind << 1.  Stops at the
+// first cycle whose relative residual is <= tol, or on divergence (not
+// finite or > 1e3), or after max_iter cycles.
+enum TailSolveStatus { TS_OK = 0, TS_MAXIT = 1, TS_DIVERGED = 2, TS_NONFINITE_B = 3 };
+constexpr int kTailSolveHead = 2;
+void launch_tail_solve(int dim, int kind, int lds_bytes, const Batch& B, double tol, int max_iter,
+                       hipStream_t s);
+
 void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s);
 void launch_cast_f32(const double* a, float* b, long count, hipStream_t s);
 void launch_count_bad_kappa(const double* k, long count, int* bad_nonpos, int* bad_nonfinite,

@@ -247,6 +247,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
   double* part = P.take<double>(maxpart);
   double* scal = P.take<double>(8);
   int* ibuf = P.take<int>(8);
+  double* tres = P.take<double>(kTailSolveHead + o.max_iter + 1);
   void* t64 = P.take<TailDesc<double>>(1);
   void* t32 = ir ? (void*)P.take<TailDesc<float>>(1) : nullptr;
   if (c) {
@@ -256,6 +257,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
     c->npart = maxpart;
     c->scal = scal;
     c->ibuf = ibuf;
+    c->tres = tres;
     c->tail64 = t64;
     c->tail32 = t32;
   }
@@ -266,7 +268,7 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
 // neighbour at offset d, from the cell coefficients kap (nullptr = 1):
 // the sum over the cells containing both nodes of kappa_c times the element
 // matrix entry, which depends only on the number of nonzero components of d.
-double q1_entry(int dim, int n, const std::vector<double>* kap, double sigma, int i, int j, int k,
+double q1_entry(int dim, int n, const double* kap, double sigma, int i, int j, int k,
                 int dx, int dy, int dz) {
   const double h = 1.0 / n;
   const double f3[4] = {4.0, 0.0, -1.0, -1.0};
@@ -284,7 +286,7 @@ double q1_entry(int dim, int n, const std::vector<double>* kap, double sigma, in
         } else {
           const long cell = (long)(i - 1 + a) + (long)n * (j - 1 + b) +
                             (dim == 3 ? (long)n * n * (k - 1 + c) : 0L);
-          ks += (*kap)[cell];
+          ks += kap[cell];
         }
       }
   // mass: (h/6)^dim 2^(dim-cls) per cell on the 2^(dim-cls) shared cells
@@ -292,18 +294,12 @@ double q1_entry(int dim, int n, const std::vector<double>* kap, double sigma, in
   return (dim == 3 ? (h / 12.0) * f3[cls] * ks : (1.0 / 6.0) * f2[cls] * ks) + mass;
 }
 
-// Dense coarsest matrix and its Cholesky factor (row major, lower).
-mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
-  const Level& Lv = c->lv[c->L - 1];
-  const int dim = c->o.dim, n = Lv.g.n, mi = n - 1, m = c->m;
-  std::vector<double> kap;
-  if (c->kappa) {
-    kap.resize(ipow(n, dim));
-    HIP_TRY(hipMemcpyAsync(kap.data(), Lv.kap64, kap.size() * sizeof(double),
-                           hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
-  std::vector<double> A((size_t)m * m, 0.0);
+// Dense matrix of a level with n cells (its m unknowns) from the cell
+// coefficients kap (host, n^d, nullptr = 1), and its Cholesky factor in
+// place (row major, lower): A = L L^T.  A holds m * m doubles.
+mg_status coarse_cholesky(int dim, int n, const double* kap, double sigma, int m, double* A) {
+  const int mi = n - 1;
+  for (long q = 0; q < (long)m * m; ++q) A[q] = 0.0;
   for (int q = 0; q < m; ++q) {
     const int i = q % mi + 1, j = (q / mi) % mi + 1, k = dim == 3 ? q / (mi * mi) + 1 : 0;
     for (int dz = (dim == 3 ? -1 : 0); dz <= (dim == 3 ? 1 : 0); ++dz)
@@ -313,11 +309,9 @@ mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
           if (qi < 1 || qi > mi || qj < 1 || qj > mi) continue;
           if (dim == 3 && (qk < 1 || qk > mi)) continue;
           const int q2 = (qi - 1) + mi * (qj - 1) + (dim == 3 ? mi * mi * (qk - 1) : 0);
-          A[(size_t)q * m + q2] =
-              q1_entry(dim, n, c->kappa ? &kap : nullptr, c->o.sigma, i, j, k, dx, dy, dz);
+          A[(size_t)q * m + q2] = q1_entry(dim, n, kap, sigma, i, j, k, dx, dy, dz);
         }
   }
-  // Cholesky A = L L^T (lower, row major), in place.
   for (int jj = 0; jj < m; ++jj) {
     double d = A[(size_t)jj * m + jj];
     for (int p = 0; p < jj; ++p) d -= A[(size_t)jj * m + p] * A[(size_t)jj * m + p];
@@ -331,6 +325,23 @@ mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
     }
     for (int p = jj + 1; p < m; ++p) A[(size_t)jj * m + p] = 0.0;
   }
+  return MG_OK;
+}
+
+// The context's coarsest factor, built on the host and copied to c->Lc.
+mg_status coarse_factor(mg_ctx* c, hipStream_t s) {
+  const Level& Lv = c->lv[c->L - 1];
+  const int dim = c->o.dim, n = Lv.g.n, m = c->m;
+  std::vector<double> kap;
+  if (c->kappa) {
+    kap.resize(ipow(n, dim));
+    HIP_TRY(hipMemcpyAsync(kap.data(), Lv.kap64, kap.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  std::vector<double> A((size_t)m * m, 0.0);
+  mg_status st = coarse_cholesky(dim, n, c->kappa ? kap.data() : nullptr, c->o.sigma, m, A.data());
+  if (st != MG_OK) return st;
   HIP_TRY(hipMemcpyAsync(c->Lc, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));
   return MG_OK;
@@ -426,11 +437,9 @@ double stiff_weight(int dim, double h, int cls) {
   return w[cls];
 }
 
-void set_stencil(mg_ctx* c, int l) {
-  Level& Lv = c->lv[l];
-  const double h = 1.0 / Lv.g.n;
-  const int dim = c->o.dim;
-  const double sg = c->o.sigma;
+// Matrix-free operator of a level with n_l cells (see StencilParams).
+StencilParams<double> stencil_of(int dim, int nl, double sg, int kind) {
+  const double h = 1.0 / nl;
   double wc, w1, w2, s, wf = 0.0;
   if (dim == 2) {
     wc = 8.0 / 3.0;
@@ -454,9 +463,15 @@ void set_stencil(mg_ctx* c, int l) {
       w2 += sg * mass_weight(3, h, 3);
     }
   }
-  const int kind = op_kind(c);
-  Lv.st64 = StencilParams<double>{kind, wc, w1, w2, s, wf};
-  Lv.st32 = StencilParams<float>{kind, (float)wc, (float)w1, (float)w2, (float)s, (float)wf};
+  return StencilParams<double>{kind, wc, w1, w2, s, wf};
+}
+
+void set_stencil(mg_ctx* c, int l) {
+  Level& Lv = c->lv[l];
+  const StencilParams<double> p = stencil_of(c->o.dim, Lv.g.n, c->o.sigma, op_kind(c));
+  Lv.st64 = p;
+  Lv.st32 = StencilParams<float>{p.kind, (float)p.wc, (float)p.w1, (float)p.w2, (float)p.s,
+                                 (float)p.wf};
 }
 
 // ---------------------------------------------------------------------------
@@ -488,55 +503,80 @@ template <> struct Bufs<float> {
   static float* xs(Level& L, int q) { return L.xs32[q]; }
 };
 
+// Descriptor of the tail levels l0..L-1 of a hierarchy: per level (index
+// l, absolute) its cells nl[l], operator st[l] and device coefficients
+// kap[l] (OP_KAPPA); the coarsest factor Lc (m x m, device); r0buf: the
+// device vector that holds level l0's residual when the LDS cannot (the
+// level's node count).  Sets D.lds_bytes; fails when the levels exceed the
+// tail's LDS budget.
+template <typename T>
+mg_status fill_tail_desc(const mg_options& o, int L, int l0, bool kappa, int m, const double* Lc,
+                         const int* nl, const StencilParams<T>* st, const T* const* kap,
+                         T* r0buf, TailDesc<T>& D) {
+  D = TailDesc<T>{};
+  D.nlev = L - l0;
+  D.dim = o.dim;
+  D.kind = st[l0].kind;
+  D.smoother = o.smoother == MG_SMOOTH_JACOBI ? 0 : (o.smoother == MG_SMOOTH_GS ? 2 : 1);
+  D.nu_pre = o.nu_pre;
+  D.nu_post = o.nu_post;
+  D.omega = (T)o.omega;
+  D.m = m;
+  D.L = Lc;
+  // LDS layout (16-byte aligned pieces): per level iterate, spare,
+  // right-hand side, residual (and cells), then the coarsest solve's
+  // work vector; offsets of level vectors in elements of T
+  long off = 0;
+  auto take = [&](long bytes) {
+    const long at = off;
+    off += (bytes + 15) / 16 * 16;
+    return at;
+  };
+  // the first level's residual goes to device memory when all else fits
+  // the LDS only without it
+  const bool r0_global =
+      tail_lds_bytes(o.dim, o.n, L, l0, kappa, (int)sizeof(T), false) > kTailLdsBytes;
+  D.r0 = r0_global ? r0buf : nullptr;
+  for (int q = 0; q < D.nlev; ++q) {
+    const int l = l0 + q;
+    const Geo g = make_geo(o.dim, nl[l]);
+    const long vb = g.nodes * (long)sizeof(T);
+    TailLevel<T>& tl = D.lv[q];
+    tl.n = g.n;
+    tl.ox = (int)(take(vb) / sizeof(T));
+    tl.ot = (int)(take(vb) / sizeof(T));
+    tl.ob = (int)(take(vb) / sizeof(T));
+    tl.orr = (q == 0 && r0_global) ? 0 : (int)(take(vb) / sizeof(T));
+    tl.ok = kappa ? (int)(take(ipow(g.n, o.dim) * (long)sizeof(T)) / sizeof(T)) : 0;
+    tl.kappa = kap[l];
+    tl.wc = st[l].wc;
+    tl.w1 = st[l].w1;
+    tl.w2 = st[l].w2;
+    tl.s = st[l].s;
+    tl.wf = st[l].wf;
+  }
+  D.oy = (int)take((long)m * sizeof(double));
+  if (off > kTailLdsBytes) return fail(MG_E_ARG, "internal: tail levels exceed the LDS budget");
+  D.lds_bytes = (int)off;
+  return MG_OK;
+}
+
 template <typename T>
 mg_status build_tail(mg_ctx* c, hipStream_t s) {
   const int l0 = c->tail0;
   TailDesc<T> D{};
   if (l0 >= 0) {
-    D.nlev = c->L - l0;
-    D.dim = c->o.dim;
-    D.kind = Bufs<T>::st(c->lv[l0]).kind;
-    D.smoother = c->o.smoother == MG_SMOOTH_JACOBI ? 0 : (c->o.smoother == MG_SMOOTH_GS ? 2 : 1);
-    D.nu_pre = c->o.nu_pre;
-    D.nu_post = c->o.nu_post;
-    D.omega = (T)c->o.omega;
-    D.m = c->m;
-    D.L = c->Lc;
-    // LDS layout (16-byte aligned pieces): per level iterate, spare,
-    // right-hand side, residual (and cells), then the coarsest solve's
-    // work vector; offsets of level vectors in elements of T
-    long off = 0;
-    auto take = [&](long bytes) {
-      const long at = off;
-      off += (bytes + 15) / 16 * 16;
-      return at;
-    };
-    // the first level's residual goes to device memory when all else fits
-    // the LDS only without it
-    const bool r0_global = tail_lds_bytes(c->o.dim, c->o.n, c->L, l0, c->kappa,
-                                          (int)sizeof(T), false) > kTailLdsBytes;
-    D.r0 = r0_global ? Bufs<T>::r(c->lv[l0]) : nullptr;
-    for (int q = 0; q < D.nlev; ++q) {
-      Level& Lv = c->lv[l0 + q];
-      const StencilParams<T>& st = Bufs<T>::st(Lv);
-      const long vb = Lv.g.nodes * (long)sizeof(T);
-      TailLevel<T>& tl = D.lv[q];
-      tl.n = Lv.g.n;
-      tl.ox = (int)(take(vb) / sizeof(T));
-      tl.ot = (int)(take(vb) / sizeof(T));
-      tl.ob = (int)(take(vb) / sizeof(T));
-      tl.orr = (q == 0 && r0_global) ? 0 : (int)(take(vb) / sizeof(T));
-      tl.ok = c->kappa ? (int)(take(ipow(Lv.g.n, c->o.dim) * (long)sizeof(T)) / sizeof(T)) : 0;
-      tl.kappa = Bufs<T>::kap(Lv);
-      tl.wc = st.wc;
-      tl.w1 = st.w1;
-      tl.w2 = st.w2;
-      tl.s = st.s;
-      tl.wf = st.wf;
+    std::vector<int> nl(c->L);
+    std::vector<StencilParams<T>> st(c->L);
+    std::vector<const T*> kap(c->L);
+    for (int l = 0; l < c->L; ++l) {
+      nl[l] = c->lv[l].g.n;
+      st[l] = Bufs<T>::st(c->lv[l]);
+      kap[l] = Bufs<T>::kap(c->lv[l]);
     }
-    D.oy = (int)take((long)c->m * sizeof(double));
-    if (off > kTailLdsBytes) return fail(MG_E_ARG, "internal: tail levels exceed the LDS budget");
-    D.lds_bytes = (int)off;
+    mg_status r = fill_tail_desc<T>(c->o, c->L, l0, c->kappa, c->m, c->Lc, nl.data(), st.data(),
+                                    kap.data(), Bufs<T>::r(c->lv[l0]), D);
+    if (r != MG_OK) return r;
   }
   c->tail_lds[Bufs<T>::prec] = D.lds_bytes;
   HIP_TRY(hipMemcpyAsync(Bufs<T>::tail(c), &D, sizeof D, hipMemcpyHostToDevice, s));
@@ -1281,6 +1321,41 @@ size_t plan_bytes(const mg_options& o, bool has_kappa) { return plan(o, has_kapp
 
 }  // namespace mg
 
+namespace {
+
+// Whether mg_solve runs the whole solve in one workgroup (k_tail_solve):
+// FP64 cycles with the matrix-free operator on a hierarchy the tail holds
+// from its finest level on, no CG and no warm start; MG_FLAG_NO_FUSE keeps
+// the cycle-by-cycle iteration (one tail launch and one residual norm per
+// cycle, read by the host).
+bool whole_tail_solve(const mg_ctx* c) {
+  return c->tail0 == 0 && !c->ir && !c->csr && !c->prof_on &&
+         !(c->o.flags & (MG_FLAG_PCG | MG_FLAG_WARM | MG_FLAG_NO_FUSE));
+}
+
+// Status, cycle count and history from the results of k_tail_solve (res:
+// host copy of kTailSolveHead + max_iter + 1 doubles).
+mg_status tail_solve_result(const double* res, int max_iter, double tol, int* iters,
+                            double* hist) {
+  const int status = (int)res[0];
+  const int k = (int)res[1];
+  *iters = k;
+  if (hist) {
+    hist[0] = 1.0;
+    for (int q = 1; q <= k && q <= max_iter; ++q) hist[q] = res[kTailSolveHead + q];
+  }
+  switch (status) {
+    case TS_OK: return MG_OK;
+    case TS_NONFINITE_B: return fail(MG_E_NONFINITE, "b holds NaN or Inf");
+    case TS_DIVERGED:
+      return fail(MG_E_DIVERGED, "relative residual %g after %d cycles", res[kTailSolveHead + k],
+                  k);
+    default: return fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, max_iter);
+  }
+}
+
+}  // namespace
+
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
@@ -1344,7 +1419,9 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream, m
   }
   c->arena_bytes = bytes;
   plan(*o, c->kappa, c->arena, c);
-  if (hipHostMalloc(&c->pinned, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+  c->npinned = std::max(8, kTailSolveHead + o->max_iter + 1);
+  if (hipHostMalloc(&c->pinned, c->npinned * sizeof(double), hipHostMallocDefault) !=
+      hipSuccess) {
     c->pinned = nullptr;
     return bail(fail(MG_E_HIP, "hipHostMalloc failed"));
   }
@@ -1428,6 +1505,22 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   c->b0_split = split_b0(c->o);
   const bool pcg = (c->o.flags & MG_FLAG_PCG) != 0;
   const bool warm = (c->o.flags & MG_FLAG_WARM) != 0;
+  if (whole_tail_solve(c)) {
+    // every cycle, the norm and the stopping test in one launch; one read
+    Batch B{};
+    B.count = 1;
+    B.it[0].a = c->tail64;
+    B.it[0].b = b;
+    B.it[0].c = u;
+    B.it[0].scal = c->tres;
+    B.it[0].flag = c->o.cycle << 1;
+    launch_tail_solve(c->o.dim, c->lv[0].st64.kind, c->tail_lds[0], B, tol, c->o.max_iter, s);
+    HIP_TRY(hipGetLastError());
+    const int nres = kTailSolveHead + c->o.max_iter + 1;
+    HIP_TRY(hipMemcpyAsync(c->pinned, c->tres, nres * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return tail_solve_result(c->pinned, c->o.max_iter, tol, iters, hist);
+  }
   const bool fuse = head_fusion(c);
   const double* bc = b;  // b as the cycles read it
   if (c->b0_split) {

@@ -72,7 +72,10 @@ def test_w_f_tail_and_grid_levels_agree_bitwise(kind, dim, n, levels, kap, prec)
             u, k, hist, st = S.solve(b, 1e-8)
             assert st == "ok"
             outs.append((k, hist, host_full(u)))
-    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    # iterates bitwise; a hierarchy the tail holds whole (2D 64^2 FP64) is
+    # solved in one launch that sums the residual norm in its own order
+    assert outs[0][0] == outs[1][0]
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=0)
     assert np.array_equal(outs[0][2], outs[1][2])
 
 

@@ -126,20 +126,75 @@ def test_graph_and_eager_agree_bitwise():
 ])
 def test_tail_and_grid_levels_agree_bitwise(dim, n, levels, kap, prec, smoother):
     """Coarse levels cycled inside one workgroup compute bitwise what the
-    level-by-level grid launches compute."""
+    level-by-level grid launches compute.  Where the tail holds the whole
+    FP64 hierarchy, the default solve runs every cycle in one launch and
+    sums the residual norm inside the workgroup: the iterates are bitwise
+    those of the cycle-by-cycle solve (MG_FLAG_NO_FUSE), the histories agree
+    to rounding of the norm."""
     torch_cuda()
-    from paper_1609_04809_amd.mg import FLAG_NO_TAIL, Solver
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, FLAG_NO_TAIL, Solver
     kappa = W.kappa_lognormal(dim, n, 4) if kap else None
     b = dev_full(dim, n, W.rhs_uniform(dim, n, 8))
     outs = []
-    for flags in (0, FLAG_NO_TAIL):
+    for flags in (0, FLAG_NO_TAIL, FLAG_NO_FUSE):
         with Solver(dim, n, levels, kappa=kappa, precision=prec, smoother=smoother,
                     flags=flags) as S:
             u, k, hist, st = S.solve(b, 1e-8)
             assert st == "ok"
             outs.append((k, hist, host_full(u)))
-    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
-    assert np.array_equal(outs[0][2], outs[1][2])
+    assert outs[0][0] == outs[1][0] == outs[2][0]
+    assert outs[1][1] == outs[2][1]
+    np.testing.assert_allclose(outs[0][1], outs[1][1], rtol=1e-12, atol=0)
+    assert np.array_equal(outs[0][2], outs[1][2]) and np.array_equal(outs[1][2], outs[2][2])
+
+
+@pytest.mark.parametrize("dim,n,levels,kap,smoother,cycle,sigma", [
+    (2, 64, 5, False, "jacobi", "V", 0.0),     # the 2D 64^2 Jacobi workload's shape
+    (2, 32, 4, True, "rbgs", "V", 0.0),
+    (2, 64, 5, True, "rbgs", "W", 0.0),
+    (3, 16, 4, False, "rbgs", "V", 0.0),
+    (3, 16, 4, True, "rbgs", "F", 0.0),
+    (3, 16, 4, False, "rbgs", "V", 50.0),
+    (3, 8, 3, False, "gs", "V", 0.0),
+    (2, 16, 1, False, "rbgs", "V", 0.0),      # one level: the exact solve
+])
+def test_whole_solve_in_one_workgroup(dim, n, levels, kap, smoother, cycle, sigma):
+    """The one-launch solve of a hierarchy the tail holds: the oracle's cycle
+    count +-1 and iterate within 1e-8, bitwise the cycle-by-cycle solve's
+    iterates, maxit and b = 0 handled like the cycle-by-cycle solve."""
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    kappa = W.kappa_lognormal(dim, n, 6) if kap else None
+    bi = W.rhs_uniform(dim, n, 9)
+    b = dev_full(dim, n, bi)
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother, cycle=cycle,
+                          sigma=sigma)
+    u_or, k_or, hist_or, st_or = O.solve(H, bi, 1e-9)
+    assert st_or == "ok"
+    res = {}
+    for flags in (0, FLAG_NO_FUSE):
+        with Solver(dim, n, levels, kappa=kappa, smoother=smoother, cycle=cycle, sigma=sigma,
+                    flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-9)
+            res[flags] = (k, hist, host_full(u), st)
+    k, hist, uf, st = res[0]
+    assert st == "ok" and abs(k - k_or) <= 1, (k, k_or)
+    assert res[FLAG_NO_FUSE][0] == k and np.array_equal(res[FLAG_NO_FUSE][2], uf)
+    np.testing.assert_allclose(hist, res[FLAG_NO_FUSE][1], rtol=1e-12, atol=0)
+    kk = min(k, k_or)
+    np.testing.assert_allclose(hist[1:kk + 1], hist_or[1:kk + 1], rtol=1e-6, atol=1e-14)
+    if k != k_or:
+        u_or, _, _, _ = O.solve(H, bi, 1e-300, max_iter=k)
+    ug = W.full_to_interior(dim, n, uf)
+    assert np.linalg.norm(ug - u_or) <= 1e-8 * np.linalg.norm(u_or)
+    assert not uf.reshape((n + 1,) * dim)[(0,) * dim]
+    with Solver(dim, n, levels, kappa=kappa, smoother=smoother, cycle=cycle, sigma=sigma,
+                max_iter=2) as S:
+        u2, k2, h2, st2 = S.solve(b, 1e-300)
+        assert st2 == "maxit" and k2 == 2 and len(h2) == 3
+        z = torch.zeros_like(b)
+        u3, k3, h3, st3 = S.solve(z, 1e-8)
+        assert st3 == "ok" and k3 == 0 and h3 == [1.0] and not torch.any(u3)
 
 
 @pytest.mark.parametrize("dim,n,levels,op,smoother,kap,nu", [
