@@ -193,6 +193,28 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream,
 mg_status mg_solve(mg_ctx* ctx, const double* b_dev, double* u_dev, double tol,
                    int* iters, double* hist_host, void* stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, e.g. tight serving loops or harnesses that forbid it): the
+ * whole mg_solve of a small hierarchy without a context, taking every
+ * buffer beyond b and u from a fixed device scratch array of 1 MiB that the
+ * library holds per GPU until the process ends.  The options are those of
+ * mg_setup, restricted to MG_PREC_FP64, MG_OP_STENCIL, flags = 0 and
+ * max_iter <= 1000, on a hierarchy that one workgroup's LDS holds whole
+ * (2D n <= 64, 3D n <= 16, e.g. the 2D 64^2 / 5-level problem) whose
+ * coarsest level has at most 256 unknowns.  Arguments and results as for
+ * mg_setup (kappa_dev: device, n^dim cells, or NULL) followed by mg_solve
+ * (b_dev, u_dev, tol, iters, hist_host); the cycles are those of mg_solve,
+ * which gives the same iterates.  Calls made from several host threads of
+ * a process run one after the other, each to completion on its stream
+ * (host-synchronous); the scratch keeps the last call's contents, so calls
+ * from separate processes on one GPU do not share it.  Errors: MG_E_ARG
+ * (options or sizes outside these limits, kappa <= 0), MG_E_NONFINITE,
+ * MG_E_NOT_SPD, MG_E_MAXIT / MG_E_DIVERGED (u, iters, hist valid),
+ * MG_E_HIP. */
+mg_status mg_solve_noalloc(const mg_options* o, const double* kappa_dev,
+                           const double* b_dev, double* u_dev, double tol,
+                           int* iters, double* hist_host, void* stream);
+
 /* Right-hand side of one Crank-Nicolson step of the heat equation (the
  * model problem of Sec. 6.2) for a context with A = K + sigma M, sigma =
  * 2/dt (kappa = 1): on the unknowns

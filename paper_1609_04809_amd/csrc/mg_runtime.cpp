@@ -18,6 +18,7 @@
 #include <cstring>
 #include <functional>
 #include <initializer_list>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -1816,6 +1817,155 @@ mg_status mg_profile_read(mg_ctx* c, long* launches, double* total_ms) {
   if (launches) *launches = c->prof_launches;
   if (total_ms) *total_ms = c->prof_ms;
   return MG_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// the solve that allocates nothing (mg_solve_noalloc)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Device scratch of mg_solve_noalloc, one copy per GPU for the life of the
+// process.  Host code never passes `scratch` itself to a kernel or a copy:
+// it uses the device address hipGetSymbolAddress returns for the current
+// device (noalloc_scratch).  Layout (bytes):
+constexpr long kNaDesc = 0;                    // TailDesc<double>
+constexpr long kNaRes = 4096;                  // results: status, cycles, history
+constexpr int kNaMaxIter = 1000;               // max_iter accepted
+constexpr long kNaBad = 12288;                 // two ints: kappa check counters
+constexpr long kNaKappa = 12544;               // cell coefficients, every level
+constexpr long kNaKappaCells = 8192;
+constexpr long kNaR0 = kNaKappa + 8 * kNaKappaCells;  // finest residual (if not in LDS)
+constexpr long kNaR0Nodes = 5120;
+constexpr long kNaL = kNaR0 + 8 * kNaR0Nodes;  // coarsest Cholesky factor
+constexpr int kNaMaxCoarse = 256;              // coarsest unknowns accepted
+constexpr long kNaBytes = 1L << 20;
+static_assert(sizeof(TailDesc<double>) <= kNaRes - kNaDesc, "descriptor slot");
+static_assert((kTailSolveHead + kNaMaxIter + 1) * 8 <= kNaBad - kNaRes, "result slot");
+static_assert(kNaL % 256 == 0 && kNaKappa % 256 == 0 && kNaR0 % 256 == 0, "alignment");
+static_assert(kNaL + 8L * kNaMaxCoarse * kNaMaxCoarse <= kNaBytes, "scratch size");
+
+__device__ __align__(256) char scratch[kNaBytes];
+
+// Host state of mg_solve_noalloc, used under g_na_mu only: calls from
+// several threads run one after the other, each to completion.
+std::mutex g_na_mu;
+char* g_na_ptr[64] = {};                        // device address per device
+double g_na_L[kNaMaxCoarse * kNaMaxCoarse];     // coarsest factor (host)
+double g_na_kc[4096];                           // coarsest cell coefficients (host)
+double g_na_res[kTailSolveHead + kNaMaxIter + 1];
+TailDesc<double> g_na_desc;
+
+// The scratch array's device address on the current device (looked up once
+// per device).
+mg_status noalloc_scratch(char** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(MG_E_ARG, "device %d out of range", dev);
+  if (!g_na_ptr[dev]) {
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    g_na_ptr[dev] = static_cast<char*>(ptr);
+  }
+  *out = g_na_ptr[dev];
+  return MG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+mg_status mg_solve_noalloc(const mg_options* o, const double* kappa_dev, const double* b,
+                           double* u, double tol, int* iters, double* hist, void* stream) {
+  if (!b || !u || !iters) return fail(MG_E_ARG, "NULL argument");
+  std::string why;
+  if (!valid_options(o, why)) return fail(MG_E_ARG, "%s", why.c_str());
+  if (!(tol > 0.0)) return fail(MG_E_ARG, "tol must be > 0");
+  if ((const void*)b == (const void*)u) return fail(MG_E_ARG, "u must not alias b");
+  if (o->precision != MG_PREC_FP64 || o->op != MG_OP_STENCIL || o->flags != 0)
+    return fail(MG_E_ARG, "the no-allocation solve takes FP64, the matrix-free operator and "
+                          "no flags");
+  if (o->max_iter > kNaMaxIter)
+    return fail(MG_E_ARG, "max_iter %d above the no-allocation limit %d", o->max_iter,
+                kNaMaxIter);
+  const bool kappa = kappa_dev != nullptr;
+  if (kappa && o->sigma > 0.0)
+    return fail(MG_E_ARG, "the matrix-free operator with per-cell kappa has no mass term");
+  if (tail_start(*o, kappa) != 0)
+    return fail(MG_E_ARG, "the no-allocation solve needs a hierarchy one workgroup holds "
+                          "(finest level at most %d unknowns, its vectors within %d bytes "
+                          "of LDS)", kTailMaxUnknowns, kTailLdsBytes);
+  const int L = o->levels, dim = o->dim;
+  const int nc = o->n >> (L - 1);
+  const int m = (int)ipow(nc - 1, dim);
+  if (m > kNaMaxCoarse)
+    return fail(MG_E_ARG, "coarsest level has %d unknowns (the no-allocation solve takes at "
+                          "most %d): use more levels", m, kNaMaxCoarse);
+  long cells = 0;
+  for (int l = 0; l < L; ++l) cells += ipow(o->n >> l, dim);
+  if ((kappa && cells > kNaKappaCells) || ipow(o->n + 1L, dim) > kNaR0Nodes ||
+      ipow(nc, dim) > 4096)
+    return fail(MG_E_ARG, "internal: hierarchy exceeds the no-allocation scratch");
+  hipStream_t s = as_stream(stream);
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  char* base = nullptr;
+  mg_status st = noalloc_scratch(&base);
+  if (st != MG_OK) return st;
+  double* kap[kTailMaxLevels] = {};
+  const double* kc_host = nullptr;
+  if (kappa) {
+    int* bad = reinterpret_cast<int*>(base + kNaBad);
+    int badh[2] = {0, 0};
+    launch_fill<double>(reinterpret_cast<double*>(bad), 1, 0.0, s);  // both counters = 0
+    launch_count_bad_kappa(kappa_dev, ipow(o->n, dim), bad, bad + 1, s);
+    HIP_TRY(hipMemcpyAsync(badh, bad, sizeof badh, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (badh[1]) return fail(MG_E_NONFINITE, "kappa has %d non-finite entries", badh[1]);
+    if (badh[0]) return fail(MG_E_ARG, "kappa has %d entries <= 0", badh[0]);
+    double* k = reinterpret_cast<double*>(base + kNaKappa);
+    for (int l = 0; l < L; ++l) {
+      kap[l] = k;
+      k += ipow(o->n >> l, dim);
+    }
+    HIP_TRY(hipMemcpyAsync(kap[0], kappa_dev, ipow(o->n, dim) * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+    for (int l = 1; l < L; ++l) launch_kappa_coarsen(dim, o->n >> (l - 1), kap[l - 1], kap[l], s);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(g_na_kc, kap[L - 1], ipow(nc, dim) * sizeof(double),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    kc_host = g_na_kc;
+  }
+  st = coarse_cholesky(dim, nc, kc_host, o->sigma, m, g_na_L);
+  if (st != MG_OK) return st;
+  double* Ld = reinterpret_cast<double*>(base + kNaL);
+  HIP_TRY(hipMemcpyAsync(Ld, g_na_L, (size_t)m * m * sizeof(double), hipMemcpyHostToDevice, s));
+  int nl[kTailMaxLevels];
+  StencilParams<double> stp[kTailMaxLevels];
+  const int kind = kappa ? OP_KAPPA : (dim == 3 && o->sigma > 0.0 ? OP_MASS : OP_CONST);
+  for (int l = 0; l < L; ++l) {
+    nl[l] = o->n >> l;
+    stp[l] = stencil_of(dim, nl[l], o->sigma, kind);
+  }
+  st = fill_tail_desc<double>(*o, L, 0, kappa, m, Ld, nl, stp, kap,
+                              reinterpret_cast<double*>(base + kNaR0), g_na_desc);
+  if (st != MG_OK) return st;
+  HIP_TRY(hipMemcpyAsync(base + kNaDesc, &g_na_desc, sizeof g_na_desc, hipMemcpyHostToDevice, s));
+  Batch B{};
+  B.count = 1;
+  B.it[0].a = base + kNaDesc;
+  B.it[0].b = b;
+  B.it[0].c = u;
+  B.it[0].scal = reinterpret_cast<double*>(base + kNaRes);
+  B.it[0].flag = o->cycle << 1;
+  launch_tail_solve(dim, kind, g_na_desc.lds_bytes, B, tol, o->max_iter, s);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(g_na_res, base + kNaRes,
+                         (kTailSolveHead + o->max_iter + 1) * sizeof(double),
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return tail_solve_result(g_na_res, o->max_iter, tol, iters, hist);
 }
 
 }  // extern "C"

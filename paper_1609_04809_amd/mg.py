@@ -78,6 +78,8 @@ SIGNATURES = {
     "mg_cn_rhs": (_I, [_VP, _VP, _VP, _VP, ctypes.c_double, _VP, ctypes.c_double, _VP,
                        ctypes.c_double, _VP, _VP]),
     "mg_apply_mass": (_I, [_VP, _VP, _VP, _VP]),
+    "mg_solve_noalloc": (_I, [ctypes.POINTER(Options), _VP, _VP, _VP, ctypes.c_double,
+                              ctypes.POINTER(_I), ctypes.POINTER(ctypes.c_double), _VP]),
     "mg_profile_enable": (_I, [_VP, _I, _I]),
     "mg_profile_read": (_I, [_VP, ctypes.POINTER(ctypes.c_long),
                              ctypes.POINTER(ctypes.c_double)]),
@@ -301,6 +303,23 @@ class Solver:
         ms = ctypes.c_double()
         _check(lib().mg_profile_read(self._ctx, ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+def solve_noalloc(dim, n, levels, b, tol, u=None, kappa=None, **kw):
+    """mg_solve_noalloc: one solve of a small hierarchy without a context or
+    any device allocation by the library (b, u, kappa: device float64
+    tensors).  Returns (u, iters, hist, status_name) like Solver.solve."""
+    o = make_options(dim, n, levels, **kw)
+    if u is None:
+        u = torch.empty_like(b)
+    iters = ctypes.c_int()
+    hist = (ctypes.c_double * (o.max_iter + 1))()
+    st = lib().mg_solve_noalloc(ctypes.byref(o), _ptr(kappa), _ptr(b), _ptr(u), float(tol),
+                                ctypes.byref(iters), hist, _stream())
+    if st not in (MG_OK, MG_E_MAXIT, MG_E_DIVERGED):
+        _check(st)
+    k = iters.value
+    return u, k, list(hist[: k + 1]), STATUS_NAMES[st]
 
 
 class Server:

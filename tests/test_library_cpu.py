@@ -156,3 +156,29 @@ def test_split_layout_footprint(kw, split_b, split_x):
     kap = sum(_aligned((n >> l) ** dim * 8) + (_aligned((n >> l) ** dim * 4) if ir else 0)
               for l in range(levels))
     assert f - f_nat == max(d_b, d_b + d_x - kap), (f - f_nat, d_b, d_x, kap)
+
+
+def test_noalloc_solve_refuses_what_it_cannot_hold():
+    """mg_solve_noalloc checks its limits before it touches the GPU."""
+    mg = _lib()
+    L = mg.lib()
+    fake = ctypes.c_void_p(0x1000)
+    it = ctypes.c_int()
+    hist = (ctypes.c_double * 1001)()
+
+    def call(**kw):
+        dim, n, levels = kw.pop("shape")
+        o = mg.make_options(dim, n, levels, **kw)
+        return L.mg_solve_noalloc(ctypes.byref(o), None, fake, ctypes.c_void_p(0x2000), 1e-8,
+                                  ctypes.byref(it), hist, None)
+
+    assert call(shape=(2, 128, 6)) == mg.MG_E_ARG             # finest level too large
+    assert b"one workgroup" in L.mg_last_error()
+    assert call(shape=(3, 32, 5)) == mg.MG_E_ARG
+    assert call(shape=(2, 64, 2)) == mg.MG_E_ARG              # coarsest 31^2 unknowns
+    assert b"coarsest" in L.mg_last_error()
+    assert call(shape=(2, 64, 5), precision="fp32_ir") == mg.MG_E_ARG
+    assert call(shape=(2, 64, 5), op="csr") == mg.MG_E_ARG
+    assert call(shape=(2, 64, 5), flags=mg.FLAG_NO_GRAPH) == mg.MG_E_ARG
+    assert call(shape=(2, 64, 5), max_iter=1001) == mg.MG_E_ARG
+
