@@ -508,6 +508,11 @@ def main():
         serving["burst_2GiB_budget"] = serve_load.run_trace(burst[: max(1, nreq // 5)],
                                                             2 << 30, 64, log=log)
         log(f"[bench] serving small budget: {serving['burst_2GiB_budget']}")
+        # the same arrivals with a quarter of the requests variable-coefficient
+        mixed = W.serving_trace(num=nreq, rate=200.0, seed=0, kappa_frac=0.25)
+        serving["poisson_arrivals_200_per_s_kappa_25pct"] = serve_load.run_trace(
+            mixed, 64 << 30, 64, log=log)
+        log(f"[bench] serving with kappa: {serving['poisson_arrivals_200_per_s_kappa_25pct']}")
     cpu = None
     if not args.no_cpu:
         log("[bench] CPU oracle baseline ...")

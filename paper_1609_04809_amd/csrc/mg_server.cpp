@@ -11,7 +11,10 @@
 // waiting for a norm read-back, groups launches with the same kernel, level
 // shape and precision, and issues each group as one batched launch on the
 // lane's stream (a lane's lone runnable request queues the rest of its
-// iteration at once).  A request that finishes an iteration (or its
+// iteration at once).  A new request goes to the lane that runs most
+// requests of its shape, and a request about to start an iteration while
+// another of its shape in its lane is inside one waits (at most 1 ms) for
+// that one, so that their iterations proceed as batched launches.  A request that finishes an iteration (or its
 // prologue) copies its norms to pinned host memory behind an event and
 // waits for that event alone; the other requests keep the GPU busy
 // meanwhile.
@@ -80,6 +83,7 @@ struct Request {
   double rho = 1.0;
   bool waiting = false;
   int lane = 0;  // the stream its launches and read-backs go to
+  double hold_until = 0;  // aligning with a same-shape request: held until then
   hipEvent_t ev = nullptr;
   double* pin = nullptr;  // 2 pinned doubles: ||r||^2, ||b||^2
   // b: host copy to the pinned staging (copy thread), then one DMA; u: DMA
@@ -131,6 +135,11 @@ struct mg_server {
   static constexpr int kLanes = 4;
   hipStream_t lanes[kLanes] = {};
   static constexpr int kStepsAhead = 8;
+  // longest wait of a request that aligns its iteration with another one's
+  static constexpr double kHoldS = 1e-3;
+  // how many more active requests than the least loaded lane a lane may
+  // hold and still be chosen for a request of a shape it runs
+  static constexpr int kLaneSlack = 4;
   hipEvent_t step_ev[kLanes][kStepsAhead] = {};
   int step_head[kLanes] = {};
   // host copies between pageable request memory and the pinned staging run
@@ -267,6 +276,33 @@ void finish(mg_server* S, Request& r, int status) {
   if (status == MG_OK) ++S->st.completed; else ++S->st.failed;
 }
 
+// Whether two requests run the same launches (equal kernels, level shapes
+// and precision), so that their launches can be batched.
+bool same_ops(const Request& a, const Request& b) {
+  return same_shape(a.o, b.o) && a.slot.poisson == b.slot.poisson;
+}
+
+// The lane for a new request: among the lanes whose load (active
+// requests) is within kLaneSlack of the least loaded one, the one running
+// the most requests of its shape (their launches batch with its own), the
+// less loaded on a tie.  The slack keeps one shape from piling up on one
+// stream while the others idle.
+int pick_lane(mg_server* S, const Request& r) {
+  int load[mg_server::kLanes] = {}, same[mg_server::kLanes] = {};
+  for (auto& a : S->active) {
+    ++load[a->lane];
+    if (same_ops(*a, r)) ++same[a->lane];
+  }
+  const int lo = *std::min_element(load, load + mg_server::kLanes);
+  int best = -1;
+  for (int q = 0; q < mg_server::kLanes; ++q) {
+    if (load[q] > lo + mg_server::kLaneSlack) continue;
+    if (best < 0 || same[q] > same[best] || (same[q] == same[best] && load[q] < load[best]))
+      best = q;
+  }
+  return best;
+}
+
 // Admit queued requests in arrival order while slots and budget allow.
 void admit(mg_server* S) {
   for (;;) {
@@ -307,12 +343,7 @@ void admit(mg_server* S) {
       continue;
     }
     hipEventCreateWithFlags(&r->ev, hipEventDisableTiming);
-    {
-      // the lane with the fewest active requests
-      int load[mg_server::kLanes] = {};
-      for (auto& a : S->active) ++load[a->lane];
-      r->lane = (int)(std::min_element(load, load + mg_server::kLanes) - load);
-    }
+    r->lane = pick_lane(S, *r);
     // b goes to the slot's pinned staging on a copy thread, then by DMA
     r->stage = Request::STAGE_IN;
     const size_t nodes = (size_t)ipow_l(r->o.n + 1L, r->o.dim);
@@ -331,6 +362,7 @@ void after_readback(mg_server* S, std::list<std::unique_ptr<Request>>::iterator 
   Request& r = **itr;
   r.waiting = false;
   r.pc = 0;
+  r.hold_until = 0;
   int st = -1;
   if (r.phase == 0) {
     const double nb2 = r.pin[1];
@@ -394,9 +426,27 @@ void step_lane(mg_server* S, int lane, std::vector<const OpRec*>& ops,
   hipStream_t stream = S->lanes[lane];
   ops.clear();
   owners.clear();
+  const double t = now_s();
   for (auto& rp : S->active) {
     Request& r = *rp;
     if (r.stage != Request::RUN || r.waiting || r.lane != lane) continue;
+    if (r.phase == 1 && r.pc == 0 && r.hold_until >= 0) {
+      // about to start an iteration while a request of its shape in this
+      // lane is inside one: wait (at most kHoldS) for that one to come
+      // back to the start, so that the two iterations run as batched
+      // launches from then on
+      bool partner = false;
+      for (auto& qp : S->active) {
+        const Request& q = *qp;
+        partner |= &q != &r && q.lane == lane && q.stage == Request::RUN && q.phase == 1 &&
+                   (q.pc > 0 || q.waiting) && same_ops(q, r);
+      }
+      if (partner) {
+        if (r.hold_until == 0) r.hold_until = t + mg_server::kHoldS;
+        if (t < r.hold_until) continue;
+      }
+      r.hold_until = -1;  // held once (or not at all) in this iteration
+    }
     const std::vector<OpRec>& list = r.phase == 0 ? r.pro : r.it;
     ops.push_back(&list[r.pc]);
     owners.push_back(&r);

@@ -24,7 +24,8 @@ def _producer(trace, out_q, stop):
         if stop.is_set():
             return
         b = W.interior_to_full(r["dim"], r["n"], W.rhs_uniform(r["dim"], r["n"], r["seed"]))
-        out_q.put((r, b))
+        kappa = W.kappa_lognormal(r["dim"], r["n"], r["seed"]) if r.get("kappa") else None
+        out_q.put((r, b, kappa))
     out_q.put(None)
 
 
@@ -49,15 +50,15 @@ def run_trace(trace, hbm_budget_bytes, max_slots=64, tol=1e-8, precision="fp32_i
             item = q.get()
             if item is None:
                 break
-            r, b = item
+            r, b, kappa = item
             wait = r["t_arrival"] - (time.perf_counter() - t0)
             while wait > 0:
                 for d in srv.poll():
                     results.append(d)
                 time.sleep(min(wait, 0.001))
                 wait = r["t_arrival"] - (time.perf_counter() - t0)
-            rid = srv.submit(r["dim"], r["n"], r["levels"], b, tol, precision=precision,
-                             smoother=smoother)
+            rid = srv.submit(r["dim"], r["n"], r["levels"], b, tol, kappa=kappa,
+                             precision=precision, smoother=smoother)
             dofs[rid] = (r["n"] + 1) ** r["dim"]
             for d in srv.poll():
                 results.append(d)
@@ -96,5 +97,8 @@ def run_trace(trace, hbm_budget_bytes, max_slots=64, tol=1e-8, precision="fp32_i
         "mean_cycles": round(float(iters.mean()), 2) if len(iters) else None,
         "tol": tol,
         "precision": precision,
+        "kappa_requests": int(sum(1 for r in trace if r.get("kappa"))),
+        "failed_status": {st: sum(1 for d in failed if d["status"] == st)
+                          for st in sorted({d["status"] for d in failed})},
     }
     return out

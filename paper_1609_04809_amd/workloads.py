@@ -220,17 +220,24 @@ def serve_levels(dim, n):
     return lv
 
 
-def serving_trace(num=2000, rate=200.0, seed=0, burst=False):
+def serving_trace(num=2000, rate=200.0, seed=0, burst=False, kappa_frac=0.0):
     """Request trace: Poisson arrivals at ``rate`` per second.
 
     Each request is 2D or 3D with probability 1/2, with a mesh size drawn
     uniformly from the sizes of its dimension, and a seed for its
     U[-1, 1] right-hand side.  ``burst`` puts every arrival at t = 0.
-    Returns a list of dicts (t_arrival, dim, n, levels, seed).
+    With ``kappa_frac`` > 0, that fraction of the 3D requests (drawn from
+    a generator of their own, so the rest of the trace is unchanged) solve
+    the variable-coefficient problem of the 192^3 workload, kappa = exp(g),
+    g ~ N(0, 1) per cell from the request's seed.  (In 2D the rediscretised
+    coarse operators of such coefficient fields make the cycle iteration
+    diverge for some fields at n >= 256, in the CPU oracle as on the GPU.)
+    Returns a list of dicts (t_arrival, dim, n, levels, seed, kappa).
     """
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / rate, num)
     t = np.cumsum(gaps) - gaps[0]
+    kap = np.random.default_rng(seed + 7919).random(num) < kappa_frac
     out = []
     for i in range(num):
         dim = 2 if rng.random() < 0.5 else 3
@@ -238,5 +245,5 @@ def serving_trace(num=2000, rate=200.0, seed=0, burst=False):
         n = int(sizes[rng.integers(len(sizes))])
         out.append(dict(id=i, t_arrival=0.0 if burst else float(t[i]),
                         dim=dim, n=n, levels=serve_levels(dim, n),
-                        seed=int(1000 + i)))
+                        seed=int(1000 + i), kappa=bool(kap[i]) and dim == 3))
     return out
