@@ -5,44 +5,16 @@
 // owns ROWS consecutive rows, reads their values and column indices
 // contiguously (coalesced), multiplies by the gathered x and stages the
 // products in LDS; NTH / ROWS threads then sum each row in a fixed order.
-#include <cstdlib>
-
 #include "mg_internal.h"
 
 namespace mg {
 
 namespace {
 
-constexpr int CSR_MAX_ROW = 27;           // 3^dim entries at most
-constexpr int CSR_MIN_ROWS = 16;          // smallest rows-per-block variant
-
-// Launch variants of the row kernel (MG_CSR_VARIANT picks one; 0 is the
-// default): rows per block, threads, whether the matrix is read with
-// non-temporal loads (it is streamed once per sweep, so it need not stay in
-// the caches that hold x), XCD-contiguous block order, and 16-byte loads of
-// groups of 4 nonzeros (WIDE).
-struct CsrVariant {
-  int rows;
-  int threads;
-  bool nt;
-  bool remap;
-  bool wide;
-};
-constexpr CsrVariant kCsrVariants[] = {
-    {64, 256, false, false, true},  {64, 256, false, false, false}, {64, 256, false, true, false},
-    {32, 256, false, true, false},  {128, 256, false, true, false}, {64, 256, true, true, false},
-    {16, 64, false, true, false},   {32, 128, false, true, false},  {128, 512, false, false, true},
-    {32, 64, false, false, true}};
-constexpr int kNumCsrVariants = sizeof(kCsrVariants) / sizeof(kCsrVariants[0]);
-
-int csr_variant() {
-  static int v = [] {
-    const char* e = getenv("MG_CSR_VARIANT");
-    int k = e ? atoi(e) : 0;
-    return (k >= 0 && k < kNumCsrVariants) ? k : 0;
-  }();
-  return v;
-}
+constexpr int CSR_MAX_ROW = 27;  // 3^dim entries at most
+// Row kernel launch shape: rows per block and threads per block.
+constexpr int CSR_ROWS = 64;
+constexpr int CSR_NTH = 256;
 
 // Sum of v over the NTH threads of a block; result valid in thread 0.
 // Wave-level butterfly, then the wave sums in a fixed order.
@@ -67,12 +39,6 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <bool NT, typename V>
-__device__ __forceinline__ V ld_stream(const V* p) {
-  if (NT) return __builtin_nontemporal_load(p);
-  return *p;
-}
-
 // MODE 0: out = b - A x (residual) with per-block partial sums of out^2.
 // MODE 1: damped Jacobi update of rows [r_begin, r_end).
 // MODE 2: red-black update of the rows of one colour [r_begin, r_end); the
@@ -84,33 +50,30 @@ __device__ __forceinline__ V ld_stream(const V* p) {
 // MODE 6: Gauss-Seidel update of the rows of one colour [r_begin, r_end) in
 //         place (out == xin): no row of the colour reads another's unknown.
 // ZERO: x = 0 (x is not read).
-// Phase 1 issues all column and value loads of a thread before any gather,
-// so that about 2 * PER loads per thread are in flight.  The loads carry no
-// branches: a thread past the block's last nonzero re-reads that nonzero
-// and writes its product to a slot beyond the rows (the LDS array has
-// PER * NTH slots), so all loads of a phase are issued before the
-// first wait.
-// WIDE: each thread takes groups of 4 consecutive nonzeros starting at the
-// block's first nonzero rounded down to a multiple of 4, with one 16-byte
-// load of the columns and 16-byte loads of the values (the arrays are
-// 256-byte aligned and padded by kCsrPad valid entries), so the matrix
-// stream takes fewer load instructions; products of nonzeros outside the
-// block's range land in LDS slots that no row sums.
-template <typename T, int MODE, bool ZERO, int ROWS, bool NT, bool REMAP, int NTH, bool WIDE>
-__global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end,
-                                                          const T* __restrict__ xin,
-                                                          const T* __restrict__ b,
-                                                          T* __restrict__ out, T omega,
-                                                          double* __restrict__ partials) {
+// A block of CSR_NTH threads owns CSR_ROWS consecutive rows.  Each thread
+// takes groups of 4 consecutive nonzeros starting at the block's first
+// nonzero rounded down to a multiple of 4, with one 16-byte load of the
+// columns and 16-byte loads of the values (the arrays are 256-byte aligned
+// and padded by kCsrPad valid entries), so the matrix stream takes few load
+// instructions; products of nonzeros outside the block's range land in LDS
+// slots that no row sums.  The loads carry no branches: a thread past the
+// block's last group re-reads that group, so all column and value loads of
+// a thread are issued before the first gather waits.
+template <typename T, int MODE, bool ZERO>
+__global__ __launch_bounds__(CSR_NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r_end,
+                                                      const T* __restrict__ xin,
+                                                      const T* __restrict__ b,
+                                                      T* __restrict__ out, T omega,
+                                                      double* __restrict__ partials) {
+  constexpr int ROWS = CSR_ROWS, NTH = CSR_NTH;
   constexpr int MAXNNZ = ROWS * CSR_MAX_ROW;
-  constexpr int PER = (MAXNNZ + NTH - 1) / NTH;
-  constexpr int PG = (MAXNNZ + 3 + 4 * NTH - 1) / (4 * NTH);  // WIDE: groups per thread
-  constexpr int SLOTS = WIDE ? 4 * PG * NTH + 3 : PER * NTH;
-  constexpr int SOFF = WIDE ? 3 : 0;  // slot of the block's first nonzero
+  constexpr int PG = (MAXNNZ + 3 + 4 * NTH - 1) / (4 * NTH);  // groups per thread
+  constexpr int SLOTS = 4 * PG * NTH + 3;
+  constexpr int SOFF = 3;  // slot of the block's first nonzero
   constexpr int TPR = NTH / ROWS;  // threads summing one row
   __shared__ T prod[SLOTS];
   const int tid = threadIdx.x;
-  const int blk = REMAP ? xcd_remap(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int blk = (int)blockIdx.x;
   const int r0 = r_begin + blk * ROWS;
   const int nr = min(ROWS, r_end - r0);
   // The block's nonzero range comes from two uniform (scalar) loads, so the
@@ -139,7 +102,7 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
     xr = xin[node + 1];  // interior node: both neighbours lie in the grid
     xl = xin[node - 1];
   }
-  if (!ZERO && WIDE) {
+  if (!ZERO) {
     const int e0 = base & ~3;
     const int ng = (base + last + 1 - e0 + 3) >> 2;
     i32x4 c4[PG];
@@ -147,16 +110,16 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
 #pragma unroll
     for (int q = 0; q < PG; ++q) {
       const int g = min(tid + q * NTH, ng - 1);
-      c4[q] = ld_stream<NT>(reinterpret_cast<const i32x4*>(A.col + e0 + 4 * g));
+      c4[q] = *reinterpret_cast<const i32x4*>(A.col + e0 + 4 * g);
       if constexpr (sizeof(T) == 8) {
         const f64x2* vp = reinterpret_cast<const f64x2*>(A.val + e0 + 4 * g);
-        const f64x2 lo = ld_stream<NT>(vp), hi = ld_stream<NT>(vp + 1);
+        const f64x2 lo = vp[0], hi = vp[1];
         v4[q][0] = lo.x;
         v4[q][1] = lo.y;
         v4[q][2] = hi.x;
         v4[q][3] = hi.y;
       } else {
-        const f32x4 f = ld_stream<NT>(reinterpret_cast<const f32x4*>(A.val + e0 + 4 * g));
+        const f32x4 f = *reinterpret_cast<const f32x4*>(A.val + e0 + 4 * g);
         v4[q][0] = f.x;
         v4[q][1] = f.y;
         v4[q][2] = f.z;
@@ -176,20 +139,6 @@ __global__ __launch_bounds__(NTH) void k_csr_rows(CsrOp<T> A, int r_begin, int r
     for (int q = 0; q < PG; ++q)
 #pragma unroll
       for (int i = 0; i < 4; ++i) prod[so + 4 * q * NTH + i] = v4[q][i] * xg[q][i];
-  } else if (!ZERO) {
-    int cl[PER];
-    T vl[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-      const int e = min(tid + q * NTH, last);
-      cl[q] = ld_stream<NT>(A.col + base + e);
-      vl[q] = ld_stream<NT>(A.val + base + e);
-    }
-    T xg[PER];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) xg[q] = xin[cl[q]];
-#pragma unroll
-    for (int q = 0; q < PER; ++q) prod[tid + q * NTH] = vl[q] * xg[q];
   }
   __syncthreads();
   T s = T(0);
@@ -293,40 +242,23 @@ __global__ void k_csr_build(Geo g, const double* __restrict__ kappa, double s_el
 
 inline int cdiv_i(long a, long b) { return (int)((a + b - 1) / b); }
 
-template <typename T, int MODE, int ROWS, bool NT, bool REMAP, int NTH = 256, bool WIDE = false>
-void launch_rows_v(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
-                   double* partials, hipStream_t s) {
-  const int nb = cdiv_i(re - rb, ROWS);
-  if (nb == 0) return;
-  if (xin == nullptr)
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, true, ROWS, NT, REMAP, NTH, WIDE>), dim3(nb),
-                       dim3(NTH), 0, s, A, rb, re, xin, b, out, omega, partials);
-  else
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, false, ROWS, NT, REMAP, NTH, WIDE>), dim3(nb),
-                       dim3(NTH), 0, s, A, rb, re, xin, b, out, omega, partials);
-}
-
 template <typename T, int MODE>
 void launch_rows(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T* out, T omega,
                  double* partials, hipStream_t s) {
-  switch (csr_variant()) {
-    case 1: launch_rows_v<T, MODE, 64, false, false>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 2: launch_rows_v<T, MODE, 64, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 3: launch_rows_v<T, MODE, 32, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 4: launch_rows_v<T, MODE, 128, false, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 5: launch_rows_v<T, MODE, 64, true, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 6: launch_rows_v<T, MODE, 16, false, true, 64>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 7: launch_rows_v<T, MODE, 32, false, true, 128>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 8: launch_rows_v<T, MODE, 128, false, false, 512, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    case 9: launch_rows_v<T, MODE, 32, false, false, 64, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-    default: launch_rows_v<T, MODE, 64, false, false, 256, true>(A, rb, re, xin, b, out, omega, partials, s); break;
-  }
+  const int nb = cdiv_i(re - rb, CSR_ROWS);
+  if (nb == 0) return;
+  if (xin == nullptr)
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, true>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
+                       xin, b, out, omega, partials);
+  else
+    hipLaunchKernelGGL((k_csr_rows<T, MODE, false>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
+                       xin, b, out, omega, partials);
 }
 
 }  // namespace
 
-long csr_residual_blocks(int rows) { return cdiv_i(rows, kCsrVariants[csr_variant()].rows); }
-long csr_residual_blocks_max(int rows) { return cdiv_i(rows, CSR_MIN_ROWS); }
+long csr_residual_blocks(int rows) { return cdiv_i(rows, CSR_ROWS); }
+long csr_residual_blocks_max(int rows) { return cdiv_i(rows, CSR_ROWS); }
 
 template <typename T>
 void launch_csr_build(const Geo& g, const double* kappa, double s_elem, double s_mass, int rows,

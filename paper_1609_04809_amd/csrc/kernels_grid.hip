@@ -464,12 +464,17 @@ template <> struct Vec2<float> { using type = float2; };
 // 32 planes from 255 up (16 cost 2-3% on the 256^3 and 512^3 solves, 24
 // leaves an unbalanced last chunk) and 24 at 191; FP32 levels 32 from 511,
 // 16 at 255 and 12 at 191; every kind 4, 2 and 1 at 127, 63 and 31.
+// (Builds with MG_TUNING_KNOBS defined read MG_SWEEP3_KZ, MG_SWEEP3_REMAP
+// and MG_PROLONG_PZ from the environment to override the launch shapes,
+// for sweeps of them; the library as built here does not.)
 inline int sweep3_kz(int m, int elem) {
+#ifdef MG_TUNING_KNOBS
   static const int forced = [] {
     const char* e = getenv("MG_SWEEP3_KZ");
     return e ? atoi(e) : 0;
   }();
   if (forced > 0) return forced;
+#endif
   if (m >= 255) return elem == 8 || m >= 511 ? 32 : 16;
   if (m >= 191) return elem == 8 ? 24 : 12;
   return m >= 127 ? 4 : (m >= 63 ? 2 : 1);
@@ -2053,13 +2058,18 @@ inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc, int elem) {
   return dim3(cdiv(m, SW_TX), cdiv(m, SW_TY), (unsigned)(*nzc * count));
 }
 
-// Whether sweep3 launches map tiles to XCDs (MG_SWEEP3_REMAP=0 turns it off).
+// Whether sweep3 launches map tiles to XCDs (always, unless a tuning build
+// is told otherwise by MG_SWEEP3_REMAP=0).
 inline int sweep3_remap() {
+#ifdef MG_TUNING_KNOBS
   static const int v = [] {
     const char* e = getenv("MG_SWEEP3_REMAP");
     return e ? (atoi(e) != 0) : 1;
   }();
   return v;
+#else
+  return 1;
+#endif
 }
 
 template <typename T, int K, int MODE, bool ZERO, bool NORM, int XL = 0>
@@ -2407,15 +2417,17 @@ void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s
 }
 
 // Fine planes per thread of the z-marching 3D prolongation: 1 (one thread
-// per node), 2, 4 or 8.  MG_PROLONG_PZ overrides it for launch-shape sweeps.
+// per node), 2, 4 or 8.  (A tuning build reads MG_PROLONG_PZ.)
 int prolong_pz(const Geo& gf) {
+  if (gf.dim != 3) return 1;
+#ifdef MG_TUNING_KNOBS
   static const int env = [] {
     const char* v = std::getenv("MG_PROLONG_PZ");
     const int z = v ? std::atoi(v) : 0;
     return z == 1 || z == 2 || z == 4 || z == 8 ? z : 0;
   }();
-  if (gf.dim != 3) return 1;
   if (env > 0) return env;
+#endif
   const int m = gf.n - 1;
   return m >= 191 ? 8 : m >= 95 ? 4 : m >= 47 ? 2 : 1;
 }

@@ -360,12 +360,7 @@ mg_status build_csr(mg_ctx* c, int l, hipStream_t s) {
   rowptr[0] = 0;
   int idx = 0;
   auto cnt = [&](int i) { return 1 + (i > 1) + (i < n - 1); };
-  static const int tile = [] {  // MG_CSR_TILE overrides the tile edge
-    const char* e = getenv("MG_CSR_TILE");
-    const int t = e ? atoi(e) : 0;
-    return t > 0 ? t : kCsrTile;
-  }();
-  const int T = dim == 3 ? tile : n;
+  const int T = dim == 3 ? kCsrTile : n;
   const int kmin = dim == 3 ? 1 : 0, kmax = dim == 3 ? n - 1 : 0;
   // two colours (red-black, sum of coordinates mod 2) or, for multicolour
   // Gauss-Seidel, the 2^dim colours of gs_colour
