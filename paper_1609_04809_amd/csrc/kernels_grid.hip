@@ -11,6 +11,7 @@
 // Thread layout of the node kernels: a block of 64 x 4 threads covers 64
 // consecutive x and 4 consecutive y of one z plane of interior nodes, so one
 // wavefront (64 lanes) reads 64 consecutive values of a grid row.
+#include <algorithm>
 #include <cstdlib>
 #include <type_traits>
 
@@ -484,27 +485,32 @@ inline int sweep3_kz(int m, int elem) {
 // (Item::e) is prolongated and added to x as x is staged, so the launch
 // smooths x + P e -- the prolongation step fused into the first
 // post-smoothing step, bitwise as k_prolong_add followed by the sweep.
-// XL (red-black half-sweeps only): layout of the iterate, for a run of
-// half-sweeps on a level with even n whose iterate is kept colour-split (the
-// even-index nodes, which are the red ones, at p / 2 of one half, the odd
-// ones at p / 2 of another; Item::a / Item::a2 are the halves read,
-// Item::c the half written).  0: natural in and out.  1: natural in, split
-// out -- the updated colour to Item::c, the other colour copied to
-// Item::c2.  2: split in and out, only the updated colour written.  3: split
-// in, natural out (both colours).  The arithmetic per node is the same in
-// every layout.
+// XL: layout of the iterate on a level with even n whose iterate is kept
+// colour-split (the even-index nodes, which are the red ones, at p / 2 of
+// one half, the odd ones at p / 2 of another; Item::a / Item::a2 are the
+// halves read, Item::c the half written).  0: natural in and out.  1:
+// natural in, split out -- the updated colour to Item::c, the other colour
+// to Item::c2.  2: split in and out, only the updated colour written (a
+// residual reads x split and writes r natural).  3: split in, natural out
+// (both colours).  4: split in and out, both halves written (Item::c the
+// updated colour's, Item::c2 the other's; with the fused prolongation,
+// whose correction changes every node).  The arithmetic per node is the
+// same in every layout.
 template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false, int XL = 0>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
                                                 int nzc, int remap, Batch B) {
   using V2 = typename Vec2<T>::type;
   constexpr bool HEAD = MODE == SW_HEAD_RB0 || MODE == SW_HEAD_JAC;
   static_assert(XL == 0 || ((MODE == SM_RB0 || MODE == SM_RB1) && !NORM) ||
-                    (MODE == SW_HEAD_RB0 && XL == 1),
-                "split iterates are for red-black half-sweeps");
-  static_assert(!PRO || XL <= 1, "the prolongation reads a natural iterate");
-  static_assert(!(ZERO && (XL == 2 || XL == 3)), "x = 0 is read in no layout");
-  constexpr bool XIN = XL == 2 || XL == 3;   // x read colour-split
-  constexpr bool XOUT = XL == 1 || XL == 2;  // updated unknowns written colour-split
+                    (MODE == SW_HEAD_RB0 && (XL == 1 || XL == 2)) ||
+                    (MODE == SW_RESID && XL == 2),
+                "split iterates are for red-black half-sweeps, heads and residuals");
+  static_assert(!PRO || XL <= 1 || XL == 4, "the prolongation writes both colours");
+  static_assert(XL != 4 || PRO, "both halves of a split iterate change only with a prolongation");
+  static_assert(!(ZERO && (XL == 2 || XL == 3 || XL == 4)), "x = 0 is read in no layout");
+  constexpr bool XIN = XL == 2 || XL == 3 || XL == 4;         // x read colour-split
+  constexpr bool XOUT = XL == 1 || XL == 2 || XL == 4;        // updated unknowns written split
+  constexpr bool XBOTH = XL == 1 || XL == 4;                  // the other colour to Item::c2
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
@@ -526,7 +532,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   const T* __restrict__ xodd = XIN ? (const T*)I.a2 : nullptr;
   const T* __restrict__ b = (const T*)I.b;
   T* __restrict__ out = (T*)I.c;  // natural, or the updated colour's half (XOUT)
-  T* __restrict__ out2 = XL == 1 ? (T*)I.c2 : nullptr;
+  T* __restrict__ out2 = XBOTH ? (T*)I.c2 : nullptr;
   const T* __restrict__ kap = (const T*)I.kappa;
   const int i0 = 1 + bx * SW_TX, j0 = 1 + by * SW_TY, k0 = 1 + zc * kz;
   const int k1 = min(k0 + kz - 1, m);
@@ -633,8 +639,8 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       const int e = tid + 256 * q;
       if (e < SW_LX * SW_LY) {
         if (PRO) {
-          const int r = e / SW_LX, c = e - r * SW_LX;
-          dst[e] = xpf[q] + pe(i0 - 1 + c, j0 - 1 + r, min(z, n));
+          const int r = e / SW_LX, c = xcol(e - r * SW_LX);
+          dst[r * SW_LX + c] = xpf[q] + pe(i0 - 1 + c, j0 - 1 + r, min(z, n));
         } else if (XIN) {
           const int r = e / SW_LX;
           dst[r * SW_LX + xcol(e - r * SW_LX)] = xpf[q];
@@ -733,7 +739,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   };
   auto store_oth = [&](int k, int u, T v) {
     const long p = i + u + j * sy + (long)k * sz;
-    if (XL == 1)
+    if (XBOTH)
       out2[p >> 1] = v;
     else if (!XOUT)
       out[p] = v;
@@ -1222,6 +1228,17 @@ __global__ void k_copy(const T* __restrict__ a, T* __restrict__ b, long count) {
   const bool inside = (i <= m) && (j <= m);                              \
   const long p = i + j * (G).sy + (long)k * (G).sz;                      \
   const Item& I = B.it[item];
+
+// u[p] = the colour-split vector's entry of node p, every node.
+template <typename T>
+__global__ __launch_bounds__(256) void k_unsplit(long nodes, Batch B) {
+  const Item& I = B.it[blockIdx.y];
+  const T* __restrict__ ev = (const T*)I.a;
+  const T* __restrict__ od = (const T*)I.a2;
+  T* __restrict__ u = (T*)I.c;
+  for (long p = blockIdx.x * 256L + threadIdx.x; p < nodes; p += 256L * gridDim.x)
+    u[p] = ((p & 1) ? od : ev)[p >> 1];
+}
 
 template <typename T, int DIM, int KIND, bool NORM>
 __global__ __launch_bounds__(256) void k_residual(Geo g, StencilParams<T> op, Batch B) {
@@ -2132,7 +2149,19 @@ inline void with_kind3(int kind, F f) {
 
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
-                     hipStream_t s) {
+                     hipStream_t s, int xl) {
+  if (xl == XL_SPLIT) {
+    // (split iterates exist on k_sweep3 levels of the constant-coefficient
+    // and mass-shifted kinds)
+    if (op.kind == OP_MASS) {
+      if (norm) launch_sweep3<T, OP_MASS, SW_RESID, false, true, XL_SPLIT>(g, op, T(0), B, s);
+      else launch_sweep3<T, OP_MASS, SW_RESID, false, false, XL_SPLIT>(g, op, T(0), B, s);
+    } else {
+      if (norm) launch_sweep3<T, OP_CONST, SW_RESID, false, true, XL_SPLIT>(g, op, T(0), B, s);
+      else launch_sweep3<T, OP_CONST, SW_RESID, false, false, XL_SPLIT>(g, op, T(0), B, s);
+    }
+    return;
+  }
   if (use_sweep3(g)) {
     with_kind3(op.kind, [&](auto k) {
       constexpr int K = decltype(k)::value;
@@ -2254,17 +2283,22 @@ void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
   const dim3 bl(64, SW_TY);
   const int rm = sweep3_remap();
-  if (xl == XL_TO_SPLIT) {
+  if (xl == XL_TO_SPLIT || xl == XL_SPLIT_BOTH) {
     // (red-black on split-iterate levels: constant-coefficient and
-    // mass-shifted kinds)
-#define L_SPX(K, M)                                                                        \
-  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true, XL_TO_SPLIT>), gr, bl, 0, s, g, op, \
-                     omega, kz, nzc, rm, B)
+    // mass-shifted kinds; the iterate read natural or split)
+#define L_SPX(K, M, X)                                                                     \
+  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true, X>), gr, bl, 0, s, g, op, omega, kz, \
+                     nzc, rm, B)
+#define L_SPX_X(K, M)                                                      \
+  do {                                                                     \
+    if (xl == XL_TO_SPLIT) L_SPX(K, M, XL_TO_SPLIT); else L_SPX(K, M, XL_SPLIT_BOTH); \
+  } while (0)
     if (op.kind == OP_MASS) {
-      if (kind == SM_RB0) L_SPX(OP_MASS, SM_RB0); else L_SPX(OP_MASS, SM_RB1);
+      if (kind == SM_RB0) L_SPX_X(OP_MASS, SM_RB0); else L_SPX_X(OP_MASS, SM_RB1);
     } else {
-      if (kind == SM_RB0) L_SPX(OP_CONST, SM_RB0); else L_SPX(OP_CONST, SM_RB1);
+      if (kind == SM_RB0) L_SPX_X(OP_CONST, SM_RB0); else L_SPX_X(OP_CONST, SM_RB1);
     }
+#undef L_SPX_X
 #undef L_SPX
     return;
   }
@@ -2316,13 +2350,20 @@ template <typename T>
 void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, const Batch& B,
                  hipStream_t s, int xl) {
   const bool jac = kind == SM_JACOBI;
-  if (xl == XL_TO_SPLIT) {
+  if (xl == XL_TO_SPLIT || xl == XL_SPLIT) {
     // (red-black heads on split-iterate levels: constant-coefficient and
-    // mass-shifted kinds)
-    if (op.kind == OP_MASS)
-      launch_sweep3<T, OP_MASS, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
-    else
-      launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
+    // mass-shifted kinds; the iterate read natural or split)
+    if (op.kind == OP_MASS) {
+      if (xl == XL_TO_SPLIT)
+        launch_sweep3<T, OP_MASS, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
+      else
+        launch_sweep3<T, OP_MASS, SW_HEAD_RB0, false, true, XL_SPLIT>(g, op, omega, B, s);
+    } else {
+      if (xl == XL_TO_SPLIT)
+        launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true, XL_TO_SPLIT>(g, op, omega, B, s);
+      else
+        launch_sweep3<T, OP_CONST, SW_HEAD_RB0, false, true, XL_SPLIT>(g, op, omega, B, s);
+    }
     return;
   }
   if (use_sweep3(g)) {
@@ -2540,6 +2581,12 @@ void launch_tail_solve(int dim, int kind, int lds_bytes, const Batch& B, double 
 #undef L_TSOLVE
 }
 
+template <typename T>
+void launch_unsplit(const Geo& g, const Batch& B, hipStream_t s) {
+  const unsigned bx = (unsigned)std::min<long>((g.nodes + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_unsplit<T>, dim3(bx, B.count), dim3(256), 0, s, g.nodes, B);
+}
+
 void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s) {
   const int nc = nf / 2;
   const long total = dim == 3 ? (long)nc * nc * nc : (long)nc * nc;
@@ -2564,7 +2611,8 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_fill<T>(T*, long, T, hipStream_t);                                   \
   template void launch_copy<T>(const T*, T*, long, hipStream_t);                            \
   template void launch_residual<T>(const Geo&, const StencilParams<T>&, bool, const Batch&, \
-                                   hipStream_t);                                            \
+                                   hipStream_t, int);                                       \
+  template void launch_unsplit<T>(const Geo&, const Batch&, hipStream_t);                   \
   template void launch_smooth_pair<T>(const Geo&, const StencilParams<T>&, int, bool,      \
                                       const Batch&, hipStream_t);                           \
   template void launch_smooth_prolong<T>(const Geo&, const StencilParams<T>&, int, T,       \

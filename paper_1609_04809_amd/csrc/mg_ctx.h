@@ -108,6 +108,15 @@ struct mg_ctx {
   bool natural = false;
   // mg_solve keeps a colour-split copy of the caller's FP64 b (level 0)
   bool b0_split = false;
+  // FP64 mg_solve with head fusion on a split-iterate finest level keeps
+  // the finest iterate colour-split from cycle to cycle (s0on): s0at[h] is
+  // the split buffer holding the even (h = 0) / odd (h = 1) half of the
+  // current iterate, s0u where the last cycle's result lives (the head of
+  // the next cycle writes the new even half elsewhere); the caller's u is
+  // written from the halves once, after the last cycle
+  bool s0on = false;
+  int s0at[2] = {0, 0};
+  int s0u[2] = {0, 0};
   std::vector<mg::Level> lv;
   char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -128,11 +137,14 @@ struct mg_ctx {
   // one cached graph per iteration kind (plain, first fused, steady fused,
   // first CG, steady CG), valid for the (u, b) it was captured with
   static constexpr int kIterKinds = 5;
-  // two cached graphs per iteration kind, keyed by the (u, b) buffers, so
-  // that solves alternating between two solution buffers replay both
-  static constexpr int kGraphSlots = 2;
+  // four cached graphs per iteration kind, keyed by the (u, b) buffers and
+  // the split state the iteration starts from (a split finest iterate
+  // alternates between two states), so that solves alternating between two
+  // solution buffers replay their graphs
+  static constexpr int kGraphSlots = 4;
   hipGraphExec_t gexec[kIterKinds][kGraphSlots] = {};
-  const void* gkey[kIterKinds][kGraphSlots][2] = {};
+  const void* gkey[kIterKinds][kGraphSlots][3] = {};
+  int gstate[kIterKinds][kGraphSlots][2] = {};  // s0at, s0u after the iteration (codes)
   int glast[kIterKinds] = {};  // most recently used slot
   // profiling
   int prof_kernel = -1;

@@ -205,9 +205,15 @@ long norm2_blocks(const Geo& g);
 
 // r = b - A x (+ per-block partial sums of r^2 when `norm`):
 //   a = x, b = b, c = r, kappa, partials.
+// xl = XL_SPLIT (k_sweep3 levels, constant-coefficient or mass-shifted):
+// x read colour-split, a = its even half, a2 = its odd half.
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
-                     hipStream_t s);
+                     hipStream_t s, int xl = 0);
+// u = the natural layout of a colour-split vector (every node; the halves'
+// boundary entries are 0):  a = even half, a2 = odd half, c = u.
+template <typename T>
+void launch_unsplit(const Geo& g, const Batch& B, hipStream_t s);
 // One smoothing step (SmoothKind); a == nullptr means x = 0 (then for every
 // item):  a = x_in, b = b, c = x_out, kappa.  Gauss-Seidel colour steps
 // (kind >= SM_GS0) update c in place (a is ignored, zero is not allowed).
@@ -217,7 +223,13 @@ void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const 
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
                    const Batch& B, hipStream_t s, int xl = 0);
-enum XLayout { XL_NATURAL = 0, XL_TO_SPLIT = 1, XL_SPLIT = 2, XL_TO_NATURAL = 3 };
+enum XLayout {
+  XL_NATURAL = 0,
+  XL_TO_SPLIT = 1,     // natural in, both halves out
+  XL_SPLIT = 2,        // split in, the updated colour's half out
+  XL_TO_NATURAL = 3,   // split in, natural out
+  XL_SPLIT_BOTH = 4    // split in, both halves out (the fused prolongation)
+};
 // Whether k_sweep3 runs the level (3D, n >= 32), which is where split
 // iterates are possible.
 bool use_split_x(const Geo& g);

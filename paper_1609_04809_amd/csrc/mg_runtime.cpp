@@ -632,12 +632,19 @@ void emit_smooth(mg_ctx* c, const Sink& sink, int l, int kind, const T* xin, con
 
 template <typename T>
 void emit_residual(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* r,
-                   double* partials) {
+                   double* partials, const int* split = nullptr) {
   OpRec o = base_op<T>(c, c->csr ? OC_CSR_RESID : OC_RESID, l);
   o.sub = partials != nullptr;
   o.item.a = x;
   o.item.b = b;
   o.item.c = r;
+  if (split) {
+    // x colour-split: even half in buffer split[0], odd half in split[1]
+    Level& Lv = c->lv[l];
+    o.sub |= XL_SPLIT << 5;
+    o.item.a = Bufs<T>::xs(Lv, split[0]);
+    o.item.a2 = Bufs<T>::xs(Lv, split[1]) + (Lv.g.nodes + 1) / 2;
+  }
   o.item.partials = partials;
   if (c->csr) o.csr = Bufs<T>::csr(c->lv[l]);
   sink(o);
@@ -647,7 +654,7 @@ void emit_residual(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T
 // pre-smoothing step of the next cycle from x.
 template <typename T>
 void emit_head(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* xout,
-               double* partials) {
+               double* partials, bool in_split = false) {
   OpRec o = base_op<T>(c, c->csr ? OC_CSR_HEAD : OC_HEAD, l);
   o.sub = c->o.smoother == MG_SMOOTH_JACOBI ? SM_JACOBI : SM_RB0;
   o.item.a = x;
@@ -658,9 +665,21 @@ void emit_head(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T* xo
   if (split_iterate<T>(c, l)) {
     // the next cycle's smoothing run continues from the split halves
     Level& Lv = c->lv[l];
-    o.sub |= XL_TO_SPLIT << 5;
-    o.item.c = Bufs<T>::xs(Lv, 0);
-    o.item.c2 = Bufs<T>::xs(Lv, 0) + (Lv.g.nodes + 1) / 2;
+    const long lay = (Lv.g.nodes + 1) / 2;
+    if (in_split) {
+      // x split (halves in c->s0at); the updated colour 0 goes to the
+      // even half of the other buffer, x itself stays where it is
+      o.sub |= XL_SPLIT << 5;
+      o.item.a = Bufs<T>::xs(Lv, c->s0at[0]);
+      o.item.a2 = Bufs<T>::xs(Lv, c->s0at[1]) + lay;
+      c->s0at[0] = 1 - c->s0at[0];
+      o.item.c = Bufs<T>::xs(Lv, c->s0at[0]);
+    } else {
+      o.sub |= XL_TO_SPLIT << 5;
+      o.item.c = Bufs<T>::xs(Lv, 0);
+      o.item.c2 = Bufs<T>::xs(Lv, 0) + lay;
+      c->s0at[0] = c->s0at[1] = 0;
+    }
   }
   sink(o);
 }
@@ -687,28 +706,35 @@ void emit_fill(mg_ctx* c, const Sink& sink, int l, T* v) {
 
 // A run of red-black half-sweeps (steps) on a level with colour-split
 // iterate buffers xs[0..1]: the first step reads *cur (or x = 0) and writes
-// both halves of xs[0] (from_split: a fused step before the run -- the
-// head or the prolongation -- has already written them); each middle step reads the current even and odd
-// halves and writes only the updated colour's half, into the buffer that
-// does not hold that colour's current half; the last step writes the
-// natural iterate where the ping-pong of natural steps would have left it
-// (*cur after an even number of steps, else *spare).  Every node gets the
-// arithmetic of the natural steps, so the result is bitwise theirs; the
-// middle steps do not copy the other colour.
+// both halves of xs[0] (from_split: the iterate is already split -- a fused
+// step before the run, the head or the prolongation, has written it); each
+// middle step reads the current even and odd halves and writes only the
+// updated colour's half, into the buffer that does not hold that colour's
+// current half; the last step writes the natural iterate where the
+// ping-pong of natural steps would have left it (*cur after an even number
+// of steps, else *spare) -- or, with end_split, stays split like a middle
+// step.  state (in/out, or nullptr for a run of its own): the buffer
+// holding the even / odd half.  Every node gets the arithmetic of the
+// natural steps, so the result is bitwise theirs; the middle steps do not
+// copy the other colour.
 template <typename T>
 void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& steps, T** cur,
-                    T** spare, bool* zero, const T* b, bool from_split = false) {
+                    T** spare, bool* zero, const T* b, bool from_split = false,
+                    int* state = nullptr, bool end_split = false) {
   Level& Lv = c->lv[l];
   T* xs[2] = {Bufs<T>::xs(Lv, 0), Bufs<T>::xs(Lv, 1)};
   const long lay = (Lv.g.nodes + 1) / 2;  // start of the odd half
-  int at[2] = {0, 0};                      // buffer holding the even / odd half
+  int local[2] = {0, 0};
+  int* at = state ? state : local;         // buffer holding the even / odd half
+  if (steps.empty()) return;
   const size_t last = steps.size() - 1;
   const bool back = steps.size() % 2 == 0;
   for (size_t q = 0; q <= last; ++q) {
     const int col = steps[q] == SM_RB1 ? 1 : 0;  // parity of the updated nodes
     const bool first = q == 0 && !from_split;
     const bool z = first && *zero;
-    const int xl = first ? XL_TO_SPLIT : (q == last ? XL_TO_NATURAL : XL_SPLIT);
+    const int xl =
+        first ? XL_TO_SPLIT : (q == last && !end_split ? XL_TO_NATURAL : XL_SPLIT);
     OpRec o = base_op<T>(c, OC_SMOOTH, l);
     o.sub = steps[q] | ((z ? 1 : 0) << 4) | (xl << 5);
     o.item.b = b;
@@ -716,10 +742,11 @@ void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& 
       o.item.a = z ? nullptr : *cur;
       o.item.c = xs[0] + (col ? lay : 0);
       o.item.c2 = xs[0] + (col ? 0 : lay);
+      at[0] = at[1] = 0;
     } else {
       o.item.a = xs[at[0]];
       o.item.a2 = xs[at[1]] + lay;
-      if (q == last) {
+      if (xl == XL_TO_NATURAL) {
         o.item.c = back ? *cur : *spare;
       } else {
         const int dst = 1 - at[col];
@@ -729,7 +756,7 @@ void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& 
     }
     sink(o);
   }
-  if (!back) std::swap(*cur, *spare);
+  if (!end_split && !back) std::swap(*cur, *spare);
   *zero = false;
 }
 
@@ -741,7 +768,8 @@ void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& 
 // the same result).
 template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
-                  const T* b, bool skip = false, bool from_split = false) {
+                  const T* b, bool skip = false, bool from_split = false,
+                  int* state = nullptr) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
   if (c->o.smoother == MG_SMOOTH_GS) {
     // multicolour Gauss-Seidel: one in-place launch per colour, colours in
@@ -769,6 +797,11 @@ void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spa
   if (skip && !steps.empty()) steps.erase(steps.begin());
   const bool pairs = !c->csr && c->o.smoother == MG_SMOOTH_RBGS &&
                      pair_sweeps(c->lv[l].g) && (c->o.flags & MG_FLAG_PAIR);
+  if (state) {
+    // the iterate stays colour-split before and after the run
+    emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b, from_split, state, true);
+    return;
+  }
   if (from_split) {
     emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b, true);
     return;
@@ -805,16 +838,21 @@ inline int cycle_sub(int kind, int i) {
   return kind == MG_CYCLE_W ? MG_CYCLE_W : (kind == MG_CYCLE_F && i == 0 ? MG_CYCLE_F : MG_CYCLE_V);
 }
 
+bool fuse_prolongation(const mg_ctx* c, int l);
+
 // One cycle of the context's kind (Algorithm 1 for the V-cycle) for
 // A_0 x = b starting from x0 (or from 0 when x0_zero); the result is
 // written back to x0.  Levels >= 1 and the spare level-0 buffer are
 // internal.  Levels from c->tail0 on run in one workgroup per request (the
 // tail kernel follows the same schedule).  head_done: the first level-0
 // pre-smoothing step has already been applied to x0, its result is in
-// spare0.
+// spare0.  split0 (with c->s0on): the level-0 iterate stays colour-split
+// through the cycle -- it starts in the halves c->s0at (after the head, or
+// from 0), the residual and the fused prolongation read it split, and the
+// result stays in the halves (recorded in c->s0u); x0 is not written.
 template <typename T>
 void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero,
-                 bool head_done = false) {
+                 bool head_done = false, bool split0 = false) {
   const int L = c->L;
   std::vector<T*> cur(L), spare(L);
   std::vector<const T*> bb(L);
@@ -850,10 +888,12 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       return;
     }
     bool z = zero;
+    const bool s0 = l == 0 && split0;  // (head fusion: at least one pre-smoothing step)
     smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
-                    l == 0 && head_done && split_iterate<T>(c, 0));
+                    l == 0 && head_done && split_iterate<T>(c, 0), s0 ? c->s0at : nullptr);
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
-    emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr);
+    emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr,
+                     s0 ? c->s0at : nullptr);
     OpRec o = base_op<T>(c, OC_RESTRICT, l);
     o.item.lay = b_split_half(c, l + 1, Bufs<T>::prec);  // the coarse b it writes
     o.item.a = Bufs<T>::r(c->lv[l]);
@@ -864,13 +904,9 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     } else {
       for (int i = 0; i < cycle_subs(kind); ++i) visit(l + 1, cycle_sub(kind, i), i == 0);
     }
-    // on the large 3D constant-coefficient stencil levels the prolongation
-    // is fused into the first post-smoothing step (bitwise the same; with
-    // per-cell kappa the fused kernel's register and LDS use cost more than
-    // the pass it saves)
-    const bool fuse_pro = !c->csr && !c->kappa && c->o.nu_post >= 1 &&
-                          c->o.smoother != MG_SMOOTH_GS && pair_sweeps(c->lv[l].g) &&
-                          !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
+    // the prolongation fused into the first post-smoothing step where that
+    // pays (bitwise the same as the separate launches)
+    const bool fuse_pro = fuse_prolongation(c, l);
     bool nz = false;
     if (fuse_pro) {
       OpRec o = base_op<T>(c, OC_SMOOTH_PRO, l);
@@ -880,16 +916,32 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       o.item.b = bb[l];
       o.item.c = spare[l];
       const bool sx = split_iterate<T>(c, l);
-      if (sx) {
+      Level& Lv = c->lv[l];
+      const long lay = (Lv.g.nodes + 1) / 2;
+      if (s0) {
+        // x split in the halves c->s0at; x + P e changes every node, so
+        // both halves go to the other buffers (colour 1 updated)
+        o.sub |= XL_SPLIT_BOTH << 5;
+        o.item.a = Bufs<T>::xs(Lv, c->s0at[0]);
+        o.item.a2 = Bufs<T>::xs(Lv, c->s0at[1]) + lay;
+        c->s0at[0] = 1 - c->s0at[0];
+        c->s0at[1] = 1 - c->s0at[1];
+        o.item.c = Bufs<T>::xs(Lv, c->s0at[1]) + lay;
+        o.item.c2 = Bufs<T>::xs(Lv, c->s0at[0]);
+      } else if (sx) {
         // colour 1 updated into the odd half, colour 0 copied to the even one
-        Level& Lv = c->lv[l];
         o.sub |= XL_TO_SPLIT << 5;
-        o.item.c = Bufs<T>::xs(Lv, 0) + (Lv.g.nodes + 1) / 2;
+        o.item.c = Bufs<T>::xs(Lv, 0) + lay;
         o.item.c2 = Bufs<T>::xs(Lv, 0);
       }
       sink(o);
       std::swap(cur[l], spare[l]);
-      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true, sx);
+      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true, sx || s0,
+                      s0 ? c->s0at : nullptr);
+      if (s0) {
+        c->s0u[0] = c->s0at[0];
+        c->s0u[1] = c->s0at[1];
+      }
     } else {
       OpRec pr = base_op<T>(c, OC_PROLONG, l);
       pr.item.a = cur[l + 1];
@@ -899,7 +951,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     }
   };
   visit(0, c->o.cycle, x0_zero);
-  if (cur[0] != x0) {
+  if (!split0 && cur[0] != x0) {
     OpRec o = base_op<T>(c, OC_COPY, 0);
     o.count = c->lv[0].g.nodes;
     o.item.a = cur[0];
@@ -915,6 +967,23 @@ bool head_fusion(const mg_ctx* c) {
   return !c->ir && c->o.nu_pre >= 1 && c->L >= 2 && c->tail0 != 0 &&
          c->o.smoother != MG_SMOOTH_GS &&
          !(c->o.flags & MG_FLAG_NO_FUSE);
+}
+
+// Whether the prolongation into level l is fused into its first
+// post-smoothing step: large 3D constant-coefficient stencil levels (with
+// per-cell kappa the fused kernel's register and LDS use cost more than the
+// pass it saves).
+bool fuse_prolongation(const mg_ctx* c, int l) {
+  return !c->csr && !c->kappa && c->o.nu_post >= 1 && c->o.smoother != MG_SMOOTH_GS &&
+         pair_sweeps(c->lv[l].g) && !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
+}
+
+// Whether an FP64 solve with head fusion keeps the finest iterate
+// colour-split from cycle to cycle (see mg_ctx::s0on): the finest level has
+// split iterates, and both its fused steps (head, prolongation) are there
+// to read and write the halves.
+bool split_persist(const mg_ctx* c) {
+  return head_fusion(c) && split_iterate<double>(c, 0) && fuse_prolongation(c, 0);
 }
 
 // Iteration kinds: IT_PLAIN = V-cycle, then residual norm;  IT_FUSED_FIRST =
@@ -1015,8 +1084,15 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
     return;
   }
   if (kind != IT_PLAIN) {
-    emit_vcycle<double>(c, sink, u, L0.t64, b, false, kind == IT_FUSED);
-    emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
+    if (c->s0on) {
+      // the finest iterate stays split (the first cycle starts from 0)
+      emit_vcycle<double>(c, sink, u, L0.t64, b, kind == IT_FUSED_FIRST, kind == IT_FUSED,
+                          true);
+      emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials, true);
+    } else {
+      emit_vcycle<double>(c, sink, u, L0.t64, b, false, kind == IT_FUSED);
+      emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
+    }
     emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
     return;
   }
@@ -1136,7 +1212,7 @@ Sink launch_sink(mg_ctx* c, hipStream_t s) {
 void drop_graph(mg_ctx* c, int kind, int slot) {
   if (c->gexec[kind][slot]) hipGraphExecDestroy(c->gexec[kind][slot]);
   c->gexec[kind][slot] = nullptr;
-  c->gkey[kind][slot][0] = c->gkey[kind][slot][1] = nullptr;
+  c->gkey[kind][slot][0] = c->gkey[kind][slot][1] = c->gkey[kind][slot][2] = nullptr;
 }
 
 void drop_graphs(mg_ctx* c) {
@@ -1153,7 +1229,8 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s, in
     HIP_TRY(hipGetLastError());
     return MG_OK;
   }
-  const void* key[2] = {u, b};
+  const int scode = c->s0on ? 1 + c->s0at[0] + 2 * c->s0at[1] : 0;
+  const void* key[3] = {u, b, reinterpret_cast<const void*>((intptr_t)scode)};
   int slot = -1;
   for (int q = 0; q < mg_ctx::kGraphSlots; ++q)
     if (c->gexec[kind][q] && memcmp(key, c->gkey[kind][q], sizeof key) == 0) slot = q;
@@ -1178,9 +1255,16 @@ mg_status run_iteration(mg_ctx* c, double* u, const double* b, hipStream_t s, in
       return fail(MG_E_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(ie));
     }
     memcpy(c->gkey[kind][slot], key, sizeof key);
+    // the split state the iteration leaves (capturing emitted it)
+    c->gstate[kind][slot][0] = c->s0at[0] + 2 * c->s0at[1];
+    c->gstate[kind][slot][1] = c->s0u[0] + 2 * c->s0u[1];
   }
   c->glast[kind] = slot;
   HIP_TRY(hipGraphLaunch(c->gexec[kind][slot], s));
+  c->s0at[0] = c->gstate[kind][slot][0] & 1;
+  c->s0at[1] = c->gstate[kind][slot][0] >> 1;
+  c->s0u[0] = c->gstate[kind][slot][1] & 1;
+  c->s0u[1] = c->gstate[kind][slot][1] >> 1;
   return MG_OK;
 }
 
@@ -1205,9 +1289,11 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
   switch (o.code) {
     case OC_SMOOTH:
       launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, ((o.sub >> 4) & 1) != 0, (T)o.omega, B,
-                       s, (o.sub >> 5) & 3);
+                       s, (o.sub >> 5) & 7);
       break;
-    case OC_RESID: launch_residual<T>(o.g, params_of<T>(o), o.sub != 0, B, s); break;
+    case OC_RESID:
+      launch_residual<T>(o.g, params_of<T>(o), (o.sub & 1) != 0, B, s, (o.sub >> 5) & 7);
+      break;
     case OC_RESTRICT: launch_restrict<T>(o.g, o.gc, B, s); break;
     case OC_PROLONG: launch_prolong_add<T>(o.g, o.gc, B, s); break;
     case OC_COARSE: launch_coarse_solve<T>(o.g, o.m, B, s); break;
@@ -1225,14 +1311,14 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
                              (T*)it.c, it.partials, s);
       break;
     case OC_HEAD:
-      launch_head<T>(o.g, params_of<T>(o), o.sub & 15, (T)o.omega, B, s, (o.sub >> 5) & 3);
+      launch_head<T>(o.g, params_of<T>(o), o.sub & 15, (T)o.omega, B, s, (o.sub >> 5) & 7);
       break;
     case OC_SMOOTH2:
       launch_smooth_pair<T>(o.g, params_of<T>(o), o.sub & 15, (o.sub >> 4) != 0, B, s);
       break;
     case OC_SMOOTH_PRO:
       launch_smooth_prolong<T>(o.g, params_of<T>(o), o.sub & 15, (T)o.omega, B, s,
-                               (o.sub >> 5) & 3);
+                               (o.sub >> 5) & 7);
       break;
     case OC_APPLY_DOT: launch_apply_dot<T>(o.g, params_of<T>(o), B, s); break;
     case OC_CSR_APPLY_DOT:
@@ -1518,6 +1604,8 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
     return tail_solve_result(c->pinned, c->o.max_iter, tol, iters, hist);
   }
   const bool fuse = head_fusion(c);
+  c->s0on = fuse && !pcg && split_persist(c);
+  c->s0at[0] = c->s0at[1] = c->s0u[0] = c->s0u[1] = 0;
   const double* bc = b;  // b as the cycles read it
   if (c->b0_split) {
     // the level-0 right-hand side colour-split (each half-sweep then reads
@@ -1551,6 +1639,20 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
     if (hist) hist[0] = rho0;
     if (rho0 <= tol) return MG_OK;
   }
+  // a split finest iterate reaches u after the last cycle
+  auto finish = [&](mg_status result) -> mg_status {
+    if (c->s0on && *iters > 0) {
+      Level& L0 = c->lv[0];
+      Batch B{};
+      B.count = 1;
+      B.it[0].a = L0.xs64[c->s0u[0]];
+      B.it[0].a2 = L0.xs64[c->s0u[1]] + (L0.g.nodes + 1) / 2;
+      B.it[0].c = u;
+      launch_unsplit<double>(L0.g, B, s);
+      HIP_TRY(hipGetLastError());
+    }
+    return result;
+  };
   for (int k = 1; k <= c->o.max_iter; ++k) {
     const int kind = pcg ? (k == 1 ? IT_PCG_FIRST : IT_PCG)
                          : (!fuse ? IT_PLAIN : (k == 1 && !warm ? IT_FUSED_FIRST : IT_FUSED));
@@ -1564,10 +1666,10 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
     *iters = k;
     if (hist) hist[k] = rho;
     if (!std::isfinite(rho) || rho > 1e3)
-      return fail(MG_E_DIVERGED, "relative residual %g after %d cycles", rho, k);
-    if (rho <= tol) return MG_OK;
+      return finish(fail(MG_E_DIVERGED, "relative residual %g after %d cycles", rho, k));
+    if (rho <= tol) return finish(MG_OK);
   }
-  return fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, c->o.max_iter);
+  return finish(fail(MG_E_MAXIT, "no convergence to %g in %d cycles", tol, c->o.max_iter));
 }
 
 mg_status mg_cn_rhs(mg_ctx* c, const double* u, double* guess, const double* g0, double c0,

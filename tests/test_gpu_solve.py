@@ -408,3 +408,40 @@ def test_colour_split_iterates_agree_bitwise(prec, nu, sigma, cycle, flags):
             outs.append((k, hist, host_full(u)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_split_finest_iterate_across_cycles_agrees_bitwise():
+    """FP64 solves keep the finest iterate colour-split from cycle to cycle
+    (written to u once, after the last cycle): repeated solves into fresh
+    and reused buffers (replaying the graphs of both split states), a
+    solve stopped by max_iter, and a warm start agree bitwise with the
+    natural layout."""
+    torch = torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_SPLIT, FLAG_WARM, Solver
+    n, levels = 256, 8
+    b = dev_full(3, n, W.rhs_uniform(3, n, 27))
+    ref = {}
+    with Solver(3, n, levels, flags=FLAG_NO_SPLIT) as S:
+        ref["ok"] = S.solve(b, 1e-9)
+    with Solver(3, n, levels, flags=FLAG_NO_SPLIT, max_iter=3) as S:
+        ref["maxit"] = S.solve(b, 1e-14)
+    with Solver(3, n, levels) as S:
+        ua = torch.empty_like(b)
+        for q in range(3):                     # fresh, reused, reused
+            u = torch.empty_like(b) if q == 0 else ua
+            u, k, hist, st = S.solve(b, 1e-9, u=u)
+            assert st == "ok" and k == ref["ok"][1] and hist == ref["ok"][2]
+            assert torch.equal(u, ref["ok"][0])
+    with Solver(3, n, levels, max_iter=3) as S:
+        u, k, hist, st = S.solve(b, 1e-14)
+        assert st == "maxit" and k == 3 and hist == ref["maxit"][2]
+        assert torch.equal(u, ref["maxit"][0])
+    u0 = 0.5 * ref["ok"][0]
+    outs = []
+    for extra in (0, FLAG_NO_SPLIT):
+        with Solver(3, n, levels, flags=FLAG_WARM | extra) as S:
+            u, k, hist, st = S.solve(b, 1e-9, u=u0.clone())
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+
