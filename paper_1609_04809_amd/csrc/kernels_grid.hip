@@ -618,19 +618,41 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   };
   // the multilinear interpolant of e at staged fine node (gi, gj, z), in the
   // arithmetic of prolong_node
-  auto pe = [&](int gi, int gj, int z) -> T {
+  // The multilinear interpolant of e at the staged fine node of element q
+  // in plane z, in the arithmetic of prolong_node: the in-plane (x, y)
+  // interpolant of the coarse planes z/2 (even z), or (z-1)/2 and (z+1)/2
+  // (odd z, weight 1/2).  FP32 (IPREG): a coarse plane K serves the fine
+  // planes 2K-1, 2K and 2K+1, so each thread forms its in-plane interpolant
+  // once, when the plane first enters (ip_plane), and keeps it and the one
+  // before in registers (ipo, ipn), which takes the LDS reads and index
+  // arithmetic of the staging from about 3.4 to about 1.1 per element and
+  // plane.  FP64 recomputes it from LDS per plane: the registers of the
+  // cache would cost a quarter of the FP64 kernel's occupancy.
+  constexpr bool IPREG = PRO && sizeof(T) == 4;
+  auto ip_elem = [&](int q, int ss) -> T {
+    const int e = tid + 256 * q;
+    const int r = e / SW_LX, c = xcol(e - r * SW_LX);
+    const int gi = i0 - 1 + c, gj = j0 - 1 + r;
     const int a0 = (gi >> 1) - 64 * bx, a1 = ((gi + 1) >> 1) - 64 * bx;
     const int r0 = (gj >> 1) - 2 * by, r1 = ((gj + 1) >> 1) - 2 * by;
-    const int s0 = (z >> 1) % 3, s1 = ((z + 1) >> 1) % 3;
     const T wi = (gi & 1) ? T(0.5) : T(1), wj = (gj & 1) ? T(0.5) : T(1);
-    const T wk = (z & 1) ? T(0.5) : T(1);
-    auto line = [&](int rr, int ss) -> T {
+    auto line = [&](int rr) -> T {
       return (gi & 1) ? wi * (sc[ss][rr][a0] + sc[ss][rr][a1]) : sc[ss][rr][a0];
     };
-    auto plane = [&](int ss) -> T {
-      return (gj & 1) ? wj * (line(r0, ss) + line(r1, ss)) : line(r0, ss);
-    };
-    return (z & 1) ? wk * (plane(s0) + plane(s1)) : plane(s0);
+    return (gj & 1) ? wj * (line(r0) + line(r1)) : line(r0);
+  };
+  T ipo[IPREG ? NX : 1], ipn[IPREG ? NX : 1];
+  auto ip_plane = [&](int K) {
+#pragma unroll
+    for (int q = 0; q < NX; ++q) ipn[q] = ip_elem(q, K % 3);
+  };
+  auto pe = [&](int q, int z) -> T {
+    if constexpr (IPREG) {
+      return (z & 1) ? T(0.5) * (ipo[q] + ipn[q]) : ipn[q];
+    } else {
+      const int s0 = (z >> 1) % 3, s1 = ((z + 1) >> 1) % 3;
+      return (z & 1) ? T(0.5) * (ip_elem(q, s0) + ip_elem(q, s1)) : ip_elem(q, s0);
+    }
   };
   auto commit_x = [&](int s, int z) {
     T* dst = &sx[s][0][0];
@@ -640,7 +662,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       if (e < SW_LX * SW_LY) {
         if (PRO) {
           const int r = e / SW_LX, c = xcol(e - r * SW_LX);
-          dst[r * SW_LX + c] = xpf[q] + pe(i0 - 1 + c, j0 - 1 + r, min(z, n));
+          dst[r * SW_LX + c] = xpf[q] + pe(q, z);
         } else if (XIN) {
           const int r = e / SW_LX;
           dst[r * SW_LX + xcol(e - r * SW_LX)] = xpf[q];
@@ -823,11 +845,19 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     }
     prefetch_c(c0 + 3);
     __syncthreads();
+    if (IPREG) ip_plane((k0 - 1) >> 1);
   }
   for (int p = k0 - 1; p <= k1 + 1; ++p) {
     if (PRO && (p & 1) && ((p + 3) >> 1) > c0 + 2) {
       commit_c((p + 3) >> 1);
       prefetch_c(((p + 3) >> 1) + 1);
+    }
+    if (IPREG && (p & 1)) {
+      // fine plane p (odd) interpolates from coarse planes (p-1)/2, kept,
+      // and (p+1)/2, new (staged at least one step earlier)
+#pragma unroll
+      for (int q = 0; q < NX; ++q) ipo[q] = ipn[q];
+      ip_plane((p + 1) >> 1);
     }
     commit_x(p & 1, p);
     prefetch_x(p + 1);
