@@ -193,6 +193,17 @@ def roofline_stencil(S, w, bd, s):
                     "bytes_per_launch": int(per)}
         if key == "halfsweep":
             out[key]["traffic"] = measured_traffic(w.name)
+    if w.precision == "fp32_ir":
+        # the first and last FP32 steps of each refinement cycle (the scaled
+        # cast of the residual and the update of u fused in): timing only
+        from paper_1609_04809_amd.mg import PROF_SMOOTH_IR
+        S.profile(PROF_SMOOTH_IR, True)
+        S.solve(bd, w.tol)
+        launches, ms = S.profile_read()
+        S.profile(PROF_SMOOTH_IR, False)
+        if launches:
+            out["ir_fused_steps"] = {"launches": launches,
+                                     "avg_us": round(ms * 1e3 / launches, 2)}
     return out
 
 

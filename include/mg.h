@@ -341,7 +341,9 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
  *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps
- *              in one pass, 5 = prolongation fused into a smoothing step
+ *              in one pass, 5 = prolongation fused into a smoothing step,
+ *              6 = FP32 smoothing step of iterative refinement with the
+ *              scaled cast of the residual or the update of u fused in
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

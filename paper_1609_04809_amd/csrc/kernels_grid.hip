@@ -496,7 +496,20 @@ inline int sweep3_kz(int m, int elem) {
 // updated colour's, Item::c2 the other's; with the fused prolongation,
 // whose correction changes every node).  The arithmetic per node is the
 // same in every layout.
-template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false, int XL = 0>
+// IRU (FP32 smoothing steps that write a natural iterate): the step is the
+// last one of the FP32 correction cycle of iterative refinement, and instead
+// of the correction c it writes u + s c (u: the FP64 iterate, Item::c; s =
+// sqrt(*Item::scal)), in the arithmetic of k_ir_update -- the refinement
+// update fused into the step that produces c.  The step reads no u that
+// other blocks write, so the update can be in place.
+// CAST (FP32 smoothing from x = 0, the first step of the refinement cycle):
+// the step's right-hand side is float(r / s) of the FP64 residual r
+// (Item::e, natural layout; s = sqrt(*Item::scal)), in the arithmetic of
+// k_scale_cast; the step writes it to Item::b (in the layout Item::lay) for
+// the rest of the cycle as it uses it -- the scaled cast fused into the
+// first step that reads it.
+template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false, int XL = 0,
+          bool IRU = false, bool CAST = false>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
                                                 int nzc, int remap, Batch B) {
   using V2 = typename Vec2<T>::type;
@@ -511,6 +524,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   constexpr bool XIN = XL == 2 || XL == 3 || XL == 4;         // x read colour-split
   constexpr bool XOUT = XL == 1 || XL == 2 || XL == 4;        // updated unknowns written split
   constexpr bool XBOTH = XL == 1 || XL == 4;                  // the other colour to Item::c2
+  static_assert(!IRU || (sizeof(T) == 4 && !ZERO && !PRO && (XL == 0 || XL == 3) &&
+                         (MODE == SM_RB0 || MODE == SM_RB1 || MODE == SM_JACOBI)),
+                "the refinement update follows a natural-output FP32 smoothing step");
+  static_assert(!CAST || (sizeof(T) == 4 && ZERO && (XL == 0 || XL == 1) &&
+                          (MODE == SM_RB0 || MODE == SM_JACOBI)),
+                "the scaled cast feeds an FP32 first step from x = 0");
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
@@ -752,19 +771,30 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       for (int u = 0; u < 2; ++u) gpf[u] = ge[p + u];
     }
   };
-  auto store = [&](int k, int u, T v) { out[i + u + j * sy + (long)k * sz] = v; };
+  double* const uo = IRU ? (double*)I.c : nullptr;
+  const double sr = IRU ? sqrt(*I.scal) : 0.0;
+  auto put = [&](long p, T v) {
+    if constexpr (IRU)
+      uo[p] = uo[p] + sr * (double)v;
+    else
+      out[p] = v;
+  };
+  auto store = [&](int k, int u, T v) { put(i + u + j * sy + (long)k * sz, v); };
   // red-black: an updated unknown, and one of the other colour (its old
   // value, or 0 from x = 0), in the layout XL writes
   auto store_upd = [&](int k, int u, T v) {
     const long p = i + u + j * sy + (long)k * sz;
-    out[XOUT ? p >> 1 : p] = v;
+    if (XOUT)
+      out[p >> 1] = v;
+    else
+      put(p, v);
   };
   auto store_oth = [&](int k, int u, T v) {
     const long p = i + u + j * sy + (long)k * sz;
     if (XBOTH)
       out2[p >> 1] = v;
     else if (!XOUT)
-      out[p] = v;
+      put(p, v);
   };
   double sq = 0.0;
   T kwp[2][3];  // cell window of layer p-1
@@ -782,12 +812,22 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       __syncthreads();
       window_k((k0 - 1) & 1, kwp);
     }
+    const double* const r64 = CAST ? (const double*)I.e : nullptr;
+    const double rs = CAST ? sqrt(*I.scal) : 0.0;
+    T* const bw = CAST ? (T*)const_cast<void*>(I.b) : nullptr;
+    double rpf[2] = {0.0, 0.0};
     for (int k = k0; k <= k1; ++k) {
       if (KAP) {
         commit_k(k & 1);
         prefetch_k(k + 1);
       }
-      prefetch_b(k);
+      if constexpr (CAST) {
+        const long p = pb0 + (long)min(k, n) * sz;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) rpf[u] = r64[p + u];
+      } else {
+        prefetch_b(k);
+      }
       __syncthreads();
       T kwc[2][3];
       if (KAP) window_k(k & 1, kwc);
@@ -796,12 +836,17 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         const bool ok = u == 0 ? ok0 : ok1;
         const bool upd = MODE == SM_JACOBI || (((i + u + j + k) & 1) == colour);
         if (!ok) continue;
+        T bv = bpf[u];
+        if constexpr (CAST) {
+          bv = (T)(rpf[u] / rs);
+          bw[lay_idx(i + u + j * sy + (long)k * sz, blay)] = bv;
+        }
         T dg = op.wc;
         if (KAP) dg = op.s * T(4) * kappa_cell_sum<T>(kwp, kwc, u);
         if (MODE == SM_JACOBI)
-          store(k, u, omega * (bpf[u] / dg));
+          store(k, u, omega * (bv / dg));
         else if (upd)
-          store_upd(k, u, bpf[u] / dg);
+          store_upd(k, u, bv / dg);
         else
           store_oth(k, u, T(0));
       }
@@ -2119,14 +2164,16 @@ inline int sweep3_remap() {
 #endif
 }
 
-template <typename T, int K, int MODE, bool ZERO, bool NORM, int XL = 0>
+template <typename T, int K, int MODE, bool ZERO, bool NORM, int XL = 0, bool IRU = false,
+          bool CAST = false>
 void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batch& B,
                    hipStream_t s) {
   int kz, nzc;
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
-  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM, false, XL>), gr, dim3(64, SW_TY), 0, s, g,
-                     op, omega, kz, nzc, sweep3_remap(), B);
+  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM, false, XL, IRU, CAST>), gr,
+                     dim3(64, SW_TY), 0, s, g, op, omega, kz, nzc, sweep3_remap(), B);
 }
+
 }  // namespace
 
 long norm2_blocks(const Geo& g) {
@@ -2256,9 +2303,55 @@ static void launch_sweep3_split(const Geo& g, const StencilParams<T>& op, bool z
 
 bool use_split_x(const Geo& g) { return use_sweep3(g); }
 
+namespace {
+// The last FP32 smoothing step of a refinement cycle with the refinement
+// update fused (IRU): natural output (xl 0) or split input (xl 3).
+template <typename T>
+void launch_sweep3_iru(const Geo& g, const StencilParams<T>& op, int kind, T omega, int xl,
+                       const Batch& B, hipStream_t s) {
+  if constexpr (std::is_same<T, float>::value) {
+    with_kind3(op.kind, [&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      if (xl == XL_TO_NATURAL) {
+        if (kind == SM_RB0)
+          launch_sweep3<T, K, SM_RB0, false, false, XL_TO_NATURAL, true>(g, op, omega, B, s);
+        else
+          launch_sweep3<T, K, SM_RB1, false, false, XL_TO_NATURAL, true>(g, op, omega, B, s);
+      } else {
+        if (kind == SM_RB0)
+          launch_sweep3<T, K, SM_RB0, false, false, 0, true>(g, op, omega, B, s);
+        else if (kind == SM_RB1)
+          launch_sweep3<T, K, SM_RB1, false, false, 0, true>(g, op, omega, B, s);
+        else
+          launch_sweep3<T, K, SM_JACOBI, false, false, 0, true>(g, op, omega, B, s);
+      }
+    });
+  }
+}
+}  // namespace
+
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s, int xl) {
+                   const Batch& B, hipStream_t s, int xl, bool iru, bool cast) {
+  if (iru) {
+    launch_sweep3_iru<T>(g, op, kind, omega, xl, B, s);
+    return;
+  }
+  if (cast) {
+    if constexpr (std::is_same<T, float>::value) {
+      with_kind3(op.kind, [&](auto kc) {
+        constexpr int K = decltype(kc)::value;
+        if (xl == XL_TO_SPLIT) {
+          launch_sweep3<T, K, SM_RB0, true, false, XL_TO_SPLIT, false, true>(g, op, omega, B, s);
+        } else if (kind == SM_RB0) {
+          launch_sweep3<T, K, SM_RB0, true, false, 0, false, true>(g, op, omega, B, s);
+        } else {
+          launch_sweep3<T, K, SM_JACOBI, true, false, 0, false, true>(g, op, omega, B, s);
+        }
+      });
+    }
+    return;
+  }
   if (xl != XL_NATURAL) {
     // (the runtime splits iterates only for red-black on k_sweep3 levels
     // of the constant-coefficient and mass-shifted kinds)
@@ -2648,7 +2741,7 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_smooth_prolong<T>(const Geo&, const StencilParams<T>&, int, T,       \
                                          const Batch&, hipStream_t, int);                   \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
-                                 const Batch&, hipStream_t, int);                           \
+                                 const Batch&, hipStream_t, int, bool, bool);               \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \
                                hipStream_t, int);                                           \
   template void launch_apply_dot<T>(const Geo&, const StencilParams<T>&, const Batch&,      \

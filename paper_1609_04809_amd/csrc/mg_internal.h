@@ -220,9 +220,17 @@ void launch_unsplit(const Geo& g, const Batch& B, hipStream_t s);
 // xl (red-black on levels where use_split_x(g), XLayout): the iterate's
 // layout in and out -- split halves are a (even) / a2 (odd) when read, c
 // (the updated colour) and c2 (the other colour, XL_TO_SPLIT) when written.
+// iru (FP32, k_sweep3 levels, a step with natural output: xl 0 or
+// XL_TO_NATURAL, kind SM_JACOBI / SM_RB0 / SM_RB1): the step's result c is
+// not stored; instead u += sqrt(*scal) c with c = u (FP64), scal.
+// cast (FP32, k_sweep3 levels, a first step from x = 0, xl 0 or
+// XL_TO_SPLIT, kind SM_JACOBI / SM_RB0): the right-hand side is
+// float(r / sqrt(*scal)) of the FP64 residual e = r, written to b (in the
+// layout lay) as it is used.
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s, int xl = 0);
+                   const Batch& B, hipStream_t s, int xl = 0, bool iru = false,
+                   bool cast = false);
 enum XLayout {
   XL_NATURAL = 0,
   XL_TO_SPLIT = 1,     // natural in, both halves out

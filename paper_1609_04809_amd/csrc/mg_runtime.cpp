@@ -850,9 +850,19 @@ bool fuse_prolongation(const mg_ctx* c, int l);
 // through the cycle -- it starts in the halves c->s0at (after the head, or
 // from 0), the residual and the fused prolongation read it split, and the
 // result stays in the halves (recorded in c->s0u); x0 is not written.
+// iru_u (FP32 cycles of iterative refinement): where the level-0 post-smoothing
+// ends with a smoothing step that writes a natural iterate on a k_sweep3
+// level, that step adds sqrt(scal[0]) times its result to the FP64 iterate
+// iru_u instead of writing x0 (*iru_done is set then; x0 is not written).
+// cast_r (FP32 cycles of iterative refinement, x0_zero): b0 is
+// float(cast_r / sqrt(scal[0])), formed by the first level-0 smoothing step
+// where it is a first step from x = 0 on a k_sweep3 level, else by a
+// scaled-cast launch before the cycle.
 template <typename T>
 void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero,
-                 bool head_done = false, bool split0 = false) {
+                 bool head_done = false, bool split0 = false, double* iru_u = nullptr,
+                 bool* iru_done = nullptr, const double* cast_r = nullptr) {
+  if (iru_done) *iru_done = false;
   const int L = c->L;
   std::vector<T*> cur(L), spare(L);
   std::vector<const T*> bb(L);
@@ -868,8 +878,22 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
   if (head_done) std::swap(cur[0], spare[0]);
   // one visit of level l by a cycle of `kind`, its iterate starting at 0
   // when `zero`
+  // level-0 pre- and post-smoothing ops are collected first (see cast_r, iru_u)
+  std::vector<OpRec> pre0, post0;
+  const Sink collect0 = [&post0](const OpRec& o) { post0.push_back(o); };
+  const Sink collectp = [&pre0](const OpRec& o) { pre0.push_back(o); };
+  // the scaled cast as a launch of its own
+  auto emit_cast = [&]() {
+    OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+    o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
+    o.item.a = cast_r;
+    o.item.c = const_cast<T*>(b0);
+    o.item.scal = c->scal + 0;
+    sink(o);
+  };
   std::function<void(int, int, bool)> visit = [&](int l, int kind, bool zero) {
     if (l == lt) {
+      if (l == 0 && cast_r) emit_cast();  // (the cycle is one tail launch)
       if (c->tail0 >= 0) {
         OpRec o = base_op<T>(c, OC_TAIL, lt);
         o.count = c->tail_lds[Bufs<T>::prec];
@@ -889,8 +913,26 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     }
     bool z = zero;
     const bool s0 = l == 0 && split0;  // (head fusion: at least one pre-smoothing step)
-    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
-                    l == 0 && head_done && split_iterate<T>(c, 0), s0 ? c->s0at : nullptr);
+    smooth_level<T>(c, l == 0 && cast_r ? collectp : sink, l, true, &cur[l], &spare[l], &z,
+                    bb[l], l == 0 && head_done, l == 0 && head_done && split_iterate<T>(c, 0),
+                    s0 ? c->s0at : nullptr);
+    if (l == 0 && cast_r) {
+      bool cast = false;
+      if (!pre0.empty()) {
+        OpRec& f = pre0.front();
+        const int kd = f.sub & 15, xl = (f.sub >> 5) & 7;
+        if (std::is_same<T, float>::value && f.code == OC_SMOOTH && use_split_x(f.g) &&
+            ((f.sub >> 4) & 1) && (kd == SM_JACOBI || kd == SM_RB0) &&
+            (xl == XL_NATURAL || xl == XL_TO_SPLIT)) {
+          f.sub |= 1 << 9;
+          f.item.e = cast_r;
+          f.item.scal = c->scal + 0;
+          cast = true;
+        }
+      }
+      if (!cast) emit_cast();
+      for (const OpRec& o : pre0) sink(o);
+    }
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr,
                      s0 ? c->s0at : nullptr);
@@ -936,8 +978,8 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       }
       sink(o);
       std::swap(cur[l], spare[l]);
-      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l], true, sx || s0,
-                      s0 ? c->s0at : nullptr);
+      smooth_level<T>(c, l == 0 && iru_u ? collect0 : sink, l, false, &cur[l], &spare[l], &nz,
+                      bb[l], true, sx || s0, s0 ? c->s0at : nullptr);
       if (s0) {
         c->s0u[0] = c->s0at[0];
         c->s0u[1] = c->s0at[1];
@@ -947,11 +989,28 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       pr.item.a = cur[l + 1];
       pr.item.c = cur[l];
       sink(pr);
-      smooth_level<T>(c, sink, l, false, &cur[l], &spare[l], &nz, bb[l]);
+      smooth_level<T>(c, l == 0 && iru_u ? collect0 : sink, l, false, &cur[l], &spare[l], &nz,
+                      bb[l]);
+    }
+    if (l == 0 && iru_u) {
+      // the refinement update fused into the last step, where possible
+      if (!post0.empty()) {
+        OpRec& z = post0.back();
+        const int kd = z.sub & 15, xl = (z.sub >> 5) & 7;
+        if (std::is_same<T, float>::value && z.code == OC_SMOOTH && use_split_x(z.g) &&
+            (kd == SM_JACOBI || kd == SM_RB0 || kd == SM_RB1) && !((z.sub >> 4) & 1) &&
+            (xl == XL_NATURAL || xl == XL_TO_NATURAL)) {
+          z.sub |= 1 << 8;
+          z.item.c = iru_u;
+          z.item.scal = c->scal + 0;
+          *iru_done = true;
+        }
+      }
+      for (const OpRec& o : post0) sink(o);
     }
   };
   visit(0, c->o.cycle, x0_zero);
-  if (!split0 && cur[0] != x0) {
+  if (!split0 && !(iru_done && *iru_done) && cur[0] != x0) {
     OpRec o = base_op<T>(c, OC_COPY, 0);
     o.count = c->lv[0].g.nodes;
     o.item.a = cur[0];
@@ -1097,19 +1156,28 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
     return;
   }
   if (c->ir) {
-    // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c
-    OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
-    o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
-    o.item.a = L0.r64;
-    o.item.c = L0.b32;
-    o.item.scal = c->scal + 0;
-    sink(o);
-    emit_vcycle<float>(c, sink, L0.x32, L0.t32, L0.b32, true);
-    OpRec up = base_op<double>(c, OC_IR_UPDATE, 0);
-    up.item.a = L0.x32;
-    up.item.c = u;
-    up.item.scal = c->scal + 0;
-    sink(up);
+    // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c; the cast
+    // and the update fused into the cycle's first and last level-0 steps
+    // where those are k_sweep3 steps (not with MG_FLAG_NO_FUSE)
+    const bool nf = (c->o.flags & MG_FLAG_NO_FUSE) != 0;
+    if (nf) {
+      OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+      o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
+      o.item.a = L0.r64;
+      o.item.c = L0.b32;
+      o.item.scal = c->scal + 0;
+      sink(o);
+    }
+    bool fused = false;
+    emit_vcycle<float>(c, sink, L0.x32, L0.t32, L0.b32, true, false, false, nf ? nullptr : u,
+                       &fused, nf ? nullptr : L0.r64);
+    if (!fused) {
+      OpRec up = base_op<double>(c, OC_IR_UPDATE, 0);
+      up.item.a = L0.x32;
+      up.item.c = u;
+      up.item.scal = c->scal + 0;
+      sink(up);
+    }
   } else {
     emit_vcycle<double>(c, sink, u, L0.t64, b, false);
   }
@@ -1146,12 +1214,13 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool
 
 // profiling hooks: bracket level-0 launches of the selected kernel class
 enum ProfKind {
-  PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4, PK_SMOOTH_PRO = 5
+  PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4, PK_SMOOTH_PRO = 5,
+  PK_SMOOTH_IR = 6
 };
 
-int prof_class(int code) {
-  switch (code) {
-    case OC_SMOOTH:
+int prof_class(const OpRec& o) {
+  switch (o.code) {
+    case OC_SMOOTH: return (o.sub >> 8) & 3 ? PK_SMOOTH_IR : PK_SMOOTH;
     case OC_CSR_SMOOTH: return PK_SMOOTH;
     case OC_SMOOTH2: return PK_SMOOTH2;
     case OC_SMOOTH_PRO: return PK_SMOOTH_PRO;
@@ -1193,7 +1262,7 @@ void prof_collect(mg_ctx* c) {
 
 Sink launch_sink(mg_ctx* c, hipStream_t s) {
   return [c, s](const OpRec& o) {
-    const bool prof = c->prof_on && o.level == 0 && prof_class(o.code) == c->prof_kernel;
+    const bool prof = c->prof_on && o.level == 0 && prof_class(o) == c->prof_kernel;
     hipEvent_t a = nullptr, b = nullptr;
     if (prof) {
       a = take_event(c);
@@ -1289,7 +1358,7 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
   switch (o.code) {
     case OC_SMOOTH:
       launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, ((o.sub >> 4) & 1) != 0, (T)o.omega, B,
-                       s, (o.sub >> 5) & 7);
+                       s, (o.sub >> 5) & 7, ((o.sub >> 8) & 1) != 0, ((o.sub >> 9) & 1) != 0);
       break;
     case OC_RESID:
       launch_residual<T>(o.g, params_of<T>(o), (o.sub & 1) != 0, B, s, (o.sub >> 5) & 7);
@@ -1900,7 +1969,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
 
 mg_status mg_profile_enable(mg_ctx* c, int kernel_id, int enable) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > 5) return fail(MG_E_ARG, "kernel_id must be 0..5");
+  if (kernel_id < 0 || kernel_id > 6) return fail(MG_E_ARG, "kernel_id must be 0..6");
   c->prof_kernel = kernel_id;
   c->prof_on = enable != 0;
   c->prof_launches = 0;

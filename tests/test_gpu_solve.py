@@ -445,3 +445,38 @@ def test_split_finest_iterate_across_cycles_agrees_bitwise():
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
 
+
+@pytest.mark.parametrize("dim,n,levels,kap,smoother,nu", [
+    (3, 64, 6, False, "rbgs", (2, 2)),
+    (3, 96, 6, True, "rbgs", (2, 2)),       # per-cell kappa
+    (3, 64, 6, False, "jacobi", (1, 2)),
+    (3, 320, 7, False, "rbgs", (3, 3)),     # FP32 vectors of 132 MB: split iterates
+    (3, 16, 4, False, "rbgs", (2, 2)),      # the whole cycle in one tail launch
+    (2, 64, 5, False, "rbgs", (2, 2)),      # 2D: separate cast and update launches
+])
+def test_ir_cast_and_update_fused_into_the_cycle_agree_bitwise(dim, n, levels, kap, smoother,
+                                                                nu):
+    """FP32-inner refinement: the scaled cast of the residual fused into the
+    cycle's first finest-level step and the update u += s c fused into its
+    last give bitwise the results of the separate launches (MG_FLAG_NO_FUSE),
+    and the same cycle count as the oracle's refinement +-1."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    kappa = W.kappa_lognormal(dim, n, 17) if kap else None
+    bi = W.rhs_uniform(dim, n, 18)
+    b = dev_full(dim, n, bi)
+    outs = []
+    for flags in (0, FLAG_NO_FUSE):
+        with Solver(dim, n, levels, kappa=kappa, precision="fp32_ir", smoother=smoother,
+                    nu_pre=nu[0], nu_post=nu[1], flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-9)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+    if n <= 96:
+        H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother=smoother, nu_pre=nu[0],
+                              nu_post=nu[1], fp32=True)
+        _, k_or, _, _ = O.solve_ir(H, bi, 1e-9)
+        assert abs(outs[0][0] - k_or) <= 1
+
