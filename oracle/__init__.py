@@ -17,7 +17,8 @@ What it computes, and where the paper defines it:
 * canonical Q1 transfer operators: multilinear interpolation P and its
   adjoint R = P^T (Sec. 5.4, read for nested conforming Q1 spaces);
 * the outer fixed-point iteration of cycles (Sec. 5.5.1);
-* an FP32-inner / FP64-outer iterative-refinement wrapper of that iteration;
+* an FP32-inner / FP64-outer iterative-refinement wrapper of that iteration
+  (float32 correction cycles on the residual scaled by a power of two);
 * conjugate gradients preconditioned by one V-cycle per iteration
   (multigrid as a Krylov preconditioner, Sec. 1), in FP64 or with the
   cycle in FP32;
@@ -63,6 +64,7 @@ from .mg import (
     solve,
     solve_ir,
     solve_pcg,
+    ir_scale,
     precondition,
     colour_mask,
 )
@@ -80,7 +82,7 @@ __all__ = [
     "kappa_coarsen", "kappa_hierarchy", "to_full", "to_interior",
     "prolongation", "restriction",
     "Hierarchy", "build_hierarchy", "jacobi_sweep", "rb_half_sweep", "smooth",
-    "vcycle", "solve", "solve_ir", "colour_mask",
+    "vcycle", "solve", "solve_ir", "ir_scale", "colour_mask",
     "dst_eigenvalues", "dst_solve", "dense_solve", "sparse_solve",
     "manufactured_factor",
 ]

@@ -34,7 +34,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .mg import CYCLE_SCHEDULE
+from .mg import CYCLE_SCHEDULE, ir_scale
 from .q1 import element_matrix, kappa_hierarchy, local_vertices
 
 
@@ -306,7 +306,8 @@ def iterate(H, b, fp32=False, max_iter=None):
     """Yield (k, u_k, rho_k) for k = 1, 2, ... from u_0 = 0.
 
     FP64: u_k = cycle(u_{k-1}, b).  FP32-inner (``fp32``): r = b - A u,
-    s = ||r||, c = float32 cycle from 0 on float32(r / s), u += s c.
+    c = float32 cycle from 0 on float32(r / s), u += s c, with s the power
+    of two :func:`oracle.mg.ir_scale` of ||b||.
     rho_k = ||b - A u_k|| / ||b|| in FP64.  b is a full-grid FP64 array with
     zero boundary and a nonzero interior."""
     b = np.asarray(b, dtype=np.float64).reshape((H.n + 1,) * H.dim)
@@ -317,7 +318,7 @@ def iterate(H, b, fp32=False, max_iter=None):
     while max_iter is None or k < max_iter:
         k += 1
         if fp32:
-            s = norm(r)
+            s = ir_scale(nb)
             r32 = (r / s).astype(np.float32)
             c = cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True)
             u = u + s * c.astype(np.float64)

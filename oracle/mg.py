@@ -36,6 +36,7 @@ design notes of the repository):
   (rediscretised, like K_l).
 """
 
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -250,13 +251,24 @@ def solve(H, b, tol, max_iter=100, u0=None, diverge=1e3):
     return u, max_iter, hist, "maxit"
 
 
+def ir_scale(nb):
+    """Scale of the float32 correction equations of iterative refinement:
+    the power of two 2^e with ||b|| = m 2^e, 1/2 <= m < 1.  Dividing by a
+    power of two is exact, so float32(r / s) = float32(r) / s and the float32
+    cycle, homogeneous under such scalings, computes the correction of r as
+    it would of float32(r) itself; s only keeps the float32 values near
+    unit size whatever the scale of b."""
+    return math.ldexp(1.0, math.frexp(float(nb))[1])
+
+
 def solve_ir(H, b, tol, max_iter=100, diverge=1e3, u0=None):
     """FP32-inner / FP64-outer iterative refinement.
 
-    FP64: r = b - A u, s = ||r||; the correction equation is solved
-    approximately by one float32 V-cycle (operators rounded from the FP64
-    assembly, coarse solve in FP64) applied to float32(r / s) from a zero
-    guess; then u += s * float64(c).  Starts and stops like :func:`solve`.
+    FP64: r = b - A u; the correction equation is solved approximately by
+    one float32 V-cycle (operators rounded from the FP64 assembly, coarse
+    solve in FP64) applied to float32(r / s) from a zero guess, s =
+    :func:`ir_scale` of ||b|| (fixed for the solve); then u += s *
+    float64(c).  Starts and stops like :func:`solve`.
     """
     if not H.A32:
         raise ValueError("hierarchy built without fp32=True")
@@ -267,8 +279,8 @@ def solve_ir(H, b, tol, max_iter=100, diverge=1e3, u0=None):
         return np.zeros_like(b), 0, [1.0], "ok"
     if u0 is not None and hist[0] <= tol:
         return u, 0, hist, "ok"
+    s = ir_scale(nb)
     for k in range(1, max_iter + 1):
-        s = np.linalg.norm(r)
         r32 = (r / s).astype(np.float32)
         c32 = cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True)
         u = u + s * c32.astype(np.float64)
@@ -284,9 +296,9 @@ def solve_ir(H, b, tol, max_iter=100, diverge=1e3, u0=None):
 
 def precondition(H, r, fp32=False):
     """The multigrid preconditioner: z = one cycle (H.cycle, V or W) from a
-    zero guess on A z = r.  With fp32, the cycle runs in float32 on
-    r / ||r|| and is scaled back: z = ||r|| * float64(cycle32(float32(r /
-    ||r||))).  The V- and W-cycles are symmetric (post-smoothing reverses
+    zero guess on A z = r.  With fp32, the cycle runs in float32 on r / s
+    and is scaled back: z = s * float64(cycle32(float32(r / s))), s =
+    :func:`ir_scale` of ||r||.  The V- and W-cycles are symmetric (post-smoothing reverses
     the colour order of the pre-smoothing, nu_pre = nu_post), so in exact
     arithmetic z = B r with B symmetric positive definite; the F-cycle is
     not and is refused."""
@@ -294,9 +306,10 @@ def precondition(H, r, fp32=False):
         raise ValueError("CG needs a symmetric cycle (V or W)")
     if not fp32:
         return cycle(H, 0, np.zeros_like(r), r, H.cycle)
-    s = np.linalg.norm(r)
-    if s == 0.0:
+    nr = np.linalg.norm(r)
+    if nr == 0.0:
         return np.zeros_like(r)
+    s = ir_scale(nr)
     r32 = (r / s).astype(np.float32)
     return s * cycle(H, 0, np.zeros_like(r32), r32, H.cycle, fp32=True).astype(np.float64)
 

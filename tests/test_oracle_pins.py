@@ -444,6 +444,38 @@ def test_fp32_ir_reaches_fp64_accuracy(dim, n, levels, kap):
     assert np.linalg.norm(u32 - ue) / np.linalg.norm(ue) < 1e-7
 
 
+def test_ir_scale_is_the_power_of_two_at_or_above_the_norm():
+    """frexp's exponent: s = 2^e with s/2 <= ||b|| < s, exactly a power of
+    two, the same for ||b|| scaled by any power of two up to that factor."""
+    for nb, want in ((1.0, 2.0), (0.75, 1.0), (0.5, 1.0), (3.0, 4.0), (1e-30, 2.0 ** -99),
+                     (2.0 ** 40 * 1.5, 2.0 ** 41)):
+        s = O.ir_scale(nb)
+        assert s == want, (nb, s)
+        assert s / 2 <= nb < s
+        assert O.ir_scale(nb * 2.0 ** 17) == s * 2.0 ** 17
+
+
+@pytest.mark.parametrize("dim,n,levels,kap", [(2, 32, 4, False), (3, 16, 4, True)])
+def test_ir_first_step_is_the_unscaled_float32_cycle_of_b(dim, n, levels, kap):
+    """With a power-of-two scale the scaling is exact: from u = 0 the first
+    refinement step u_1 = s * cycle32(float32(b / s)) equals the float32
+    cycle applied to float32(b) itself, bitwise, and scaling b by 2^k
+    scales every iterate by 2^k and leaves the history unchanged, bitwise
+    (a scale s = ||r|| would break the first identity)."""
+    kappa = W.kappa_lognormal(dim, n, 4) if kap else None
+    H = O.build_hierarchy(dim, n, levels, kappa=kappa, smoother="rbgs", fp32=True)
+    b = W.rhs_uniform(dim, n, 5) * 3.7e-3
+    u1, k1, _, st = O.solve_ir(H, b, 1e-300, max_iter=1)
+    assert st == "maxit" and k1 == 1
+    b32 = b.astype(np.float32)
+    c = O.cycle(H, 0, np.zeros_like(b32), b32, H.cycle, fp32=True)
+    assert np.array_equal(u1, c.astype(np.float64))
+    ua, ka, ha, _ = O.solve_ir(H, b, 1e-9)
+    ub, kb, hb, _ = O.solve_ir(H, b * 2.0 ** 40, 1e-9)
+    assert ka == kb and ha == hb
+    assert np.array_equal(ub, ua * 2.0 ** 40)
+
+
 def test_variable_kappa_solution_matches_direct():
     n = 16
     kap = W.kappa_lognormal(3, n, 5)
