@@ -102,7 +102,8 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 (Sec. 5.5.1); needs a symmetric cycle
                                 (nu_pre == nu_post).  In FP32_IR contexts the
                                 preconditioning cycle runs in FP32 on
-                                r / ||r||.  Iterations and the history then
+                                r / s, s the power of two with
+                                s / 2 <= ||r|| < s.  Iterations and the history then
                                 count CG iterations, with the recursively
                                 updated residual.  V- or W-cycles only (the
                                 F-cycle is not symmetric).  Not for the
@@ -176,8 +177,9 @@ mg_status mg_setup(const mg_options* o, const double* kappa_dev, void* stream,
  * (2-norm over the unknowns), starting from u = 0 (or from the given u with
  * MG_FLAG_WARM), one V(nu_pre, nu_post) cycle per iteration (Sec. 5.5.1).
  * With MG_PREC_FP32_IR each iteration is
- * one FP32 V-cycle on the scaled FP64 residual, followed by an FP64 update
- * and residual.
+ * one FP32 V-cycle from 0 on float(r / s), r the FP64 residual and s the
+ * power of two with s / 2 <= ||b|| < s (exact scaling), followed by the FP64
+ * update u += s c and residual.
  *   b_dev      device, (n+1)^dim doubles; boundary entries ignored.
  *   u_dev      device, (n+1)^dim doubles, output (and with MG_FLAG_WARM
  *              the initial iterate on its unknowns); boundary entries set
@@ -342,8 +344,8 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps
  *              in one pass, 5 = prolongation fused into a smoothing step,
- *              6 = FP32 smoothing step of iterative refinement with the
- *              scaled cast of the residual or the update of u fused in
+ *              6 = last FP32 smoothing step of an iterative-refinement
+ *              cycle, with the update of u fused in
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

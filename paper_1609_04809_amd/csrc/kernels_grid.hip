@@ -499,15 +499,14 @@ inline int sweep3_kz(int m, int elem) {
 // IRU (FP32 smoothing steps that write a natural iterate): the step is the
 // last one of the FP32 correction cycle of iterative refinement, and instead
 // of the correction c it writes u + s c (u: the FP64 iterate, Item::c; s =
-// sqrt(*Item::scal)), in the arithmetic of k_ir_update -- the refinement
-// update fused into the step that produces c.  The step reads no u that
-// other blocks write, so the update can be in place.
-// CAST (FP32 smoothing from x = 0, the first step of the refinement cycle):
-// the step's right-hand side is float(r / s) of the FP64 residual r
-// (Item::e, natural layout; s = sqrt(*Item::scal)), in the arithmetic of
-// k_scale_cast; the step writes it to Item::b (in the layout Item::lay) for
-// the rest of the cycle as it uses it -- the scaled cast fused into the
-// first step that reads it.
+// ir_scale(*Item::scal)), in the arithmetic of k_ir_update -- the
+// refinement update fused into the step that produces c.  The step reads no
+// u that other blocks write, so the update can be in place.
+// CAST (FP64 residual, x and b natural): r = b - A x is not stored; the
+// step writes float(r / s) (s = ir_scale(*Item::scal)) to the FP32 vector
+// Item::c in the layout Item::lay, in the arithmetic of k_scale_cast -- the
+// residual of iterative refinement written directly as the right-hand side
+// of the next FP32 correction cycle.
 template <typename T, int KIND, int MODE, bool ZERO, bool NORM, bool PRO = false, int XL = 0,
           bool IRU = false, bool CAST = false>
 __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T omega, int kz,
@@ -527,9 +526,8 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   static_assert(!IRU || (sizeof(T) == 4 && !ZERO && !PRO && (XL == 0 || XL == 3) &&
                          (MODE == SM_RB0 || MODE == SM_RB1 || MODE == SM_JACOBI)),
                 "the refinement update follows a natural-output FP32 smoothing step");
-  static_assert(!CAST || (sizeof(T) == 4 && ZERO && (XL == 0 || XL == 1) &&
-                          (MODE == SM_RB0 || MODE == SM_JACOBI)),
-                "the scaled cast feeds an FP32 first step from x = 0");
+  static_assert(!CAST || (sizeof(T) == 8 && MODE == SW_RESID && !ZERO && !PRO && XL == 0),
+                "the scaled cast is written by an FP64 residual");
   __shared__ __align__(16) T sx[2][SW_LY][SW_LX];
   __shared__ T sk[2][SW_TY + 1][SW_TX + 1];
   const int n = g.n, m = n - 1;
@@ -755,7 +753,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   T bpf[2] = {T(0), T(0)};
   T* const ge = MODE == SW_CN ? (T*)const_cast<void*>(I.e) : nullptr;
   T gpf[2] = {T(0), T(0)};
-  const long blay = I.lay;  // b colour-split (see Item::lay) or natural
+  const long blay = CAST ? 0 : I.lay;  // b colour-split (see Item::lay) or natural
   // Red-black on a colour-split b: every unknown a half-sweep updates has
   // parity `colour`, so its b is element p / 2 of that colour's half.  A
   // lane clamped onto node (n, n, n) (parity 0) in a colour-1 sweep reads
@@ -772,10 +770,13 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     }
   };
   double* const uo = IRU ? (double*)I.c : nullptr;
-  const double sr = IRU ? sqrt(*I.scal) : 0.0;
+  const double sr = IRU || CAST ? ir_scale(*I.scal) : 0.0;
+  float* const co = CAST ? (float*)I.c : nullptr;
   auto put = [&](long p, T v) {
     if constexpr (IRU)
       uo[p] = uo[p] + sr * (double)v;
+    else if constexpr (CAST)
+      co[lay_idx(p, I.lay)] = (float)((double)v / sr);
     else
       out[p] = v;
   };
@@ -812,22 +813,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       __syncthreads();
       window_k((k0 - 1) & 1, kwp);
     }
-    const double* const r64 = CAST ? (const double*)I.e : nullptr;
-    const double rs = CAST ? sqrt(*I.scal) : 0.0;
-    T* const bw = CAST ? (T*)const_cast<void*>(I.b) : nullptr;
-    double rpf[2] = {0.0, 0.0};
     for (int k = k0; k <= k1; ++k) {
       if (KAP) {
         commit_k(k & 1);
         prefetch_k(k + 1);
       }
-      if constexpr (CAST) {
-        const long p = pb0 + (long)min(k, n) * sz;
-#pragma unroll
-        for (int u = 0; u < 2; ++u) rpf[u] = r64[p + u];
-      } else {
-        prefetch_b(k);
-      }
+      prefetch_b(k);
       __syncthreads();
       T kwc[2][3];
       if (KAP) window_k(k & 1, kwc);
@@ -836,11 +827,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
         const bool ok = u == 0 ? ok0 : ok1;
         const bool upd = MODE == SM_JACOBI || (((i + u + j + k) & 1) == colour);
         if (!ok) continue;
-        T bv = bpf[u];
-        if constexpr (CAST) {
-          bv = (T)(rpf[u] / rs);
-          bw[lay_idx(i + u + j * sy + (long)k * sz, blay)] = bv;
-        }
+        const T bv = bpf[u];
         T dg = op.wc;
         if (KAP) dg = op.s * T(4) * kappa_cell_sum<T>(kwp, kwc, u);
         if (MODE == SM_JACOBI)
@@ -1496,21 +1483,22 @@ __global__ __launch_bounds__(256) void k_split_norm(Geo g, Batch B) {
     I.partials[blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * plane)] = t;
 }
 
-// b32 = float(r / ||r||) on the unknowns, ||r||^2 read from device memory.
+// b32 = float(r / s) on the unknowns, s = ir_scale(||b||^2) (read from
+// device memory).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_scale_cast(Geo g, Batch B) {
   NODE_INDEX(DIM, g)
   if (!inside) return;
-  const double s = sqrt(*I.scal);
+  const double s = ir_scale(*I.scal);
   ((float*)I.c)[lay_idx(p, I.lay)] = (float)(((const double*)I.a)[p] / s);
 }
 
-// u += ||r|| * double(c) on the unknowns.
+// u += s * double(c) on the unknowns, s = ir_scale(||b||^2).
 template <int DIM>
 __global__ __launch_bounds__(256) void k_ir_update(Geo g, Batch B) {
   NODE_INDEX(DIM, g)
   if (!inside) return;
-  const double s = sqrt(*I.scal);
+  const double s = ir_scale(*I.scal);
   double* u = (double*)I.c;
   u[p] = u[p] + s * (double)((const float*)I.a)[p];
 }
@@ -2226,7 +2214,17 @@ inline void with_kind3(int kind, F f) {
 
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
-                     hipStream_t s, int xl) {
+                     hipStream_t s, int xl, bool cast) {
+  if (cast) {
+    // (the runtime asks for it on k_sweep3 levels in FP64 with norm)
+    if constexpr (std::is_same<T, double>::value) {
+      with_kind3(op.kind, [&](auto k) {
+        constexpr int K = decltype(k)::value;
+        launch_sweep3<T, K, SW_RESID, false, true, 0, false, true>(g, op, T(0), B, s);
+      });
+    }
+    return;
+  }
   if (xl == XL_SPLIT) {
     // (split iterates exist on k_sweep3 levels of the constant-coefficient
     // and mass-shifted kinds)
@@ -2332,24 +2330,9 @@ void launch_sweep3_iru(const Geo& g, const StencilParams<T>& op, int kind, T ome
 
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s, int xl, bool iru, bool cast) {
+                   const Batch& B, hipStream_t s, int xl, bool iru) {
   if (iru) {
     launch_sweep3_iru<T>(g, op, kind, omega, xl, B, s);
-    return;
-  }
-  if (cast) {
-    if constexpr (std::is_same<T, float>::value) {
-      with_kind3(op.kind, [&](auto kc) {
-        constexpr int K = decltype(kc)::value;
-        if (xl == XL_TO_SPLIT) {
-          launch_sweep3<T, K, SM_RB0, true, false, XL_TO_SPLIT, false, true>(g, op, omega, B, s);
-        } else if (kind == SM_RB0) {
-          launch_sweep3<T, K, SM_RB0, true, false, 0, false, true>(g, op, omega, B, s);
-        } else {
-          launch_sweep3<T, K, SM_JACOBI, true, false, 0, false, true>(g, op, omega, B, s);
-        }
-      });
-    }
     return;
   }
   if (xl != XL_NATURAL) {
@@ -2734,14 +2717,14 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_fill<T>(T*, long, T, hipStream_t);                                   \
   template void launch_copy<T>(const T*, T*, long, hipStream_t);                            \
   template void launch_residual<T>(const Geo&, const StencilParams<T>&, bool, const Batch&, \
-                                   hipStream_t, int);                                       \
+                                   hipStream_t, int, bool);                                 \
   template void launch_unsplit<T>(const Geo&, const Batch&, hipStream_t);                   \
   template void launch_smooth_pair<T>(const Geo&, const StencilParams<T>&, int, bool,      \
                                       const Batch&, hipStream_t);                           \
   template void launch_smooth_prolong<T>(const Geo&, const StencilParams<T>&, int, T,       \
                                          const Batch&, hipStream_t, int);                   \
   template void launch_smooth<T>(const Geo&, const StencilParams<T>&, int, bool, T,         \
-                                 const Batch&, hipStream_t, int, bool, bool);               \
+                                 const Batch&, hipStream_t, int, bool);                     \
   template void launch_head<T>(const Geo&, const StencilParams<T>&, int, T, const Batch&,   \
                                hipStream_t, int);                                           \
   template void launch_apply_dot<T>(const Geo&, const StencilParams<T>&, const Batch&,      \

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(PT) void k_pcg_update(double* __restrict__ u,
 __global__ __launch_bounds__(PT) void k_pcg_zscale(const float* __restrict__ c,
                                                    double* __restrict__ z,
                                                    const double* __restrict__ scal, long n) {
-  const double s = sqrt(scal[0]);
+  const double s = ir_scale(scal[0]);
   for (long e = blockIdx.x * (long)PT + threadIdx.x; e < n; e += (long)gridDim.x * PT)
     z[e] = s * (double)c[e];
 }

@@ -77,7 +77,9 @@ enum PcgOp { PO_DOTS2 = 0, PO_SCALARS, PO_DIR, PO_UPDATE, PO_ZSCALE };
 struct OpRec {
   int code = 0;
   int prec = 0;     // 0 double, 1 float
-  int sub = 0;      // OC_SMOOTH: kind | zero << 4;  OC_RESID: norm
+  // OC_SMOOTH: kind | zero << 4 | XLayout << 5 | IRU << 8;
+  // OC_RESID: norm | XLayout << 5 | scaled cast << 9
+  int sub = 0;
   int level = 0;    // level index within its context (profiling)
   Geo g{}, gc{};    // level geometry and the next coarser one
   int opkind = 0;   // OP_CONST / OP_KAPPA / OP_MASS

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 
@@ -107,6 +108,17 @@ __host__ __device__ inline long lay_idx(long p, long lay) {
   return lay ? (p >> 1) + (p & 1) * lay : p;
 }
 
+// Scale s of the FP32 correction equations of iterative refinement, from
+// ||b||^2: the power of two 2^e with ||b|| = m 2^e, 1/2 <= m < 1.  The
+// cycle gets float(r / s) and u += s c; dividing and multiplying by a power
+// of two is exact, so the scale changes no rounding, it only keeps the FP32
+// values near unit size.
+__host__ __device__ inline double ir_scale(double b_norm2) {
+  int e;
+  (void)frexp(sqrt(b_norm2), &e);
+  return ldexp(1.0, e);
+}
+
 struct Batch {
   Item it[kMaxBatch];
   int count;
@@ -207,9 +219,12 @@ long norm2_blocks(const Geo& g);
 //   a = x, b = b, c = r, kappa, partials.
 // xl = XL_SPLIT (k_sweep3 levels, constant-coefficient or mass-shifted):
 // x read colour-split, a = its even half, a2 = its odd half.
+// cast (FP64, k_sweep3 levels, x and b natural): r is not stored; instead
+// float(r / ir_scale(*scal)) goes to the FP32 vector c in the layout lay
+// (the right-hand side of the refinement's FP32 cycle).
 template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
-                     hipStream_t s, int xl = 0);
+                     hipStream_t s, int xl = 0, bool cast = false);
 // u = the natural layout of a colour-split vector (every node; the halves'
 // boundary entries are 0):  a = even half, a2 = odd half, c = u.
 template <typename T>
@@ -222,15 +237,10 @@ void launch_unsplit(const Geo& g, const Batch& B, hipStream_t s);
 // (the updated colour) and c2 (the other colour, XL_TO_SPLIT) when written.
 // iru (FP32, k_sweep3 levels, a step with natural output: xl 0 or
 // XL_TO_NATURAL, kind SM_JACOBI / SM_RB0 / SM_RB1): the step's result c is
-// not stored; instead u += sqrt(*scal) c with c = u (FP64), scal.
-// cast (FP32, k_sweep3 levels, a first step from x = 0, xl 0 or
-// XL_TO_SPLIT, kind SM_JACOBI / SM_RB0): the right-hand side is
-// float(r / sqrt(*scal)) of the FP64 residual e = r, written to b (in the
-// layout lay) as it is used.
+// not stored; instead u += ir_scale(*scal) c with c = u (FP64), scal.
 template <typename T>
 void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero, T omega,
-                   const Batch& B, hipStream_t s, int xl = 0, bool iru = false,
-                   bool cast = false);
+                   const Batch& B, hipStream_t s, int xl = 0, bool iru = false);
 enum XLayout {
   XL_NATURAL = 0,
   XL_TO_SPLIT = 1,     // natural in, both halves out
@@ -278,9 +288,10 @@ template <typename T>
 void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s);
 // scal = sum of partials[0..count), fixed order, one block per request.
 void launch_reduce_final(long count, const Batch& B, hipStream_t s);
-// b32 = float(r / sqrt(scal)):  a = r (double), c = b32 (float), scal.
+// b32 = float(r / ir_scale(*scal)):  a = r (double), c = b32 (float), scal
+// (= ||b||^2), lay (b32's layout).
 void launch_scale_cast(const Geo& g, const Batch& B, hipStream_t s);
-// u += sqrt(scal) * double(c):  a = c (float), c = u (double), scal.
+// u += ir_scale(*scal) * double(c):  a = c (float), c = u (double), scal.
 void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s);
 // The V-cycle on the tail levels, one block per request:  a = TailDesc<T>*
 // (device), b = level-l0 right-hand side, c = level-l0 iterate (updated in

@@ -852,16 +852,13 @@ bool fuse_prolongation(const mg_ctx* c, int l);
 // result stays in the halves (recorded in c->s0u); x0 is not written.
 // iru_u (FP32 cycles of iterative refinement): where the level-0 post-smoothing
 // ends with a smoothing step that writes a natural iterate on a k_sweep3
-// level, that step adds sqrt(scal[0]) times its result to the FP64 iterate
-// iru_u instead of writing x0 (*iru_done is set then; x0 is not written).
-// cast_r (FP32 cycles of iterative refinement, x0_zero): b0 is
-// float(cast_r / sqrt(scal[0])), formed by the first level-0 smoothing step
-// where it is a first step from x = 0 on a k_sweep3 level, else by a
-// scaled-cast launch before the cycle.
+// level, that step adds ir_scale(scal[1]) times its result to the FP64
+// iterate iru_u instead of writing x0 (*iru_done is set then; x0 is not
+// written).
 template <typename T>
 void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, bool x0_zero,
                  bool head_done = false, bool split0 = false, double* iru_u = nullptr,
-                 bool* iru_done = nullptr, const double* cast_r = nullptr) {
+                 bool* iru_done = nullptr) {
   if (iru_done) *iru_done = false;
   const int L = c->L;
   std::vector<T*> cur(L), spare(L);
@@ -878,22 +875,11 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
   if (head_done) std::swap(cur[0], spare[0]);
   // one visit of level l by a cycle of `kind`, its iterate starting at 0
   // when `zero`
-  // level-0 pre- and post-smoothing ops are collected first (see cast_r, iru_u)
-  std::vector<OpRec> pre0, post0;
+  // level-0 post-smoothing ops are collected first (see iru_u)
+  std::vector<OpRec> post0;
   const Sink collect0 = [&post0](const OpRec& o) { post0.push_back(o); };
-  const Sink collectp = [&pre0](const OpRec& o) { pre0.push_back(o); };
-  // the scaled cast as a launch of its own
-  auto emit_cast = [&]() {
-    OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
-    o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
-    o.item.a = cast_r;
-    o.item.c = const_cast<T*>(b0);
-    o.item.scal = c->scal + 0;
-    sink(o);
-  };
   std::function<void(int, int, bool)> visit = [&](int l, int kind, bool zero) {
     if (l == lt) {
-      if (l == 0 && cast_r) emit_cast();  // (the cycle is one tail launch)
       if (c->tail0 >= 0) {
         OpRec o = base_op<T>(c, OC_TAIL, lt);
         o.count = c->tail_lds[Bufs<T>::prec];
@@ -913,26 +899,8 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     }
     bool z = zero;
     const bool s0 = l == 0 && split0;  // (head fusion: at least one pre-smoothing step)
-    smooth_level<T>(c, l == 0 && cast_r ? collectp : sink, l, true, &cur[l], &spare[l], &z,
-                    bb[l], l == 0 && head_done, l == 0 && head_done && split_iterate<T>(c, 0),
-                    s0 ? c->s0at : nullptr);
-    if (l == 0 && cast_r) {
-      bool cast = false;
-      if (!pre0.empty()) {
-        OpRec& f = pre0.front();
-        const int kd = f.sub & 15, xl = (f.sub >> 5) & 7;
-        if (std::is_same<T, float>::value && f.code == OC_SMOOTH && use_split_x(f.g) &&
-            ((f.sub >> 4) & 1) && (kd == SM_JACOBI || kd == SM_RB0) &&
-            (xl == XL_NATURAL || xl == XL_TO_SPLIT)) {
-          f.sub |= 1 << 9;
-          f.item.e = cast_r;
-          f.item.scal = c->scal + 0;
-          cast = true;
-        }
-      }
-      if (!cast) emit_cast();
-      for (const OpRec& o : pre0) sink(o);
-    }
+    smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
+                    l == 0 && head_done && split_iterate<T>(c, 0), s0 ? c->s0at : nullptr);
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
     emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr,
                      s0 ? c->s0at : nullptr);
@@ -1002,7 +970,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
             (xl == XL_NATURAL || xl == XL_TO_NATURAL)) {
           z.sub |= 1 << 8;
           z.item.c = iru_u;
-          z.item.scal = c->scal + 0;
+          z.item.scal = c->scal + 1;
           *iru_done = true;
         }
       }
@@ -1074,7 +1042,7 @@ void emit_pcg_op(mg_ctx* c, const Sink& sink, int sub, std::initializer_list<voi
 //   p = z + beta p (p = z first);  q = A p;  alpha = rz / p.q;
 //   u += alpha p;  r_old = r;  r -= alpha q;  ||r||^2 into scal[0].
 // B is the V-cycle from a zero guess on A z = r (FP64), or in FP32 on
-// r / ||r|| scaled back by ||r||.  r lives in its own vector: the cycle
+// r / s scaled back by s = ir_scale(||r||^2).  r lives in its own vector: the cycle
 // uses the level's residual buffer internally.
 void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
   Level& L0 = c->lv[0];
@@ -1107,6 +1075,36 @@ void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
   emit_reduce(c, sink, residual_partials(c, 0), S + PCG_PQ, c->partials);
   emit_pcg_op(c, sink, PO_UPDATE, {u, L0.p64, L0.rk64, L0.ro64, L0.q64}, N);
   emit_reduce(c, sink, PB, S + 0, c->partials);
+}
+
+// Iterative refinement: the partial sums of ||b - A u||^2 and the FP32
+// cycle's right-hand side b32 = float(r / s), s = ir_scale(scal[1] =
+// ||b||^2) -- in one residual pass on k_sweep3 levels (r is not stored;
+// not with MG_FLAG_NO_FUSE), else r into r64 and a scaled-cast launch.
+// Both give the same b32 bitwise.
+void emit_ir_residual(mg_ctx* c, const Sink& sink, double* u, const double* b) {
+  Level& L0 = c->lv[0];
+  const long lay32 = b_split_half(c, 0, 1);  // layout of b32
+  if (!c->csr && use_split_x(L0.g) && !(c->o.flags & MG_FLAG_NO_FUSE) &&
+      b_split_half(c, 0, 0) == 0) {
+    OpRec o = base_op<double>(c, OC_RESID, 0);
+    o.sub = 1 | (1 << 9);  // with the partial sums; the scaled cast
+    o.item.a = u;
+    o.item.b = b;
+    o.item.c = L0.b32;
+    o.item.lay = lay32;
+    o.item.scal = c->scal + 1;
+    o.item.partials = c->partials;
+    sink(o);
+    return;
+  }
+  emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
+  OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
+  o.item.lay = lay32;
+  o.item.a = L0.r64;
+  o.item.c = L0.b32;
+  o.item.scal = c->scal + 1;
+  sink(o);
 }
 
 // u = 0, or for a warm start u's boundary entries = 0.
@@ -1156,33 +1154,27 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
     return;
   }
   if (c->ir) {
-    // b32 = float(r/||r||), c = V-cycle32(0, b32), u += ||r|| c; the cast
-    // and the update fused into the cycle's first and last level-0 steps
-    // where those are k_sweep3 steps (not with MG_FLAG_NO_FUSE)
+    // c = V-cycle32(0, b32), u += s c (b32 = float(r / s) from the residual
+    // of the previous iteration or the prologue, s = ir_scale(||b||^2)); the
+    // update fused into the cycle's last level-0 step where that is a
+    // k_sweep3 step (not with MG_FLAG_NO_FUSE)
     const bool nf = (c->o.flags & MG_FLAG_NO_FUSE) != 0;
-    if (nf) {
-      OpRec o = base_op<double>(c, OC_SCALE_CAST, 0);
-      o.item.lay = b_split_half(c, 0, 1);  // the FP32 right-hand side it writes
-      o.item.a = L0.r64;
-      o.item.c = L0.b32;
-      o.item.scal = c->scal + 0;
-      sink(o);
-    }
     bool fused = false;
     emit_vcycle<float>(c, sink, L0.x32, L0.t32, L0.b32, true, false, false, nf ? nullptr : u,
-                       &fused, nf ? nullptr : L0.r64);
+                       &fused);
     if (!fused) {
       OpRec up = base_op<double>(c, OC_IR_UPDATE, 0);
       up.item.a = L0.x32;
       up.item.c = u;
-      up.item.scal = c->scal + 0;
+      up.item.scal = c->scal + 1;
       sink(up);
     }
+    emit_ir_residual(c, sink, u, b);
   } else {
     emit_vcycle<double>(c, sink, u, L0.t64, b, false);
+    // r = b - A u and ||r||^2 into scal[0]
+    emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
   }
-  // r = b - A u and ||r||^2 into scal[0]
-  emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
   emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
 }
 
@@ -1206,7 +1198,10 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool
   if (warm && fuse) {
     emit_head<double>(c, sink, 0, u, b, L0.t64, c->partials);
     emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
-  } else if (c->ir || warm) {
+  } else if (c->ir) {
+    emit_ir_residual(c, sink, u, b);
+    emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
+  } else if (warm) {
     emit_residual<double>(c, sink, 0, u, b, L0.r64, c->partials);
     emit_reduce(c, sink, residual_partials(c, 0), c->scal + 0);
   }
@@ -1220,7 +1215,7 @@ enum ProfKind {
 
 int prof_class(const OpRec& o) {
   switch (o.code) {
-    case OC_SMOOTH: return (o.sub >> 8) & 3 ? PK_SMOOTH_IR : PK_SMOOTH;
+    case OC_SMOOTH: return (o.sub >> 8) & 1 ? PK_SMOOTH_IR : PK_SMOOTH;
     case OC_CSR_SMOOTH: return PK_SMOOTH;
     case OC_SMOOTH2: return PK_SMOOTH2;
     case OC_SMOOTH_PRO: return PK_SMOOTH_PRO;
@@ -1358,10 +1353,11 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
   switch (o.code) {
     case OC_SMOOTH:
       launch_smooth<T>(o.g, params_of<T>(o), o.sub & 15, ((o.sub >> 4) & 1) != 0, (T)o.omega, B,
-                       s, (o.sub >> 5) & 7, ((o.sub >> 8) & 1) != 0, ((o.sub >> 9) & 1) != 0);
+                       s, (o.sub >> 5) & 7, ((o.sub >> 8) & 1) != 0);
       break;
     case OC_RESID:
-      launch_residual<T>(o.g, params_of<T>(o), (o.sub & 1) != 0, B, s, (o.sub >> 5) & 7);
+      launch_residual<T>(o.g, params_of<T>(o), (o.sub & 1) != 0, B, s, (o.sub >> 5) & 7,
+                         ((o.sub >> 9) & 1) != 0);
       break;
     case OC_RESTRICT: launch_restrict<T>(o.g, o.gc, B, s); break;
     case OC_PROLONG: launch_prolong_add<T>(o.g, o.gc, B, s); break;
