@@ -454,12 +454,13 @@ def test_split_finest_iterate_across_cycles_agrees_bitwise():
     (3, 16, 4, False, "rbgs", (2, 2)),      # the whole cycle in one tail launch
     (2, 64, 5, False, "rbgs", (2, 2)),      # 2D: separate cast and update launches
 ])
-def test_ir_cast_and_update_fused_into_the_cycle_agree_bitwise(dim, n, levels, kap, smoother,
+def test_ir_residual_cast_and_update_fusions_agree_bitwise(dim, n, levels, kap, smoother,
                                                                 nu):
-    """FP32-inner refinement: the scaled cast of the residual fused into the
-    cycle's first finest-level step and the update u += s c fused into its
-    last give bitwise the results of the separate launches (MG_FLAG_NO_FUSE),
-    and the same cycle count as the oracle's refinement +-1."""
+    """FP32-inner refinement: the FP32 right-hand side float(r / s) written
+    by the FP64 residual pass itself and the update u += s c fused into the
+    cycle's last finest-level step give bitwise the results of the separate
+    launches (MG_FLAG_NO_FUSE: r stored, then cast; update launched after the
+    cycle), and the same cycle count as the oracle's refinement +-1."""
     torch_cuda()
     from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
     kappa = W.kappa_lognormal(dim, n, 17) if kap else None
