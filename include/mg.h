@@ -345,7 +345,8 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps
  *              in one pass, 5 = prolongation fused into a smoothing step,
  *              6 = last FP32 smoothing step of an iterative-refinement
- *              cycle, with the update of u fused in
+ *              cycle, with the update of u fused in, 7 = residual and
+ *              restriction in one pass
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

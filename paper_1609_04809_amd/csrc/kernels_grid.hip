@@ -370,6 +370,19 @@ __device__ __forceinline__ T residual_node(const StencilParams<T>& op, const T* 
   return b[p] - ax;
 }
 
+// The 3D restriction as explicit fused multiply-adds (the same roundings
+// in every kernel that restricts, whatever the compiler contracts): a row
+// of three fine values around an even column, r0 + (rm + rp) / 2, and the
+// weighted sum of three rows (then of three planes), m / 2 + c + p / 2.
+template <typename T>
+__device__ __forceinline__ T restrict_row(T rm, T r0, T rp) {
+  return fma(T(0.5), rm + rp, r0);
+}
+template <typename T>
+__device__ __forceinline__ T restrict_sum(T m, T c, T p) {
+  return fma(T(0.5), p, fma(T(0.5), m, c));
+}
+
 // Coarse node (i, j[, k]) gathers the fine residual around fine node 2I
 // with weights prod_d (o_d == 0 ? 1 : 1/2).  Only fine unknowns are read.
 template <typename T, int DIM>
@@ -383,19 +396,18 @@ __device__ __forceinline__ T restrict_node(const DGeo& gf, const T* __restrict__
            q * ((r[pf - 1 - sy] + r[pf + 1 - sy]) + (r[pf - 1 + sy] + r[pf + 1 + sy]));
   }
   const long sy = gf.sy, sz = gf.sz;
-  T acc = 0;
+  T pl[3];
 #pragma unroll
-  for (int dz = -1; dz <= 1; ++dz) {
-    T pl = 0;
+  for (int dz = 0; dz < 3; ++dz) {
+    T row[3];
 #pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const long o = pf + dy * sy + dz * sz;
-      const T row = r[o] + h * (r[o - 1] + r[o + 1]);
-      pl += (dy == 0 ? T(1) : h) * row;
+    for (int dy = 0; dy < 3; ++dy) {
+      const long o = pf + (dy - 1) * sy + (dz - 1) * sz;
+      row[dy] = restrict_row(r[o - 1], r[o], r[o + 1]);
     }
-    acc += (dz == 0 ? T(1) : h) * pl;
+    pl[dz] = restrict_sum(row[0], row[1], row[2]);
   }
-  return acc;
+  return restrict_sum(pl[0], pl[1], pl[2]);
 }
 
 // Multilinear interpolant of the coarse correction at fine node (i, j[, k]):
@@ -1021,6 +1033,234 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     if (tid == 0)
       I.partials[bx + (long)gridDim.x * (by + (long)gridDim.y * zc)] = t;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Residual and restriction in one pass on the 3D levels k_sweep3 runs (the
+// constant-coefficient and mass-shifted kinds): the coarse right-hand side
+// b_c = R (b - A x), R = P^T, without storing r.  A block computes r on the
+// k_sweep3 tile (128 x 4 unknowns, two per thread and plane, with the same
+// plane parts and sums, so r is bitwise that of the k_sweep3 residual) and
+// on one more row, the next tile's first, with a fifth wave: coarse row J
+// reads fine rows 2J-1 .. 2J+1, and the rows j0 .. j0+4 (j0 odd) hold those
+// of the tile's coarse rows (j0+1)/2 and (j0+3)/2.  In x a lane forms the
+// row sum of coarse column (i+1)/2 from its two unknowns and its right
+// neighbour's first (a lane shift); the last lane's coarse column needs the
+// next tile's first column, so the three fine columns of that coarse column
+// are written to the residual vector (Item::e) and k_restrict_xcols
+// restricts it afterwards.  In z a block marches the fine planes
+// 2K0-1 .. 2K1+1 of its coarse planes K0 .. K1 (plane 2K1+1 is also the next
+// chunk's first): plane 2K-1 opens coarse plane K, 2K adds to it and 2K+1
+// completes it, with the sums of restrict_node in its order, so b_c is
+// bitwise that of the separate residual and restriction launches.
+//   Item: a = x (XIN: its even half, a2 the odd half), b = b (layout lay),
+//   c = b_c (colour-split when flag), e = the fine residual vector.
+// ---------------------------------------------------------------------------
+constexpr int RR_TY = SW_TY + 1;  // fine rows computed per tile
+constexpr int RR_LY = RR_TY + 2;  // staged rows of x
+constexpr int RR_THREADS = 64 * RR_TY;
+
+template <typename T, int KIND, bool XIN>
+__global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilParams<T> op,
+                                                                int kzc, int nzc, int remap,
+                                                                Batch B) {
+  static_assert(KIND != OP_KAPPA, "the per-cell operator has its own parts");
+  constexpr bool MASS = KIND == OP_MASS;
+  constexpr int NS = MASS ? 4 : 3;
+  __shared__ __align__(16) T sx[2][RR_LY][SW_LX];
+  __shared__ T srow[RR_TY][64];
+  const int n = g.n, m = n - 1, nco = n >> 1, mc = nco - 1;
+  const long sy = g.sy, sz = g.sz;
+  const long syc = nco + 1, szc = syc * syc;
+  int bx = blockIdx.x, by = blockIdx.y, bz = blockIdx.z;
+  if (remap) {
+    const int gxy = gridDim.x * gridDim.y;
+    const int nb = gxy * gridDim.z;
+    const int L = xcd_remap(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), nb);
+    bx = L % gridDim.x;
+    by = (L / gridDim.x) % gridDim.y;
+    bz = L / gxy;
+  }
+  const int item = bz / nzc, zc = bz % nzc;
+  const Item& I = B.it[item];
+  const T* __restrict__ x = (const T*)I.a;
+  const T* __restrict__ xodd = XIN ? (const T*)I.a2 : nullptr;
+  const T* __restrict__ b = (const T*)I.b;
+  T* __restrict__ bc = (T*)I.c;
+  T* __restrict__ rv = (T*)const_cast<void*>(I.e);
+  const long blay = I.lay;
+  const long clay = I.flag ? (syc * szc + 1) / 2 : 0;
+  const int i0 = 1 + bx * SW_TX, j0 = 1 + by * SW_TY;
+  const int K0 = 1 + zc * kzc, K1 = min(K0 + kzc - 1, mc);
+  const int k0 = 2 * K0 - 1, k1 = 2 * K1 + 1;
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int i = i0 + 2 * tx, j = j0 + ty;
+  const bool row_ok = j <= m;
+  const bool ok0 = row_ok && i <= m, ok1 = row_ok && i + 1 <= m;
+
+  // x planes staged as in k_sweep3 (columns i0-1 .. i0+128, rows
+  // j0-1 .. j0+5), element e = tid + RR_THREADS q
+  constexpr int NX = (SW_LX * RR_LY + RR_THREADS - 1) / RR_THREADS;
+  int xoff[NX];
+  T xpf[NX];
+  auto xcol = [&](int cc) {
+    return XIN ? (cc < SW_LX / 2 ? 2 * cc : 2 * (cc - SW_LX / 2) + 1) : cc;
+  };
+#pragma unroll
+  for (int q = 0; q < NX; ++q) {
+    const int e = tid + RR_THREADS * q;
+    const int r = e / SW_LX, c = xcol(e - r * SW_LX);
+    const int gi = i0 - 1 + c, gj = j0 - 1 + r;
+    xoff[q] = min(gi, n) + min(gj, n) * (int)sy;  // always inside the grid
+  }
+  auto prefetch_x = [&](int z) {
+    if constexpr (XIN) {
+      const long zb = (long)min(z, n) * sz;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) {
+        const long p = zb + xoff[q];
+        xpf[q] = ((p & 1) ? xodd : x)[p >> 1];
+      }
+    } else {
+      const T* __restrict__ xz = x + (long)min(z, n) * sz;
+#pragma unroll
+      for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
+    }
+  };
+  auto commit_x = [&](int s) {
+    T* dst = &sx[s][0][0];
+#pragma unroll
+    for (int q = 0; q < NX; ++q) {
+      const int e = tid + RR_THREADS * q;
+      if (e < SW_LX * RR_LY) {
+        const int r = e / SW_LX;
+        dst[r * SW_LX + xcol(e - r * SW_LX)] = xpf[q];
+      }
+    }
+  };
+  auto window_x = [&](int s, T (&w)[3][4]) {
+    using V2 = typename Vec2<T>::type;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      const V2* row = reinterpret_cast<const V2*>(&sx[s][ty + r][0]);
+      const V2 a = row[tx], c = row[tx + 1];
+      w[r][0] = a.x;
+      w[r][1] = a.y;
+      w[r][2] = c.x;
+      w[r][3] = c.y;
+    }
+  };
+  const long pb0 = min(i, n - 1) + min(j, n) * sy;  // clamped into the grid
+  T bpf[2] = {T(0), T(0)};
+  auto prefetch_b = [&](int k) {
+    const long p = pb0 + (long)min(k, n) * sz;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) bpf[u] = b[lay_idx(p + u, blay)];
+  };
+
+  // carried plane parts, as in k_sweep3's residual
+  T s2[2][NS], s1[2][NS], g1[2], x1[2], f1[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    g1[q] = x1[q] = f1[q] = T(0);
+#pragma unroll
+    for (int t = 0; t < NS; ++t) s2[q][t] = s1[q][t] = T(0);
+  }
+  // waves 0 and 1 each own one coarse node per lane: column 64 bx + 1 + tx
+  // (not the last lane's), row 2 by + 1 + ty
+  const int ic = 64 * bx + 1 + tx, jc = 2 * by + 1 + ty;
+  const bool own = ty < 2 && tx < 63 && ic <= mc && jc <= mc;
+  const bool edge_l = tx == 63 && 64 * bx + 64 <= mc;  // columns of a boundary coarse column
+  const bool edge_f = tx == 0 && bx > 0;
+  T plm = T(0), part = T(0);  // plane 2K-1's row sum; m / 2 + c of coarse plane K
+  prefetch_x(k0 - 1);
+  for (int p = k0 - 1; p <= k1 + 1; ++p) {
+    commit_x(p & 1);
+    prefetch_x(p + 1);
+    const T bcur[2] = {bpf[0], bpf[1]};  // b of plane p-1
+    prefetch_b(p);
+    __syncthreads();
+    T w[3][4];
+    window_x(p & 1, w);
+    T sn[2][NS], gn[2], xn[2], fn[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      plane_parts<T>(w, q, sn[q][0], sn[q][1], sn[q][2]);
+      if constexpr (MASS) sn[q][3] = w[1][q + 1];
+      T ea, eb;
+      plane_parts<T>(w, q, ea, eb, gn[q]);
+      fn[q] = MASS ? ea + eb : T(0);
+      xn[q] = w[1][q + 1];
+    }
+    const int k = p - 1;
+    if (k >= k0) {
+      T res[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        T ax;
+        if constexpr (MASS)
+          ax = stencil3_mass_sum(op, x1[q], g1[q], f1[q], s2[q][0], sn[q][0], s2[q][1],
+                                 sn[q][1], s2[q][2], sn[q][2], s2[q][3], sn[q][3]);
+        else
+          ax = stencil3_const_sum(op, x1[q], g1[q], s2[q][0], sn[q][0], s2[q][1], sn[q][1],
+                                  s2[q][2], sn[q][2]);
+        res[q] = (q == 0 ? ok0 : ok1) ? bcur[q] - ax : T(0);
+      }
+      if (ty < SW_TY && row_ok) {
+        const long pk = i + j * sy + (long)k * sz;
+        if (edge_l) {
+          rv[pk] = res[0];
+          rv[pk + 1] = res[1];
+        }
+        if (edge_f) rv[pk] = res[0];
+      }
+      const T rn = __shfl_down(res[0], 1);  // the right neighbour's first column
+      srow[ty][tx] = restrict_row(res[0], res[1], rn);
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+      for (int t = 0; t < NS; ++t) {
+        s2[q][t] = s1[q][t];
+        s1[q][t] = sn[q][t];
+      }
+      g1[q] = gn[q];
+      x1[q] = xn[q];
+      f1[q] = fn[q];
+    }
+    if (k >= k0) {
+      __syncthreads();
+      if (ty < 2) {
+        const T pl = restrict_sum(srow[2 * ty][tx], srow[2 * ty + 1][tx], srow[2 * ty + 2][tx]);
+        if (k & 1) {
+          // plane 2K+1 completes coarse plane K = (k-1)/2 and opens K+1
+          if (k > k0 && own) bc[lay_idx(ic + jc * syc + (long)(k >> 1) * szc, clay)] =
+              fma(T(0.5), pl, part);
+          plm = pl;
+        } else {
+          part = fma(T(0.5), plm, pl);
+        }
+      }
+    }
+  }
+}
+
+// The coarse columns 64, 128, ... (<= n/2 - 1) that k_resid_restrict3 leaves
+// to the end: restrict_node from the residual's fine columns it wrote.
+//   Item: a = the fine residual, c = b_c (layout lay).
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_xcols(Geo gf, int ncols, Batch B) {
+  const Item& I = B.it[blockIdx.y];
+  const int mc = (gf.n >> 1) - 1;
+  const long q = blockIdx.x * 256L + threadIdx.x;
+  const long per = (long)mc * mc;
+  if (q >= per * ncols) return;
+  const int col = (int)(q / per);
+  const int jj = (int)(q % mc) + 1, kk = (int)((q / mc) % mc) + 1;
+  const int ii = 64 * (col + 1);
+  const long syc = (gf.n >> 1) + 1;
+  ((T*)I.c)[lay_idx(ii + jj * syc + (long)kk * syc * syc, I.lay)] =
+      restrict_node<T, 3>(dgeo(gf), (const T*)I.a, ii, jj, kk);
 }
 
 // ---------------------------------------------------------------------------
@@ -2301,6 +2541,49 @@ static void launch_sweep3_split(const Geo& g, const StencilParams<T>& op, bool z
 
 bool use_split_x(const Geo& g) { return use_sweep3(g); }
 
+template <typename T>
+void launch_resid_restrict(const Geo& g, const StencilParams<T>& op, bool xin, const Batch& B,
+                           hipStream_t s) {
+  const int m = g.n - 1, mc = (g.n >> 1) - 1;
+  // coarse planes per block: half the fine planes of a k_sweep3 block, and
+  // in FP64 at most 512 blocks per launch (about 110 VGPRs: at most three
+  // of these 5-wave blocks fit on a CU, two per CU measured fastest, 4%
+  // faster 256^3 solves than four per CU in two rounds)
+  int kzc = std::max(1, sweep3_kz(m, (int)sizeof(T)) / 2);
+  if (sizeof(T) == 8) {
+    const long xy = (long)cdiv(m, SW_TX) * cdiv(mc, 2) * B.count;
+    while (kzc < mc && xy * (long)cdiv(mc, kzc) > 512) ++kzc;
+  }
+  const int nzc = (int)cdiv(mc, kzc);
+  const dim3 gr(cdiv(m, SW_TX), cdiv(mc, 2), (unsigned)(nzc * B.count)), bl(64, RR_TY);
+  auto go = [&](auto kc, auto xc) {
+    constexpr int K = decltype(kc)::value;
+    constexpr bool X = decltype(xc)::value;
+    hipLaunchKernelGGL((k_resid_restrict3<T, K, X>), gr, bl, 0, s, g, op, kzc, nzc,
+                       sweep3_remap(), B);
+  };
+  using MassK = std::integral_constant<int, OP_MASS>;
+  using ConstK = std::integral_constant<int, OP_CONST>;
+  if (op.kind == OP_MASS) {
+    if (xin) go(MassK{}, std::true_type{});
+    else go(MassK{}, std::false_type{});
+  } else {
+    if (xin) go(ConstK{}, std::true_type{});
+    else go(ConstK{}, std::false_type{});
+  }
+}
+
+int resid_restrict_xcols(const Geo& gf) { return ((gf.n >> 1) - 1) / 64; }
+
+template <typename T>
+void launch_restrict_xcols(const Geo& gf, const Batch& B, hipStream_t s) {
+  const int mc = (gf.n >> 1) - 1, ncols = resid_restrict_xcols(gf);
+  if (ncols == 0) return;
+  const long total = (long)mc * mc * ncols;
+  hipLaunchKernelGGL((k_restrict_xcols<T>), dim3((unsigned)cdiv(total, 256), B.count), dim3(256),
+                     0, s, gf, ncols, B);
+}
+
 namespace {
 // The last FP32 smoothing step of a refinement cycle with the refinement
 // update fused (IRU): natural output (xl 0) or split input (xl 3).
@@ -2730,6 +3013,9 @@ void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfi
   template void launch_apply_dot<T>(const Geo&, const StencilParams<T>&, const Batch&,      \
                                     hipStream_t);                                           \
   template void launch_restrict<T>(const Geo&, const Geo&, const Batch&, hipStream_t);      \
+  template void launch_resid_restrict<T>(const Geo&, const StencilParams<T>&, bool,         \
+                                         const Batch&, hipStream_t);                        \
+  template void launch_restrict_xcols<T>(const Geo&, const Batch&, hipStream_t);            \
   template void launch_prolong_add<T>(const Geo&, const Geo&, const Batch&, hipStream_t);   \
   template void launch_coarse_solve<T>(const Geo&, int, const Batch&, hipStream_t);         \
   template void launch_norm2_partial<T>(const Geo&, const Batch&, hipStream_t);             \

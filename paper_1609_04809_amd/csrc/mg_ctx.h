@@ -67,6 +67,8 @@ enum OpCode {
   OC_CSR_APPLY_DOT,
   OC_PCG,            // CG vector kernel (sub: PcgOp), pointers in ext[]
   OC_ZERO_BOUNDARY,  // c = 0 on the boundary nodes (FP64)
+  OC_RESID_RESTRICT,  // b_c = R (b - A x) in one pass (sub: x colour-split)
+  OC_RESTRICT_XCOLS,  // the coarse columns OC_RESID_RESTRICT leaves
 };
 
 // CG vector kernels (OpRec::sub of OC_PCG)

@@ -650,6 +650,57 @@ void emit_residual(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b, T
   sink(o);
 }
 
+// Whether the residual of level l and its restriction run as one pass
+// (k_resid_restrict3): 3D matrix-free levels k_sweep3 runs, constant or
+// mass-shifted operator, not with MG_FLAG_NO_FUSE.
+template <typename T>
+bool fuse_resid_restrict(const mg_ctx* c, int l) {
+  const Level& Lv = c->lv[l];
+  return !c->csr && !(c->o.flags & MG_FLAG_NO_FUSE) && l + 1 < c->L && use_split_x(Lv.g) &&
+         Bufs<T>::st(const_cast<Level&>(Lv)).kind != OP_KAPPA;
+}
+
+// b_{l+1} = R (b - A x) on level l: one pass where fuse_resid_restrict
+// (plus the few coarse columns it leaves), else the residual into the
+// level's r and the restriction.  split: x colour-split, even half in
+// buffer split[0], odd half in split[1].
+template <typename T>
+void emit_resid_restrict(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b,
+                         const int* split) {
+  Level& Lv = c->lv[l];
+  T* const r = Bufs<T>::r(Lv);
+  T* const bc = Bufs<T>::b(c->lv[l + 1]);
+  const long clay = b_split_half(c, l + 1, Bufs<T>::prec);  // the coarse b's layout
+  if (fuse_resid_restrict<T>(c, l)) {
+    OpRec o = base_op<T>(c, OC_RESID_RESTRICT, l);
+    o.item.a = x;
+    o.item.b = b;
+    o.item.c = bc;
+    o.item.e = r;
+    o.item.flag = clay != 0;
+    if (split) {
+      o.sub = 1;
+      o.item.a = Bufs<T>::xs(Lv, split[0]);
+      o.item.a2 = Bufs<T>::xs(Lv, split[1]) + (Lv.g.nodes + 1) / 2;
+    }
+    sink(o);
+    if (resid_restrict_xcols(Lv.g) > 0) {
+      OpRec f = base_op<T>(c, OC_RESTRICT_XCOLS, l);
+      f.item.lay = clay;
+      f.item.a = r;
+      f.item.c = bc;
+      sink(f);
+    }
+    return;
+  }
+  emit_residual<T>(c, sink, l, x, b, r, nullptr, split);
+  OpRec o = base_op<T>(c, OC_RESTRICT, l);
+  o.item.lay = clay;
+  o.item.a = r;
+  o.item.c = bc;
+  sink(o);
+}
+
 // Partial sums of ||b - A x||^2 on level l and, into xout, the first
 // pre-smoothing step of the next cycle from x.
 template <typename T>
@@ -902,13 +953,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
                     l == 0 && head_done && split_iterate<T>(c, 0), s0 ? c->s0at : nullptr);
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
-    emit_residual<T>(c, sink, l, cur[l], bb[l], Bufs<T>::r(c->lv[l]), nullptr,
-                     s0 ? c->s0at : nullptr);
-    OpRec o = base_op<T>(c, OC_RESTRICT, l);
-    o.item.lay = b_split_half(c, l + 1, Bufs<T>::prec);  // the coarse b it writes
-    o.item.a = Bufs<T>::r(c->lv[l]);
-    o.item.c = Bufs<T>::b(c->lv[l + 1]);
-    sink(o);
+    emit_resid_restrict<T>(c, sink, l, cur[l], bb[l], s0 ? c->s0at : nullptr);
     if (l + 1 == L - 1) {
       visit(l + 1, kind, true);
     } else {
@@ -1210,7 +1255,7 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool
 // profiling hooks: bracket level-0 launches of the selected kernel class
 enum ProfKind {
   PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4, PK_SMOOTH_PRO = 5,
-  PK_SMOOTH_IR = 6
+  PK_SMOOTH_IR = 6, PK_RESID_RESTRICT = 7
 };
 
 int prof_class(const OpRec& o) {
@@ -1225,7 +1270,9 @@ int prof_class(const OpRec& o) {
     case OC_CSR_HEAD:
     case OC_APPLY_DOT:
     case OC_CSR_APPLY_DOT: return PK_RESID;
-    case OC_RESTRICT: return PK_RESTRICT;
+    case OC_RESTRICT:
+    case OC_RESTRICT_XCOLS: return PK_RESTRICT;
+    case OC_RESID_RESTRICT: return PK_RESID_RESTRICT;
     case OC_PROLONG: return PK_PROLONG;
     default: return -1;
   }
@@ -1360,6 +1407,8 @@ void launch_typed(const OpRec& o, const Batch& B, hipStream_t s) {
                          ((o.sub >> 9) & 1) != 0);
       break;
     case OC_RESTRICT: launch_restrict<T>(o.g, o.gc, B, s); break;
+    case OC_RESID_RESTRICT: launch_resid_restrict<T>(o.g, params_of<T>(o), o.sub == 1, B, s); break;
+    case OC_RESTRICT_XCOLS: launch_restrict_xcols<T>(o.g, B, s); break;
     case OC_PROLONG: launch_prolong_add<T>(o.g, o.gc, B, s); break;
     case OC_COARSE: launch_coarse_solve<T>(o.g, o.m, B, s); break;
     case OC_NORM2: launch_norm2_partial<T>(o.g, B, s); break;
@@ -1965,7 +2014,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
 
 mg_status mg_profile_enable(mg_ctx* c, int kernel_id, int enable) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > 6) return fail(MG_E_ARG, "kernel_id must be 0..6");
+  if (kernel_id < 0 || kernel_id > 7) return fail(MG_E_ARG, "kernel_id must be 0..7");
   c->prof_kernel = kernel_id;
   c->prof_on = enable != 0;
   c->prof_launches = 0;

@@ -481,3 +481,36 @@ def test_ir_residual_cast_and_update_fusions_agree_bitwise(dim, n, levels, kap, 
         _, k_or, _, _ = O.solve_ir(H, bi, 1e-9)
         assert abs(outs[0][0] - k_or) <= 1
 
+
+
+@pytest.mark.parametrize("n,levels,prec,sigma,nu", [
+    (160, 6, "fp64", 0.0, (2, 2)),      # two x tiles: the coarse column 64 restricted apart
+    (96, 5, "fp64", 50.0, (1, 2)),      # mass-shifted operator
+    (320, 7, "fp32_ir", 0.0, (2, 2)),   # three x tiles, colour-split FP32 iterates
+    (64, 5, "fp64", 0.0, (3, 1)),
+])
+def test_residual_and_restriction_in_one_pass_agree_bitwise(n, levels, prec, sigma, nu):
+    """The residual restricted in the same pass (k_resid_restrict3, r not
+    stored) gives bitwise the iterate and residual history of the separate
+    residual and restriction launches (MG_FLAG_NO_FUSE), and the oracle's
+    cycle count +-1 where the oracle runs."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    bi = W.rhs_uniform(3, n, 31)
+    b = dev_full(3, n, bi)
+    outs = []
+    for flags in (0, FLAG_NO_FUSE):
+        print(f"[rr] n={n} prec={prec} sigma={sigma} flags={flags}", flush=True)
+        with Solver(3, n, levels, precision=prec, sigma=sigma, nu_pre=nu[0], nu_post=nu[1],
+                    flags=flags) as S:
+            u, k, hist, st = S.solve(b, 1e-9)
+            assert st == "ok"
+            outs.append((k, hist, host_full(u)))
+    assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
+    assert np.array_equal(outs[0][2], outs[1][2])
+    if n <= 96:
+        H = O.build_hierarchy(3, n, levels, sigma=sigma, nu_pre=nu[0], nu_post=nu[1],
+                              fp32=prec != "fp64")
+        solve = O.solve if prec == "fp64" else O.solve_ir
+        _, k_or, _, _ = solve(H, bi, 1e-9)
+        assert abs(outs[0][0] - k_or) <= 1
