@@ -1047,7 +1047,7 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 // row sum of coarse column (i+1)/2 from its two unknowns and its right
 // neighbour's first (a lane shift); the last lane's coarse column needs the
 // next tile's first column, so the three fine columns of that coarse column
-// are written to the residual vector (Item::e) and k_restrict_xcols
+// are written to Item::e, packed as edge_idx gives, and k_restrict_xcols
 // restricts it afterwards.  In z a block marches the fine planes
 // 2K0-1 .. 2K1+1 of its coarse planes K0 .. K1 (plane 2K1+1 is also the next
 // chunk's first): plane 2K-1 opens coarse plane K, 2K adds to it and 2K+1
@@ -1056,6 +1056,12 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
 //   Item: a = x (XIN: its even half, a2 the odd half), b = b (layout lay),
 //   c = b_c (colour-split when flag), e = the fine residual vector.
 // ---------------------------------------------------------------------------
+// Packed fine columns 2I-1, 2I, 2I+1 (c = 0, 1, 2) of the coarse column
+// I = 64 (col + 1) at fine row j, plane k: consecutive rows are adjacent.
+__device__ __forceinline__ long edge_idx(int n, int col, int k, int j, int c) {
+  return (((long)col * (n + 1) + k) * (n + 1) + j) * 3 + c;
+}
+
 constexpr int RR_TY = SW_TY + 1;  // fine rows computed per tile
 constexpr int RR_LY = RR_TY + 2;  // staged rows of x
 constexpr int RR_THREADS = 64 * RR_TY;
@@ -1207,12 +1213,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
         res[q] = (q == 0 ? ok0 : ok1) ? bcur[q] - ax : T(0);
       }
       if (ty < SW_TY && row_ok) {
-        const long pk = i + j * sy + (long)k * sz;
         if (edge_l) {
-          rv[pk] = res[0];
-          rv[pk + 1] = res[1];
+          rv[edge_idx(n, bx, k, j, 0)] = res[0];
+          rv[edge_idx(n, bx, k, j, 1)] = res[1];
         }
-        if (edge_f) rv[pk] = res[0];
+        if (edge_f) rv[edge_idx(n, bx - 1, k, j, 2)] = res[0];
       }
       const T rn = __shfl_down(res[0], 1);  // the right neighbour's first column
       srow[ty][tx] = restrict_row(res[0], res[1], rn);
@@ -1246,21 +1251,33 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
 }
 
 // The coarse columns 64, 128, ... (<= n/2 - 1) that k_resid_restrict3 leaves
-// to the end: restrict_node from the residual's fine columns it wrote.
-//   Item: a = the fine residual, c = b_c (layout lay).
+// to the end, from the fine columns it packed (edge_idx), in the
+// arithmetic of restrict_node.
+//   Item: a = the packed fine columns, c = b_c (layout lay).
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_xcols(Geo gf, int ncols, Batch B) {
   const Item& I = B.it[blockIdx.y];
-  const int mc = (gf.n >> 1) - 1;
+  const int n = gf.n, mc = (n >> 1) - 1;
   const long q = blockIdx.x * 256L + threadIdx.x;
   const long per = (long)mc * mc;
   if (q >= per * ncols) return;
   const int col = (int)(q / per);
   const int jj = (int)(q % mc) + 1, kk = (int)((q / mc) % mc) + 1;
-  const int ii = 64 * (col + 1);
-  const long syc = (gf.n >> 1) + 1;
-  ((T*)I.c)[lay_idx(ii + jj * syc + (long)kk * syc * syc, I.lay)] =
-      restrict_node<T, 3>(dgeo(gf), (const T*)I.a, ii, jj, kk);
+  const T* __restrict__ v = (const T*)I.a;
+  T pl[3];
+#pragma unroll
+  for (int dz = 0; dz < 3; ++dz) {
+    T row[3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy) {
+      const long e = edge_idx(n, col, 2 * kk + dz - 1, 2 * jj + dy - 1, 0);
+      row[dy] = restrict_row(v[e], v[e + 1], v[e + 2]);
+    }
+    pl[dz] = restrict_sum(row[0], row[1], row[2]);
+  }
+  const long syc = (n >> 1) + 1;  // coarse nodes per direction
+  ((T*)I.c)[lay_idx(64 * (col + 1) + jj * syc + (long)kk * syc * syc, I.lay)] =
+      restrict_sum(pl[0], pl[1], pl[2]);
 }
 
 // ---------------------------------------------------------------------------

@@ -226,16 +226,18 @@ template <typename T>
 void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const Batch& B,
                      hipStream_t s, int xl = 0, bool cast = false);
 // b_c = R (b - A x) on a 3D level where use_split_x(g), constant-coefficient
-// or mass-shifted operator, without storing r (r's fine columns around the
-// coarse columns 64, 128, ... are written to e; launch_restrict_xcols
-// restricts those columns afterwards):  a = x (xin: its even half, a2 the
-// odd half), b = b (layout lay), c = b_c (colour-split when flag), e = r.
+// or mass-shifted operator, without storing r (the three fine columns of
+// r under each of the coarse columns 64, 128, ... go to e, packed;
+// launch_restrict_xcols restricts those columns afterwards):  a = x (xin:
+// its even half, a2 the odd half), b = b (layout lay), c = b_c
+// (colour-split when flag), e = scratch of the level's node count.
 // Bitwise the result of launch_residual followed by launch_restrict.
 template <typename T>
 void launch_resid_restrict(const Geo& g, const StencilParams<T>& op, bool xin, const Batch& B,
                            hipStream_t s);
 // The coarse columns launch_resid_restrict leaves (their number:
-// resid_restrict_xcols(gf)):  a = r, c = b_c (layout lay).
+// resid_restrict_xcols(gf)):  a = the packed columns (its e), c = b_c
+// (layout lay).
 int resid_restrict_xcols(const Geo& gf);
 template <typename T>
 void launch_restrict_xcols(const Geo& gf, const Batch& B, hipStream_t s);
