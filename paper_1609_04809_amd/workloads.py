@@ -231,7 +231,7 @@ def serving_trace(num=2000, rate=200.0, seed=0, burst=False, kappa_frac=0.0):
     the variable-coefficient problem of the 192^3 workload, kappa = exp(g),
     g ~ N(0, 1) per cell from the request's seed.  (In 2D the rediscretised
     coarse operators of such coefficient fields make the cycle iteration
-    diverge for some fields at n >= 256, in the CPU oracle as on the GPU.)
+    diverge for some fields at n >= 512, in the CPU oracle as on the GPU.)
     Returns a list of dicts (t_arrival, dim, n, levels, seed, kappa).
     """
     rng = np.random.default_rng(seed)
