@@ -83,7 +83,6 @@ struct Request {
   double rho = 1.0;
   bool waiting = false;
   int lane = 0;  // the stream its launches and read-backs go to
-  double hold_until = 0;  // aligning with a same-shape request: held until then
   hipEvent_t ev = nullptr;
   double* pin = nullptr;  // 2 pinned doubles: ||r||^2, ||b||^2
   // b: host copy to the pinned staging (copy thread), then one DMA; u: DMA
@@ -135,12 +134,13 @@ struct mg_server {
   static constexpr int kLanes = 4;
   hipStream_t lanes[kLanes] = {};
   static constexpr int kStepsAhead = 8;
-  // longest wait of a request that aligns its iteration with another one's
-  static constexpr double kHoldS = 1e-3;
   // how many more active requests than the least loaded lane a lane may
   // hold and still be chosen for a request of a shape it runs
   static constexpr int kLaneSlack = 4;
   hipEvent_t step_ev[kLanes][kStepsAhead] = {};
+  // per shape in a lane: a request of that shape, the smallest position
+  // of those inside an iteration (scheduler scratch)
+  std::vector<std::pair<const Request*, size_t>> lag;
   int step_head[kLanes] = {};
   // host copies between pageable request memory and the pinned staging run
   // on their own threads, so the scheduler keeps launching meanwhile
@@ -362,7 +362,6 @@ void after_readback(mg_server* S, std::list<std::unique_ptr<Request>>::iterator 
   Request& r = **itr;
   r.waiting = false;
   r.pc = 0;
-  r.hold_until = 0;
   int st = -1;
   if (r.phase == 0) {
     const double nb2 = r.pin[1];
@@ -426,33 +425,47 @@ void step_lane(mg_server* S, int lane, std::vector<const OpRec*>& ops,
   hipStream_t stream = S->lanes[lane];
   ops.clear();
   owners.clear();
-  const double t = now_s();
+  // Laggard first: among the runnable requests of one shape in this lane
+  // inside their iterations, only those at the smallest position advance,
+  // so a request that starts an iteration (or fell behind) catches up
+  // with the others of its shape, and from then on they run as batched
+  // launches.  The requests at the smallest position always advance.
+  auto& lag = S->lag;
+  lag.clear();
+  for (auto& rp : S->active) {
+    const Request& r = *rp;
+    if (r.stage != Request::RUN || r.waiting || r.lane != lane || r.phase != 1) continue;
+    bool found = false;
+    for (auto& g : lag)
+      if (same_ops(*g.first, r)) {
+        g.second = std::min(g.second, r.pc);
+        found = true;
+        break;
+      }
+    if (!found) lag.emplace_back(&r, r.pc);
+  }
+  bool deferred = false;
   for (auto& rp : S->active) {
     Request& r = *rp;
     if (r.stage != Request::RUN || r.waiting || r.lane != lane) continue;
-    if (r.phase == 1 && r.pc == 0 && r.hold_until >= 0) {
-      // about to start an iteration while a request of its shape in this
-      // lane is inside one: wait (at most kHoldS) for that one to come
-      // back to the start, so that the two iterations run as batched
-      // launches from then on
-      bool partner = false;
-      for (auto& qp : S->active) {
-        const Request& q = *qp;
-        partner |= &q != &r && q.lane == lane && q.stage == Request::RUN && q.phase == 1 &&
-                   (q.pc > 0 || q.waiting) && same_ops(q, r);
+    if (r.phase == 1) {
+      bool behind = false;
+      for (auto& g : lag)
+        if (same_ops(*g.first, r)) {
+          behind = r.pc > g.second;
+          break;
+        }
+      if (behind) {
+        deferred = true;
+        continue;
       }
-      if (partner) {
-        if (r.hold_until == 0) r.hold_until = t + mg_server::kHoldS;
-        if (t < r.hold_until) continue;
-      }
-      r.hold_until = -1;  // held once (or not at all) in this iteration
     }
     const std::vector<OpRec>& list = r.phase == 0 ? r.pro : r.it;
     ops.push_back(&list[r.pc]);
     owners.push_back(&r);
   }
   if (ops.empty()) return;
-  if (ops.size() == 1) {
+  if (ops.size() == 1 && !deferred) {
     // a lone runnable request has nothing to be batched with: queue the
     // rest of its list at once rather than one launch per step, which
     // would leave the GPU waiting for the scheduler between its small
