@@ -309,7 +309,13 @@ mg_status mg_apply_smooth(mg_ctx* ctx, int level, int prec, int step,
 mg_status mg_apply_restrict(mg_ctx* ctx, int level, int prec, const void* r,
                             void* b_coarse, void* stream);
 
-/* b_coarse = P^T (b - A_l x), fused (no fine residual stored). */
+/* b_coarse = P^T (b - A_l x) (Algorithm 1: residual, then its restriction,
+ * Sec. 5.4).  On 3D matrix-free levels with n >= 32 and the constant or
+ * mass-shifted operator one pass, the fine residual not stored (the
+ * context's residual buffer of the level serves as scratch), unless the
+ * context was set up with MG_FLAG_NO_FUSE; elsewhere the residual and the
+ * restriction.  b_coarse: (n_l/2+1)^dim elements, boundary entries set to
+ * 0. */
 mg_status mg_apply_residual_restrict(mg_ctx* ctx, int level, int prec,
                                      const void* x, const void* b,
                                      void* b_coarse, void* stream);

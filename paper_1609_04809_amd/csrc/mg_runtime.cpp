@@ -660,16 +660,16 @@ bool fuse_resid_restrict(const mg_ctx* c, int l) {
          Bufs<T>::st(const_cast<Level&>(Lv)).kind != OP_KAPPA;
 }
 
-// b_{l+1} = R (b - A x) on level l: one pass where fuse_resid_restrict
-// (plus the few coarse columns it leaves), else the residual into the
-// level's r and the restriction.  split: x colour-split, even half in
-// buffer split[0], odd half in split[1].
+// b_{l+1} = R (b - A x) on level l (into bc_out, else the level's b): one
+// pass where fuse_resid_restrict (plus the few coarse columns it leaves),
+// else the residual into the level's r and the restriction.  split: x
+// colour-split, even half in buffer split[0], odd half in split[1].
 template <typename T>
 void emit_resid_restrict(mg_ctx* c, const Sink& sink, int l, const T* x, const T* b,
-                         const int* split) {
+                         const int* split, T* bc_out = nullptr) {
   Level& Lv = c->lv[l];
   T* const r = Bufs<T>::r(Lv);
-  T* const bc = Bufs<T>::b(c->lv[l + 1]);
+  T* const bc = bc_out ? bc_out : Bufs<T>::b(c->lv[l + 1]);
   const long clay = b_split_half(c, l + 1, Bufs<T>::prec);  // the coarse b's layout
   if (fuse_resid_restrict<T>(c, l)) {
     OpRec o = base_op<T>(c, OC_RESID_RESTRICT, l);
@@ -1941,14 +1941,9 @@ mg_status mg_apply_residual_restrict(mg_ctx* c, int level, int prec, const void*
   const Sink sink = launch_sink(c, as_stream(stream));
   return typed(prec, [&](auto tag) {
     using T = decltype(tag);
-    T* r = Bufs<T>::r(c->lv[level]);
+    // (natural layouts: check_step set c->natural)
     emit_fill<T>(c, sink, level + 1, (T*)bc);
-    emit_residual<T>(c, sink, level, (const T*)x, (const T*)b, r, nullptr);
-    OpRec o = base_op<T>(c, OC_RESTRICT, level);
-    o.item.lay = b_split_half(c, level + 1, Bufs<T>::prec);
-    o.item.a = r;
-    o.item.c = bc;
-    sink(o);
+    emit_resid_restrict<T>(c, sink, level, (const T*)x, (const T*)b, nullptr, (T*)bc);
   });
 }
 

@@ -190,3 +190,48 @@ def test_one_vcycle_matches_oracle(case):
     S.vcycle(xd, dev_full(dim, n, b32, "float32"))
     got32 = host_int(dim, n, xd)
     assert np.linalg.norm(got32 - want32) <= 1e-5 * np.linalg.norm(want32)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [160, 272])
+def test_fused_residual_restriction_across_tiles(n, prec):
+    """mg_apply_residual_restrict on 3D levels with two and three x tiles of
+    128 unknowns, where the pass restricts every coarse column but 64 (and
+    128) itself and leaves those to k_restrict_xcols: element by element
+    against the matrix-free oracle's P^T (b - A x), and bitwise against the
+    separate residual and restriction (MG_FLAG_NO_FUSE)."""
+    torch = torch_cuda()
+    from oracle import matfree as MF
+    from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    dim, levels = 3, 5
+    nc = n // 2
+    tdt = "float64" if prec == "fp64" else "float32"
+    eps = EPS64 if prec == "fp64" else EPS32
+    rng = np.random.default_rng(n + (0 if prec == "fp64" else 1))
+    N = (n - 1) ** dim
+    x = _round(rng.uniform(-1, 1, N), prec)
+    b = _round(rng.uniform(-1, 1, N), prec)
+    print(f"[rr-step] n={n} {prec}", flush=True)
+    outs = []
+    for flags in (0, FLAG_NO_FUSE):
+        with Solver(dim, n, levels, precision="fp32_ir", flags=flags) as S:
+            bc = torch.full(((nc + 1) ** dim,), 7.0, dtype=getattr(torch, tdt), device="cuda")
+            S.residual_restrict(0, dev_full(dim, n, x, tdt), dev_full(dim, n, b, tdt), bc)
+            torch.cuda.synchronize()
+            outs.append(bc.cpu().numpy().astype(np.float64))
+    assert np.array_equal(outs[0], outs[1])
+    Ke = O.element_matrix(dim, 1.0 / n)
+    if prec == "fp32":
+        Ke = Ke.astype(np.float32).astype(np.float64)
+    xf, bf = W.interior_to_full(dim, n, x), W.interior_to_full(dim, n, b)
+    want = MF.restrict(dim, n, bf.reshape((n + 1,) * dim) - MF.apply(dim, n, None, xf, Ke))
+    scale = MF.restrict(dim, n, np.abs(bf).reshape((n + 1,) * dim)
+                        + MF.apply(dim, n, None, np.abs(xf), np.abs(Ke)))
+    got = outs[0].reshape((nc + 1,) * dim)
+    assert_scaled_close(W.full_to_interior(dim, nc, got.ravel()),
+                        W.full_to_interior(dim, nc, want.ravel()),
+                        W.full_to_interior(dim, nc, scale.ravel()), eps, c=128.0,
+                        what="fused residual+restrict")
+    inner = np.zeros_like(got, dtype=bool)
+    inner[(slice(1, nc),) * dim] = True
+    assert not np.any(got[~inner])
