@@ -658,6 +658,10 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   // plane.  FP64 recomputes it from LDS per plane: the registers of the
   // cache would cost a quarter of the FP64 kernel's occupancy.
   constexpr bool IPREG = PRO && sizeof(T) == 4;
+  // FP64 (IPLDS): the same cache, in thread-private LDS slots instead of
+  // registers (slot (K & 1) holds coarse plane K's interpolants)
+  constexpr bool IPLDS = PRO && sizeof(T) == 8;
+  __shared__ T ipl[IPLDS ? 2 : 1][IPLDS ? NX : 1][IPLDS ? 256 : 1];
   auto ip_elem = [&](int q, int ss) -> T {
     const int e = tid + 256 * q;
     const int r = e / SW_LX, c = xcol(e - r * SW_LX);
@@ -673,11 +677,20 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
   T ipo[IPREG ? NX : 1], ipn[IPREG ? NX : 1];
   auto ip_plane = [&](int K) {
 #pragma unroll
-    for (int q = 0; q < NX; ++q) ipn[q] = ip_elem(q, K % 3);
+    for (int q = 0; q < NX; ++q) {
+      if constexpr (IPLDS)
+        ipl[K & 1][q][tid] = ip_elem(q, K % 3);
+      else
+        ipn[q] = ip_elem(q, K % 3);
+    }
   };
   auto pe = [&](int q, int z) -> T {
     if constexpr (IPREG) {
       return (z & 1) ? T(0.5) * (ipo[q] + ipn[q]) : ipn[q];
+    } else if constexpr (IPLDS) {
+      const int K = (z + 1) >> 1;  // the newer plane (z / 2 for even z)
+      return (z & 1) ? T(0.5) * (ipl[(K - 1) & 1][q][tid] + ipl[K & 1][q][tid])
+                     : ipl[K & 1][q][tid];
     } else {
       const int s0 = (z >> 1) % 3, s1 = ((z + 1) >> 1) % 3;
       return (z & 1) ? T(0.5) * (ip_elem(q, s0) + ip_elem(q, s1)) : ip_elem(q, s0);
@@ -889,13 +902,14 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
     }
     prefetch_c(c0 + 3);
     __syncthreads();
-    if (IPREG) ip_plane((k0 - 1) >> 1);
+    if (IPREG || IPLDS) ip_plane((k0 - 1) >> 1);
   }
   for (int p = k0 - 1; p <= k1 + 1; ++p) {
     if (PRO && (p & 1) && ((p + 3) >> 1) > c0 + 2) {
       commit_c((p + 3) >> 1);
       prefetch_c(((p + 3) >> 1) + 1);
     }
+    if (IPLDS && (p & 1)) ip_plane((p + 1) >> 1);  // (the slot of (p-3)/2)
     if (IPREG && (p & 1)) {
       // fine plane p (odd) interpolates from coarse planes (p-1)/2, kept,
       // and (p+1)/2, new (staged at least one step earlier)
