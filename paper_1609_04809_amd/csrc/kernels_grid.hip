@@ -1122,7 +1122,11 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
   // j0-1 .. j0+5), element e = tid + RR_THREADS q
   constexpr int NX = (SW_LX * RR_LY + RR_THREADS - 1) / RR_THREADS;
   int xoff[NX];
-  T xpf[NX];
+  // FP64: x planes two ahead (planes p+1 and p+2 in flight, slot = plane &
+  // 1; 2% faster 256^3 FP64 solves with two blocks per CU); FP32 one ahead
+  // (two ahead was 1% slower there)
+  constexpr bool PF2 = sizeof(T) == 8;
+  T xpf[PF2 ? 2 : 1][NX];
   auto xcol = [&](int cc) {
     return XIN ? (cc < SW_LX / 2 ? 2 * cc : 2 * (cc - SW_LX / 2) + 1) : cc;
   };
@@ -1133,28 +1137,28 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
     const int gi = i0 - 1 + c, gj = j0 - 1 + r;
     xoff[q] = min(gi, n) + min(gj, n) * (int)sy;  // always inside the grid
   }
-  auto prefetch_x = [&](int z) {
+  auto prefetch_x = [&](int z, T (&buf)[NX]) {
     if constexpr (XIN) {
       const long zb = (long)min(z, n) * sz;
 #pragma unroll
       for (int q = 0; q < NX; ++q) {
         const long p = zb + xoff[q];
-        xpf[q] = ((p & 1) ? xodd : x)[p >> 1];
+        buf[q] = ((p & 1) ? xodd : x)[p >> 1];
       }
     } else {
       const T* __restrict__ xz = x + (long)min(z, n) * sz;
 #pragma unroll
-      for (int q = 0; q < NX; ++q) xpf[q] = xz[xoff[q]];
+      for (int q = 0; q < NX; ++q) buf[q] = xz[xoff[q]];
     }
   };
-  auto commit_x = [&](int s) {
+  auto commit_x = [&](int s, const T (&buf)[NX]) {
     T* dst = &sx[s][0][0];
 #pragma unroll
     for (int q = 0; q < NX; ++q) {
       const int e = tid + RR_THREADS * q;
       if (e < SW_LX * RR_LY) {
         const int r = e / SW_LX;
-        dst[r * SW_LX + xcol(e - r * SW_LX)] = xpf[q];
+        dst[r * SW_LX + xcol(e - r * SW_LX)] = buf[q];
       }
     }
   };
@@ -1193,10 +1197,16 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
   const bool edge_l = tx == 63 && 64 * bx + 64 <= mc;  // columns of a boundary coarse column
   const bool edge_f = tx == 0 && bx > 0;
   T plm = T(0), part = T(0);  // plane 2K-1's row sum; m / 2 + c of coarse plane K
-  prefetch_x(k0 - 1);
-  for (int p = k0 - 1; p <= k1 + 1; ++p) {
-    commit_x(p & 1);
-    prefetch_x(p + 1);
+  // k0 - 1 is even, so plane p's LDS slot (and with PF2 its register
+  // buffer) is p & 1; the loop body is instantiated per slot, so register
+  // indices stay constant
+  prefetch_x(k0 - 1, xpf[0]);
+  if constexpr (PF2) prefetch_x(k0, xpf[PF2 ? 1 : 0]);
+  auto body = [&](int p, auto slot) {
+    constexpr int SL = decltype(slot)::value;
+    constexpr int B = PF2 ? SL : 0;
+    commit_x(SL, xpf[B]);
+    prefetch_x(PF2 ? p + 2 : p + 1, xpf[B]);
     const T bcur[2] = {bpf[0], bpf[1]};  // b of plane p-1
     prefetch_b(p);
     __syncthreads();
@@ -1261,6 +1271,10 @@ __global__ __launch_bounds__(RR_THREADS) void k_resid_restrict3(Geo g, StencilPa
         }
       }
     }
+  };
+  for (int p = k0 - 1; p <= k1 + 1; p += 2) {
+    body(p, std::integral_constant<int, 0>{});
+    if (p + 1 <= k1 + 1) body(p + 1, std::integral_constant<int, 1>{});
   }
 }
 
