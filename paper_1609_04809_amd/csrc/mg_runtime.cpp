@@ -1232,7 +1232,9 @@ void emit_iteration(mg_ctx* c, const Sink& sink, double* u, const double* b,
 void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool warm = false,
                    bool fuse = false, bool norm_ready = false) {
   Level& L0 = c->lv[0];
-  emit_start(c, sink, u, warm);
+  // (a solve whose finest iterate stays split from 0 writes u only after
+  // its last cycle; mg_solve fills u itself when no cycle runs)
+  if (warm || !c->s0on) emit_start(c, sink, u, warm);
   if (!norm_ready) {
     OpRec o = base_op<double>(c, OC_NORM2, 0);
     o.item.a = b;
@@ -1737,7 +1739,7 @@ mg_status mg_solve(mg_ctx* c, const double* b, double* u, double tol, int* iters
   if (st != MG_OK) return st;
   if (!std::isfinite(nb2)) return fail(MG_E_NONFINITE, "b holds NaN or Inf");
   if (nb2 == 0.0) {
-    if (warm) {
+    if (warm || c->s0on) {
       emit_fill<double>(c, launch_sink(c, s), 0, u);
       HIP_TRY(hipGetLastError());
     }

@@ -444,6 +444,11 @@ def test_split_finest_iterate_across_cycles_agrees_bitwise():
             outs.append((k, hist, host_full(u)))
     assert outs[0][0] == outs[1][0] and outs[0][1] == outs[1][1]
     assert np.array_equal(outs[0][2], outs[1][2])
+    # b = 0: no cycle runs, u = 0 (the split solve writes u only after cycles)
+    with Solver(3, n, levels) as S:
+        u = torch.full_like(b, 3.0)
+        u, k, hist, st = S.solve(torch.zeros_like(b), 1e-9, u=u)
+        assert st == "ok" and k == 0 and not torch.any(u)
 
 
 @pytest.mark.parametrize("dim,n,levels,kap,smoother,nu", [
