@@ -838,21 +838,36 @@ __global__ __launch_bounds__(256) void k_sweep3(Geo g, StencilParams<T> op, T om
       __syncthreads();
       window_k((k0 - 1) & 1, kwp);
     }
+    // b of the unknowns set at plane k -- for red-black only the updated
+    // one's (u = (colour + i + j + k) & 1) -- loaded one plane ahead; no
+    // barrier without cell layers (nothing else goes through LDS)
+    T bnx[2] = {T(0), T(0)};
+    auto load_b = [&](int k) {
+      const long p = pb0 + (long)min(k, n) * sz;
+      if (MODE == SM_JACOBI) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) bnx[u] = b[lay_idx(p + u, blay)];
+      } else {
+        bnx[0] = b[lay_idx(p + ((colour + i + j + k) & 1), blay)];
+      }
+    };
+    load_b(k0);
     for (int k = k0; k <= k1; ++k) {
+      const T bc0 = bnx[0], bc1 = bnx[1];
+      load_b(k + 1);
+      T kwc[2][3];
       if (KAP) {
         commit_k(k & 1);
         prefetch_k(k + 1);
+        __syncthreads();
+        window_k(k & 1, kwc);
       }
-      prefetch_b(k);
-      __syncthreads();
-      T kwc[2][3];
-      if (KAP) window_k(k & 1, kwc);
 #pragma unroll
       for (int u = 0; u < 2; ++u) {
         const bool ok = u == 0 ? ok0 : ok1;
         const bool upd = MODE == SM_JACOBI || (((i + u + j + k) & 1) == colour);
         if (!ok) continue;
-        const T bv = bpf[u];
+        const T bv = MODE == SM_JACOBI && u == 1 ? bc1 : bc0;
         T dg = op.wc;
         if (KAP) dg = op.s * T(4) * kappa_cell_sum<T>(kwp, kwc, u);
         if (MODE == SM_JACOBI)
