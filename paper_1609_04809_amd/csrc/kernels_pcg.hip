@@ -87,8 +87,8 @@ __global__ __launch_bounds__(PT) void k_pcg_update(double* __restrict__ u,
   if (threadIdx.x == 0) part[blockIdx.x] = sq;
 }
 
-// z = ||r|| * double(c), ||r||^2 = scal[0] (the FP32 preconditioner's
-// correction scaled back)
+// z = s * double(c), s = ir_scale(scal[0] = ||r||^2) (the FP32
+// preconditioner's correction scaled back)
 __global__ __launch_bounds__(PT) void k_pcg_zscale(const float* __restrict__ c,
                                                    double* __restrict__ z,
                                                    const double* __restrict__ scal, long n) {

@@ -1087,8 +1087,8 @@ void emit_pcg_op(mg_ctx* c, const Sink& sink, int sub, std::initializer_list<voi
 //   p = z + beta p (p = z first);  q = A p;  alpha = rz / p.q;
 //   u += alpha p;  r_old = r;  r -= alpha q;  ||r||^2 into scal[0].
 // B is the V-cycle from a zero guess on A z = r (FP64), or in FP32 on
-// r / s scaled back by s = ir_scale(||r||^2).  r lives in its own vector: the cycle
-// uses the level's residual buffer internally.
+// r / s scaled back by s = ir_scale(||r||^2).  r lives in its own vector:
+// the cycle uses the level's residual buffer internally.
 void emit_pcg_iteration(mg_ctx* c, const Sink& sink, double* u, bool first) {
   Level& L0 = c->lv[0];
   const long N = L0.g.nodes;
