@@ -519,3 +519,28 @@ def test_residual_and_restriction_in_one_pass_agree_bitwise(n, levels, prec, sig
         solve = O.solve if prec == "fp64" else O.solve_ir
         _, k_or, _, _ = solve(H, bi, 1e-9)
         assert abs(outs[0][0] - k_or) <= 1
+
+
+@pytest.mark.parametrize("prec,n,levels", [("fp32_ir", 64, 6), ("fp64", 64, 6),
+                                           ("fp32_ir", 96, 6)])
+def test_power_of_two_scaled_rhs_scales_the_solve_exactly(prec, n, levels):
+    """Every step of a solve is exactly equivariant under b -> 2^k b: the
+    residuals, norms and sweeps scale exactly, and the refinement scale of
+    the FP32 cycles is a power of two taken from ||b|| (so its FP32 values
+    are the same whatever k).  So u(2^k b) = 2^k u(b) bitwise, with the same
+    history, for k = 40 and k = -30."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import Solver
+    bi = W.rhs_uniform(3, n, 33)
+    ref = None
+    for k in (0, 40, -30):
+        b = dev_full(3, n, bi * 2.0 ** k)
+        with Solver(3, n, levels, precision=prec) as S:
+            u, it, hist, st = S.solve(b, 1e-9)
+            assert st == "ok"
+            got = (it, hist, host_full(u) * 2.0 ** -k)
+        if ref is None:
+            ref = got
+        else:
+            assert got[0] == ref[0] and got[1] == ref[1], k
+            assert np.array_equal(got[2], ref[2]), k
