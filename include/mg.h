@@ -343,9 +343,11 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
 
 /* ---------------------------------------------------------------------
  * Kernel timing: while enabled, mg_solve launches kernels one by one and
- * brackets every launch of the kernels matching `kernel_id` on level 0 with
- * HIP events on the launch stream.  mg_profile_read returns the number of
- * such launches and their summed duration in milliseconds.
+ * times every launch of the kernels matching `kernel_id` on level 0 with
+ * HIP events: the start and end of the kernel itself, recorded by its
+ * launch (hipExtLaunchKernelGGL), or, for a step of more than one kernel,
+ * events on the launch stream around the step.  mg_profile_read returns
+ * the number of such launches and their summed duration in milliseconds.
  *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
  *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps

@@ -248,11 +248,11 @@ void launch_rows(const CsrOp<T>& A, int rb, int re, const T* xin, const T* b, T*
   const int nb = cdiv_i(re - rb, CSR_ROWS);
   if (nb == 0) return;
   if (xin == nullptr)
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, true>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
-                       xin, b, out, omega, partials);
+    MG_LAUNCH((k_csr_rows<T, MODE, true>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
+              xin, b, out, omega, partials);
   else
-    hipLaunchKernelGGL((k_csr_rows<T, MODE, false>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
-                       xin, b, out, omega, partials);
+    MG_LAUNCH((k_csr_rows<T, MODE, false>), dim3(nb), dim3(CSR_NTH), 0, s, A, rb, re,
+              xin, b, out, omega, partials);
 }
 
 }  // namespace
@@ -266,11 +266,11 @@ void launch_csr_build(const Geo& g, const double* kappa, double s_elem, double s
   const unsigned blocks = (unsigned)cdiv_i(rows, 256);
   if (blocks == 0) return;
   if (g.dim == 2)
-    hipLaunchKernelGGL((k_csr_build<T, 2>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
-                       s_mass, rows, rowmap, rowptr, col, val);
+    MG_LAUNCH((k_csr_build<T, 2>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
+              s_mass, rows, rowmap, rowptr, col, val);
   else
-    hipLaunchKernelGGL((k_csr_build<T, 3>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
-                       s_mass, rows, rowmap, rowptr, col, val);
+    MG_LAUNCH((k_csr_build<T, 3>), dim3(blocks), dim3(256), 0, s, g, kappa, s_elem,
+              s_mass, rows, rowmap, rowptr, col, val);
 }
 
 template <typename T>

@@ -2458,8 +2458,8 @@ void launch_sweep3(const Geo& g, const StencilParams<T>& op, T omega, const Batc
                    hipStream_t s) {
   int kz, nzc;
   const dim3 gr = sweep3_grid(g, B.count, &kz, &nzc, (int)sizeof(T));
-  hipLaunchKernelGGL((k_sweep3<T, K, MODE, ZERO, NORM, false, XL, IRU, CAST>), gr,
-                     dim3(64, SW_TY), 0, s, g, op, omega, kz, nzc, sweep3_remap(), B);
+  MG_LAUNCH((k_sweep3<T, K, MODE, ZERO, NORM, false, XL, IRU, CAST>), gr,
+            dim3(64, SW_TY), 0, s, g, op, omega, kz, nzc, sweep3_remap(), B);
 }
 
 }  // namespace
@@ -2482,11 +2482,11 @@ long grid_blocks(const Geo& g) {
 
 template <typename T>
 void launch_fill(T* v, long count, T val, hipStream_t s) {
-  hipLaunchKernelGGL(k_fill<T>, dim3(flat_blocks(count)), dim3(256), 0, s, v, count, val);
+  MG_LAUNCH(k_fill<T>, dim3(flat_blocks(count)), dim3(256), 0, s, v, count, val);
 }
 template <typename T>
 void launch_copy(const T* a, T* b, long count, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy<T>, dim3(flat_blocks(count)), dim3(256), 0, s, a, b, count);
+  MG_LAUNCH(k_copy<T>, dim3(flat_blocks(count)), dim3(256), 0, s, a, b, count);
 }
 
 // 2D operators are OP_CONST (any sigma) or OP_KAPPA; 3D ones any kind.
@@ -2551,9 +2551,9 @@ void launch_residual(const Geo& g, const StencilParams<T>& op, bool norm, const 
 #define L_RES(D, K)                                                                   \
   do {                                                                                \
     if (norm)                                                                         \
-      hipLaunchKernelGGL((k_residual<T, D, K, true>), gr, bl, 0, s, g, op, B);        \
+      MG_LAUNCH((k_residual<T, D, K, true>), gr, bl, 0, s, g, op, B);                 \
     else                                                                              \
-      hipLaunchKernelGGL((k_residual<T, D, K, false>), gr, bl, 0, s, g, op, B);       \
+      MG_LAUNCH((k_residual<T, D, K, false>), gr, bl, 0, s, g, op, B);                \
   } while (0)
   DISPATCH_DIM_KIND(g.dim, op.kind, L_RES);
 #undef L_RES
@@ -2564,11 +2564,11 @@ static void launch_smooth_k(const Geo& g, const StencilParams<T>& op, int kind, 
                             const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
   if (kind == SM_JACOBI)
-    hipLaunchKernelGGL((k_smooth<T, D, K, SM_JACOBI, Z>), gr, bl, 0, s, g, op, omega, B);
+    MG_LAUNCH((k_smooth<T, D, K, SM_JACOBI, Z>), gr, bl, 0, s, g, op, omega, B);
   else if (kind == SM_RB0)
-    hipLaunchKernelGGL((k_smooth<T, D, K, SM_RB0, Z>), gr, bl, 0, s, g, op, omega, B);
+    MG_LAUNCH((k_smooth<T, D, K, SM_RB0, Z>), gr, bl, 0, s, g, op, omega, B);
   else
-    hipLaunchKernelGGL((k_smooth<T, D, K, SM_RB1, Z>), gr, bl, 0, s, g, op, omega, B);
+    MG_LAUNCH((k_smooth<T, D, K, SM_RB1, Z>), gr, bl, 0, s, g, op, omega, B);
 }
 
 template <typename T, int K, bool Z>
@@ -2619,8 +2619,8 @@ void launch_resid_restrict(const Geo& g, const StencilParams<T>& op, bool xin, c
   auto go = [&](auto kc, auto xc) {
     constexpr int K = decltype(kc)::value;
     constexpr bool X = decltype(xc)::value;
-    hipLaunchKernelGGL((k_resid_restrict3<T, K, X>), gr, bl, 0, s, g, op, kzc, nzc,
-                       sweep3_remap(), B);
+    MG_LAUNCH((k_resid_restrict3<T, K, X>), gr, bl, 0, s, g, op, kzc, nzc,
+              sweep3_remap(), B);
   };
   using MassK = std::integral_constant<int, OP_MASS>;
   using ConstK = std::integral_constant<int, OP_CONST>;
@@ -2640,8 +2640,8 @@ void launch_restrict_xcols(const Geo& gf, const Batch& B, hipStream_t s) {
   const int mc = (gf.n >> 1) - 1, ncols = resid_restrict_xcols(gf);
   if (ncols == 0) return;
   const long total = (long)mc * mc * ncols;
-  hipLaunchKernelGGL((k_restrict_xcols<T>), dim3((unsigned)cdiv(total, 256), B.count), dim3(256),
-                     0, s, gf, ncols, B);
+  MG_LAUNCH((k_restrict_xcols<T>), dim3((unsigned)cdiv(total, 256), B.count), dim3(256),
+            0, s, gf, ncols, B);
 }
 
 namespace {
@@ -2697,7 +2697,7 @@ void launch_smooth(const Geo& g, const StencilParams<T>& op, int kind, bool zero
   if (kind >= SM_GS0) {
     const dim3 gr = node_grid(g, B.count), bl(BX, BY);
 #define L_GS(D, K) \
-  hipLaunchKernelGGL((k_smooth_gs<T, D, K>), gr, bl, 0, s, g, op, kind - SM_GS0, B)
+  MG_LAUNCH((k_smooth_gs<T, D, K>), gr, bl, 0, s, g, op, kind - SM_GS0, B)
     DISPATCH_DIM_KIND(g.dim, op.kind, L_GS);
 #undef L_GS
     return;
@@ -2736,8 +2736,8 @@ void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T
     // (red-black on split-iterate levels: constant-coefficient and
     // mass-shifted kinds; the iterate read natural or split)
 #define L_SPX(K, M, X)                                                                     \
-  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true, X>), gr, bl, 0, s, g, op, omega, kz, \
-                     nzc, rm, B)
+  MG_LAUNCH((k_sweep3<T, K, M, false, false, true, X>), gr, bl, 0, s, g, op, omega, kz,          \
+            nzc, rm, B)
 #define L_SPX_X(K, M)                                                      \
   do {                                                                     \
     if (xl == XL_TO_SPLIT) L_SPX(K, M, XL_TO_SPLIT); else L_SPX(K, M, XL_SPLIT_BOTH); \
@@ -2752,7 +2752,7 @@ void launch_smooth_prolong(const Geo& g, const StencilParams<T>& op, int kind, T
     return;
   }
 #define L_SP(K, M) \
-  hipLaunchKernelGGL((k_sweep3<T, K, M, false, false, true>), gr, bl, 0, s, g, op, omega, kz, nzc, rm, B)
+  MG_LAUNCH((k_sweep3<T, K, M, false, false, true>), gr, bl, 0, s, g, op, omega, kz, nzc, rm, B)
 #define L_SP_K(K)                                          \
   do {                                                     \
     if (kind == SM_JACOBI) L_SP(K, SM_JACOBI);             \
@@ -2777,7 +2777,7 @@ void launch_smooth_pair(const Geo& g, const StencilParams<T>& op, int first, boo
   const dim3 bl(64, SW_TY);
   const int rm = sweep3_remap();
 #define L_PAIR(K, CA, Z) \
-  hipLaunchKernelGGL((k_sweep3_pair<T, K, CA, Z>), gr, bl, 0, s, g, op, kz, nzc, rm, B)
+  MG_LAUNCH((k_sweep3_pair<T, K, CA, Z>), gr, bl, 0, s, g, op, kz, nzc, rm, B)
 #define L_PAIR_K(K)                                  \
   do {                                               \
     if (first == SM_RB0) {                           \
@@ -2829,9 +2829,9 @@ void launch_head(const Geo& g, const StencilParams<T>& op, int kind, T omega, co
 #define L_HEAD(D, K)                                                                        \
   do {                                                                                      \
     if (jac)                                                                                \
-      hipLaunchKernelGGL((k_head<T, D, K, SM_JACOBI>), gr, bl, 0, s, g, op, omega, B);      \
+      MG_LAUNCH((k_head<T, D, K, SM_JACOBI>), gr, bl, 0, s, g, op, omega, B);               \
     else                                                                                    \
-      hipLaunchKernelGGL((k_head<T, D, K, SM_RB0>), gr, bl, 0, s, g, op, omega, B);         \
+      MG_LAUNCH((k_head<T, D, K, SM_RB0>), gr, bl, 0, s, g, op, omega, B);                  \
   } while (0)
   DISPATCH_DIM_KIND(g.dim, op.kind, L_HEAD);
 #undef L_HEAD
@@ -2846,7 +2846,7 @@ void launch_apply_dot(const Geo& g, const StencilParams<T>& op, const Batch& B, 
     return;
   }
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
-#define L_AD(D, K) hipLaunchKernelGGL((k_apply_dot<T, D, K>), gr, bl, 0, s, g, op, B)
+#define L_AD(D, K) MG_LAUNCH((k_apply_dot<T, D, K>), gr, bl, 0, s, g, op, B)
   DISPATCH_DIM_KIND(g.dim, op.kind, L_AD);
 #undef L_AD
 }
@@ -2867,24 +2867,24 @@ void launch_cn_rhs(const Geo& g, const CnWeights& w, const double* u, double* gu
     launch_sweep3<double, OP_MASS, SW_CN, false, false>(g, op, F ? w.cf : 0.0, B, s);
     const long m = g.n - 1;
     const long total = 2 * m * m + 2 * m * (m - 2) + 2 * (m - 2) * (m - 2);
-    hipLaunchKernelGGL(k_cn_bnd, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, w,
-                       u, g0, g1, b);
+    MG_LAUNCH(k_cn_bnd, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, g, w,
+              u, g0, g1, b);
     return;
   }
   const dim3 gr = node_grid(g, 1), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
+    MG_LAUNCH(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
   else
-    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
+    MG_LAUNCH(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, guess, g0, g1, F, b);
 }
 
 void launch_cn_rhs_nodes(const Geo& g, const CnWeights& w, const double* u, const double* g0,
                          double* b, hipStream_t s) {
   const dim3 gr = node_grid(g, 1), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
+    MG_LAUNCH(k_cn_rhs<2>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
   else
-    hipLaunchKernelGGL(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
+    MG_LAUNCH(k_cn_rhs<3>, gr, bl, 0, s, g, w, u, nullptr, g0, nullptr, nullptr, b);
 }
 
 void launch_zero_boundary(const Geo& g, double* v, hipStream_t s) {
@@ -2892,18 +2892,18 @@ void launch_zero_boundary(const Geo& g, double* v, hipStream_t s) {
   const long total = 2L * g.dim * (g.dim == 3 ? N1 * N1 : N1);
   const unsigned blocks = (unsigned)((total + 255) / 256);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_zero_boundary<2>, dim3(blocks), dim3(256), 0, s, g, v);
+    MG_LAUNCH(k_zero_boundary<2>, dim3(blocks), dim3(256), 0, s, g, v);
   else
-    hipLaunchKernelGGL(k_zero_boundary<3>, dim3(blocks), dim3(256), 0, s, g, v);
+    MG_LAUNCH(k_zero_boundary<3>, dim3(blocks), dim3(256), 0, s, g, v);
 }
 
 template <typename T>
 void launch_restrict(const Geo& gf, const Geo& gc, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(gc, B.count), bl(BX, BY);
   if (gf.dim == 2)
-    hipLaunchKernelGGL((k_restrict<T, 2>), gr, bl, 0, s, gf, gc, B);
+    MG_LAUNCH((k_restrict<T, 2>), gr, bl, 0, s, gf, gc, B);
   else
-    hipLaunchKernelGGL((k_restrict<T, 3>), gr, bl, 0, s, gf, gc, B);
+    MG_LAUNCH((k_restrict<T, 3>), gr, bl, 0, s, gf, gc, B);
 }
 
 // Fine planes per thread of the z-marching 3D prolongation: 1 (one thread
@@ -2929,32 +2929,32 @@ void launch_prolong_add(const Geo& gf, const Geo& gc, const Batch& B, hipStream_
     const long m = gf.n - 1, chunks = cdiv(m, pz);
     const dim3 gr(cdiv(m, BX), cdiv(m, BY), (unsigned)(chunks * B.count)), bl(BX, BY);
     if (pz == 2)
-      hipLaunchKernelGGL((k_prolong_add_z<T, 2>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+      MG_LAUNCH((k_prolong_add_z<T, 2>), gr, bl, 0, s, gf, gc, B, (int)chunks);
     else if (pz == 4)
-      hipLaunchKernelGGL((k_prolong_add_z<T, 4>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+      MG_LAUNCH((k_prolong_add_z<T, 4>), gr, bl, 0, s, gf, gc, B, (int)chunks);
     else
-      hipLaunchKernelGGL((k_prolong_add_z<T, 8>), gr, bl, 0, s, gf, gc, B, (int)chunks);
+      MG_LAUNCH((k_prolong_add_z<T, 8>), gr, bl, 0, s, gf, gc, B, (int)chunks);
     return;
   }
   const dim3 gr = node_grid(gf, B.count), bl(BX, BY);
   if (gf.dim == 2)
-    hipLaunchKernelGGL((k_prolong_add<T, 2>), gr, bl, 0, s, gf, gc, B);
+    MG_LAUNCH((k_prolong_add<T, 2>), gr, bl, 0, s, gf, gc, B);
   else
-    hipLaunchKernelGGL((k_prolong_add<T, 3>), gr, bl, 0, s, gf, gc, B);
+    MG_LAUNCH((k_prolong_add<T, 3>), gr, bl, 0, s, gf, gc, B);
 }
 
 template <typename T>
 void launch_coarse_solve(const Geo& gc, int m, const Batch& B, hipStream_t s) {
-  hipLaunchKernelGGL((k_coarse_solve<T>), dim3(B.count), dim3(256), 0, s, gc, m, B);
+  MG_LAUNCH((k_coarse_solve<T>), dim3(B.count), dim3(256), 0, s, gc, m, B);
 }
 
 template <typename T>
 void launch_norm2_partial(const Geo& g, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL((k_norm2_partial<T, 2>), gr, bl, 0, s, g, B);
+    MG_LAUNCH((k_norm2_partial<T, 2>), gr, bl, 0, s, g, B);
   else
-    hipLaunchKernelGGL((k_norm2_partial<T, 3>), gr, bl, 0, s, g, B);
+    MG_LAUNCH((k_norm2_partial<T, 3>), gr, bl, 0, s, g, B);
 }
 
 void launch_split_norm(const Geo& g, const double* src, double* dst, long lay,
@@ -2967,29 +2967,29 @@ void launch_split_norm(const Geo& g, const double* src, double* dst, long lay,
   B.it[0].partials = partials;
   const dim3 gr = node_grid(g, 1), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_split_norm<2>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_split_norm<2>, gr, bl, 0, s, g, B);
   else
-    hipLaunchKernelGGL(k_split_norm<3>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_split_norm<3>, gr, bl, 0, s, g, B);
 }
 
 void launch_reduce_final(long count, const Batch& B, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_final, dim3(B.count), dim3(RED_THREADS), 0, s, count, B);
+  MG_LAUNCH(k_reduce_final, dim3(B.count), dim3(RED_THREADS), 0, s, count, B);
 }
 
 void launch_scale_cast(const Geo& g, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_scale_cast<2>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_scale_cast<2>, gr, bl, 0, s, g, B);
   else
-    hipLaunchKernelGGL(k_scale_cast<3>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_scale_cast<3>, gr, bl, 0, s, g, B);
 }
 
 void launch_ir_update(const Geo& g, const Batch& B, hipStream_t s) {
   const dim3 gr = node_grid(g, B.count), bl(BX, BY);
   if (g.dim == 2)
-    hipLaunchKernelGGL(k_ir_update<2>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_ir_update<2>, gr, bl, 0, s, g, B);
   else
-    hipLaunchKernelGGL(k_ir_update<3>, gr, bl, 0, s, g, B);
+    MG_LAUNCH(k_ir_update<3>, gr, bl, 0, s, g, B);
 }
 
 template <typename T, int D, int K>
@@ -3000,7 +3000,7 @@ static void launch_tail_k(int lds_bytes, const Batch& B, hipStream_t s) {
                                kTailLdsBytes) == hipSuccess;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_tail<T, D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B);
+  MG_LAUNCH((k_tail<T, D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B);
 }
 
 template <typename T>
@@ -3019,8 +3019,8 @@ static void launch_tail_solve_k(int lds_bytes, const Batch& B, double tol, int m
                                kTailLdsBytes) == hipSuccess;
   }();
   (void)attr;
-  hipLaunchKernelGGL((k_tail_solve<D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B,
-                     tol, max_iter);
+  MG_LAUNCH((k_tail_solve<D, K>), dim3(B.count), dim3(TAIL_THREADS), lds_bytes, s, B,
+            tol, max_iter);
 }
 
 void launch_tail_solve(int dim, int kind, int lds_bytes, const Batch& B, double tol, int max_iter,
@@ -3033,7 +3033,7 @@ void launch_tail_solve(int dim, int kind, int lds_bytes, const Batch& B, double 
 template <typename T>
 void launch_unsplit(const Geo& g, const Batch& B, hipStream_t s) {
   const unsigned bx = (unsigned)std::min<long>((g.nodes + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_unsplit<T>, dim3(bx, B.count), dim3(256), 0, s, g.nodes, B);
+  MG_LAUNCH(k_unsplit<T>, dim3(bx, B.count), dim3(256), 0, s, g.nodes, B);
 }
 
 void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStream_t s) {
@@ -3041,19 +3041,19 @@ void launch_kappa_coarsen(int dim, int nf, const double* kf, double* kc, hipStre
   const long total = dim == 3 ? (long)nc * nc * nc : (long)nc * nc;
   const unsigned blocks = (unsigned)((total + 255) / 256);
   if (dim == 2)
-    hipLaunchKernelGGL(k_kappa_coarsen<2>, dim3(blocks), dim3(256), 0, s, nf, kf, kc);
+    MG_LAUNCH(k_kappa_coarsen<2>, dim3(blocks), dim3(256), 0, s, nf, kf, kc);
   else
-    hipLaunchKernelGGL(k_kappa_coarsen<3>, dim3(blocks), dim3(256), 0, s, nf, kf, kc);
+    MG_LAUNCH(k_kappa_coarsen<3>, dim3(blocks), dim3(256), 0, s, nf, kf, kc);
 }
 
 void launch_cast_f32(const double* a, float* b, long count, hipStream_t s) {
-  hipLaunchKernelGGL(k_cast_f32, dim3(flat_blocks(count)), dim3(256), 0, s, a, b, count);
+  MG_LAUNCH(k_cast_f32, dim3(flat_blocks(count)), dim3(256), 0, s, a, b, count);
 }
 
 void launch_count_bad_kappa(const double* k, long count, int* nonpos, int* nonfinite,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_count_bad_kappa, dim3(flat_blocks(count)), dim3(256), 0, s, k, count,
-                     nonpos, nonfinite);
+  MG_LAUNCH(k_count_bad_kappa, dim3(flat_blocks(count)), dim3(256), 0, s, k, count,
+            nonpos, nonfinite);
 }
 
 #define INST(T)                                                                             \

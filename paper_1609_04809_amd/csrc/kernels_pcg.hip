@@ -108,26 +108,26 @@ long pcg_blocks(long n) { return pcg_grid(n); }
 
 void launch_pcg_dots2(const double* z, const double* r, const double* ro, long n, double* pa,
                       double* pb, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_dots2, dim3(pcg_grid(n)), dim3(PT), 0, s, z, r, ro, n, pa, pb);
+  MG_LAUNCH(k_pcg_dots2, dim3(pcg_grid(n)), dim3(PT), 0, s, z, r, ro, n, pa, pb);
 }
 
 void launch_pcg_scalars(double* scal, int first, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_scalars, dim3(1), dim3(64), 0, s, scal, first);
+  MG_LAUNCH(k_pcg_scalars, dim3(1), dim3(64), 0, s, scal, first);
 }
 
 void launch_pcg_dir(const double* z, double* p, const double* scal, long n, int first,
                     hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_dir, dim3(pcg_grid(n)), dim3(PT), 0, s, z, p, scal, n, first);
+  MG_LAUNCH(k_pcg_dir, dim3(pcg_grid(n)), dim3(PT), 0, s, z, p, scal, n, first);
 }
 
 void launch_pcg_update(double* u, const double* p, double* r, double* ro, const double* q,
                        const double* scal, long n, double* part, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_update, dim3(pcg_grid(n)), dim3(PT), 0, s, u, p, r, ro, q, scal, n,
-                     part);
+  MG_LAUNCH(k_pcg_update, dim3(pcg_grid(n)), dim3(PT), 0, s, u, p, r, ro, q, scal, n,
+            part);
 }
 
 void launch_pcg_zscale(const float* c, double* z, const double* scal, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_zscale, dim3(pcg_grid(n)), dim3(PT), 0, s, c, z, scal, n);
+  MG_LAUNCH(k_pcg_zscale, dim3(pcg_grid(n)), dim3(PT), 0, s, c, z, scal, n);
 }
 
 }  // namespace mg

@@ -157,6 +157,7 @@ struct mg_ctx {
   double prof_ms = 0.0;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
+  std::vector<hipEvent_t> ev_spare;  // recorded but not read; back to ev_pool
 };
 
 namespace mg {

@@ -3,6 +3,7 @@
 // the HIP kernels.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -29,6 +30,28 @@ inline Geo make_geo(int dim, int n) {
   g.nodes = dim == 3 ? (long)(n + 1) * (n + 1) * (n + 1) : (long)(n + 1) * (n + 1);
   return g;
 }
+
+// Timing of one profiled step: while `start` is set, the first kernel the
+// step launches through MG_LAUNCH records its own start and end into
+// start / stop (hipExtLaunchKernelGGL), so their elapsed time is that
+// kernel's execution alone, with no gap before or after it; `launches`
+// counts the kernels the step issued.  Every launch of the library goes
+// through MG_LAUNCH; with `start` unset it is a plain hipLaunchKernelGGL.
+struct KernelEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+  int launches = 0;
+};
+extern thread_local KernelEvents g_kernel_events;
+
+#define MG_LAUNCH(KERNEL, GRID, BLOCK, SHM, STREAM, ...)                                 \
+  do {                                                                                   \
+    ::mg::KernelEvents& kev_ = ::mg::g_kernel_events;                                    \
+    if (kev_.start && kev_.launches++ == 0)                                              \
+      hipExtLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, kev_.start, kev_.stop, 0u, \
+                            __VA_ARGS__);                                                \
+    else                                                                                 \
+      hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHM, STREAM, __VA_ARGS__);                 \
+  } while (0)
 
 // Workgroups are dispatched round-robin over the 8 XCDs of the chip (each
 // with its own L2) in linear order.  xcd_remap maps a dispatch index to a

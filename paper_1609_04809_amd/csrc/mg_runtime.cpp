@@ -33,6 +33,7 @@ using namespace mg;
 // ---------------------------------------------------------------------------
 namespace mg {
 thread_local std::string g_err;
+thread_local KernelEvents g_kernel_events;
 
 mg_status fail(mg_status st, const char* fmt, ...) {
   char buf[512];
@@ -1302,22 +1303,35 @@ void prof_collect(mg_ctx* c) {
     c->ev_pool.push_back(pr.second);
   }
   c->ev_pending.clear();
+  c->ev_pool.insert(c->ev_pool.end(), c->ev_spare.begin(), c->ev_spare.end());
+  c->ev_spare.clear();
 }
 
 Sink launch_sink(mg_ctx* c, hipStream_t s) {
   return [c, s](const OpRec& o) {
     const bool prof = c->prof_on && o.level == 0 && prof_class(o) == c->prof_kernel;
-    hipEvent_t a = nullptr, b = nullptr;
+    // ka, kb: the start and end of the step's kernel, recorded by its launch
+    // (the measured time when the step is one kernel); a, b: events on the
+    // stream around the whole step (the measured time otherwise)
+    hipEvent_t a = nullptr, b = nullptr, ka = nullptr, kb = nullptr;
     if (prof) {
       a = take_event(c);
       b = take_event(c);
+      ka = take_event(c);
+      kb = take_event(c);
       hipEventRecord(a, s);
+      g_kernel_events = KernelEvents{ka, kb, 0};
     }
     const OpRec* p = &o;
     launch_ops(&p, 1, s);
     if (prof) {
+      const int kernels = g_kernel_events.launches;
+      g_kernel_events = KernelEvents{};
       hipEventRecord(b, s);
+      if (kernels == 1) std::swap(a, ka), std::swap(b, kb);
       c->ev_pending.emplace_back(a, b);
+      c->ev_spare.push_back(ka);
+      c->ev_spare.push_back(kb);
     }
   };
 }
@@ -1673,6 +1687,7 @@ void mg_destroy(mg_ctx* c) {
     c->ev_pool.push_back(pr.first);
     c->ev_pool.push_back(pr.second);
   }
+  for (hipEvent_t e : c->ev_spare) hipEventDestroy(e);
   for (hipEvent_t e : c->ev_pool) hipEventDestroy(e);
   if (c->cap) hipStreamDestroy(c->cap);
   if (c->pinned) hipHostFree(c->pinned);

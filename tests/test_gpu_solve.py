@@ -544,3 +544,44 @@ def test_power_of_two_scaled_rhs_scales_the_solve_exactly(prec, n, levels):
         else:
             assert got[0] == ref[0] and got[1] == ref[1], k
             assert np.array_equal(got[2], ref[2]), k
+
+
+@pytest.mark.parametrize("dim,n,levels,op,prec", [(3, 64, 5, "stencil", "fp64"),
+                                                  (3, 96, 5, "stencil", "fp32_ir"),
+                                                  (3, 32, 4, "csr", "fp64"),
+                                                  (2, 128, 6, "stencil", "fp64")])
+def test_kernel_timing_leaves_the_solve_unchanged(dim, n, levels, op, prec):
+    """mg_profile_enable: a timed solve (kernels launched one by one, each
+    finest-level step of the class timed by events that its own launch
+    records) gives bitwise the untimed solve's iterate and history, and the
+    timing is the same number of launches on every timed solve, one or more
+    per cycle, each of positive duration; a class with no launch in the
+    solve (the half-sweep pair) reads zero."""
+    torch_cuda()
+    from paper_1609_04809_amd.mg import (PROF_PAIR, PROF_RESID_RESTRICT, PROF_SMOOTH,
+                                         PROF_SMOOTH_PRO, Solver)
+    b = dev_full(dim, n, W.rhs_uniform(dim, n, 35))
+    with Solver(dim, n, levels, op=op, precision=prec) as S:
+        print(f"[timing] {dim}d n={n} {op} {prec}", flush=True)
+        u0, k0, h0, st = S.solve(b, 1e-9)
+        assert st == "ok"
+        ref = host_full(u0)
+        kinds = [PROF_SMOOTH, PROF_PAIR] + ([PROF_SMOOTH_PRO, PROF_RESID_RESTRICT]
+                                            if op == "stencil" and dim == 3 and prec == "fp64"
+                                            else [])
+        for kid in kinds:
+            counts = []
+            for _ in range(2):
+                S.profile(kid, True)
+                u, k, h, st = S.solve(b, 1e-9)
+                launches, ms = S.profile_read()
+                S.profile(kid, False)
+                assert st == "ok" and k == k0 and h == h0, kid
+                assert np.array_equal(host_full(u), ref), kid
+                counts.append(launches)
+                if kid == PROF_PAIR:
+                    assert launches == 0 and ms == 0.0
+                else:
+                    assert launches >= k0, (kid, launches, k0)
+                    assert 0.0 < ms / launches < 50.0, (kid, ms, launches)
+            assert counts[0] == counts[1], (kid, counts)
