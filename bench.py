@@ -174,7 +174,8 @@ def stencil_pair_bytes(n, s, kappa=False):
 
 def roofline_stencil(S, w, bd, s):
     """Finest-level smoothing kernels of one eager solve: single red-black
-    half-sweeps and half-sweep pairs, each timed with HIP events."""
+    half-sweeps that read the iterate (a step from x = 0 reads no x and is
+    not counted) and half-sweep pairs, each timed with HIP events."""
     from paper_1609_04809_amd.mg import PROF_PAIR, PROF_SMOOTH
     out = {}
     for key, kid, per in (("halfsweep", PROF_SMOOTH,

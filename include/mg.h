@@ -111,7 +111,7 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
 #define MG_FLAG_NO_SPLIT 64  /* keep every vector in the natural layout.
                                 By default the right-hand sides of the 3D
                                 matrix-free levels with even n whose vectors
-                                reach 128 MB are stored colour-split --
+                                reach 64 MB are stored colour-split --
                                 even-indexed nodes first, then odd-indexed
                                 ones, which for even n are the two red-black
                                 colours -- so a half-sweep reads its colour's
@@ -348,13 +348,15 @@ mg_status mg_norm2(mg_ctx* ctx, int level, int prec, const void* v,
  * launch (hipExtLaunchKernelGGL), or, for a step of more than one kernel,
  * events on the launch stream around the step.  mg_profile_read returns
  * the number of such launches and their summed duration in milliseconds.
- *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep),
+ *   kernel_id: 0 = smoothing sweep (Jacobi sweep or red-black half-sweep)
+ *              that reads the iterate,
  *              1 = residual (with or without norm), 2 = restriction,
  *              3 = prolongation + add, 4 = pair of red-black half-sweeps
  *              in one pass, 5 = prolongation fused into a smoothing step,
  *              6 = last FP32 smoothing step of an iterative-refinement
  *              cycle, with the update of u fused in, 7 = residual and
- *              restriction in one pass
+ *              restriction in one pass, 8 = smoothing step from x = 0
+ *              (the iterate is not read)
  * ------------------------------------------------------------------- */
 mg_status mg_profile_enable(mg_ctx* ctx, int kernel_id, int enable);
 mg_status mg_profile_read(mg_ctx* ctx, long* launches, double* total_ms);

@@ -145,9 +145,10 @@ int tail_start(const mg_options& o, bool kappa) {
 // `elem` bytes, are stored colour-split (Item::lay): 3D matrix-free levels
 // swept by k_sweep3 with red-black or Jacobi smoothing on single
 // half-sweeps, even n_l (then a node's index parity is its colour), and
-// vectors of at least 128 MB, which stream from HBM (smaller levels stay in
-// the 256 MB last-level cache, where the split layout measured no gain).
-constexpr long kSplitMinBytes = 128L << 20;
+// vectors of at least 64 MB, which stream largely from HBM (smaller levels
+// stay in the 256 MB last-level cache, where the split layout measured no
+// gain; the 256^3 FP32 level, 68 MB per vector, gains 2% of the solve).
+constexpr long kSplitMinBytes = 64L << 20;
 bool split_level(const mg_options& o, int nl, int elem) {
   const long nodes = (long)(nl + 1) * (nl + 1) * (nl + 1);
   return o.op == MG_OP_STENCIL && o.dim == 3 && nl >= 32 && nl % 2 == 0 &&
@@ -1258,13 +1259,14 @@ void emit_prologue(mg_ctx* c, const Sink& sink, double* u, const double* b, bool
 // profiling hooks: bracket level-0 launches of the selected kernel class
 enum ProfKind {
   PK_SMOOTH = 0, PK_RESID = 1, PK_RESTRICT = 2, PK_PROLONG = 3, PK_SMOOTH2 = 4, PK_SMOOTH_PRO = 5,
-  PK_SMOOTH_IR = 6, PK_RESID_RESTRICT = 7
+  PK_SMOOTH_IR = 6, PK_RESID_RESTRICT = 7, PK_SMOOTH_ZERO = 8
 };
 
 int prof_class(const OpRec& o) {
   switch (o.code) {
-    case OC_SMOOTH: return (o.sub >> 8) & 1 ? PK_SMOOTH_IR : PK_SMOOTH;
-    case OC_CSR_SMOOTH: return PK_SMOOTH;
+    case OC_SMOOTH:
+      return (o.sub >> 8) & 1 ? PK_SMOOTH_IR : ((o.sub >> 4) & 1 ? PK_SMOOTH_ZERO : PK_SMOOTH);
+    case OC_CSR_SMOOTH: return o.sub >> 4 ? PK_SMOOTH_ZERO : PK_SMOOTH;
     case OC_SMOOTH2: return PK_SMOOTH2;
     case OC_SMOOTH_PRO: return PK_SMOOTH_PRO;
     case OC_RESID:
@@ -2026,7 +2028,7 @@ mg_status mg_norm2(mg_ctx* c, int level, int prec, const void* v, double* out, v
 
 mg_status mg_profile_enable(mg_ctx* c, int kernel_id, int enable) {
   if (!c) return fail(MG_E_ARG, "ctx is NULL");
-  if (kernel_id < 0 || kernel_id > 7) return fail(MG_E_ARG, "kernel_id must be 0..7");
+  if (kernel_id < 0 || kernel_id > 8) return fail(MG_E_ARG, "kernel_id must be 0..8");
   c->prof_kernel = kernel_id;
   c->prof_on = enable != 0;
   c->prof_launches = 0;

@@ -37,7 +37,7 @@ STEP_JACOBI, STEP_RB0, STEP_RB1, STEP_RB_PRE, STEP_RB_POST = 0, 1, 2, 3, 4
 STEP_GS0 = 5          # STEP_GS0 + c: multicolour Gauss-Seidel update of colour c
 # mg_profile_enable kernel ids
 (PROF_SMOOTH, PROF_RESID, PROF_RESTRICT, PROF_PROLONG, PROF_PAIR, PROF_SMOOTH_PRO,
- PROF_SMOOTH_IR, PROF_RESID_RESTRICT) = 0, 1, 2, 3, 4, 5, 6, 7
+ PROF_SMOOTH_IR, PROF_RESID_RESTRICT, PROF_SMOOTH_ZERO) = 0, 1, 2, 3, 4, 5, 6, 7, 8
 
 
 class MgError(RuntimeError):

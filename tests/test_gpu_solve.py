@@ -351,7 +351,7 @@ def test_paired_half_sweeps_agree_bitwise(dim, n, levels, kap, prec, nu):
 
 
 @pytest.mark.parametrize("dim,n,levels,kap,prec,smoother,sigma,flags", [
-    # sizes whose finest vectors reach the 128 MB above which b is split
+    # sizes whose finest vectors reach the 64 MB above which b is split
     (3, 256, 8, False, "fp64", "rbgs", 0.0, 0),
     (3, 256, 8, True, "fp64", "jacobi", 0.0, 0),
     (3, 256, 8, False, "fp64", "rbgs", 200.0, "warm"),
@@ -556,19 +556,20 @@ def test_kernel_timing_leaves_the_solve_unchanged(dim, n, levels, op, prec):
     records) gives bitwise the untimed solve's iterate and history, and the
     timing is the same number of launches on every timed solve, one or more
     per cycle, each of positive duration; a class with no launch in the
-    solve (the half-sweep pair) reads zero."""
+    solve (the half-sweep pair) reads zero.  The steps from x = 0 are a class
+    of their own: one per FP32 correction cycle of iterative refinement."""
     torch_cuda()
     from paper_1609_04809_amd.mg import (PROF_PAIR, PROF_RESID_RESTRICT, PROF_SMOOTH,
-                                         PROF_SMOOTH_PRO, Solver)
+                                         PROF_SMOOTH_PRO, PROF_SMOOTH_ZERO, Solver)
     b = dev_full(dim, n, W.rhs_uniform(dim, n, 35))
     with Solver(dim, n, levels, op=op, precision=prec) as S:
         print(f"[timing] {dim}d n={n} {op} {prec}", flush=True)
         u0, k0, h0, st = S.solve(b, 1e-9)
         assert st == "ok"
         ref = host_full(u0)
-        kinds = [PROF_SMOOTH, PROF_PAIR] + ([PROF_SMOOTH_PRO, PROF_RESID_RESTRICT]
-                                            if op == "stencil" and dim == 3 and prec == "fp64"
-                                            else [])
+        kinds = [PROF_SMOOTH, PROF_PAIR, PROF_SMOOTH_ZERO]
+        if op == "stencil" and dim == 3 and prec == "fp64":
+            kinds += [PROF_SMOOTH_PRO, PROF_RESID_RESTRICT]
         for kid in kinds:
             counts = []
             for _ in range(2):
@@ -581,6 +582,9 @@ def test_kernel_timing_leaves_the_solve_unchanged(dim, n, levels, op, prec):
                 counts.append(launches)
                 if kid == PROF_PAIR:
                     assert launches == 0 and ms == 0.0
+                elif kid == PROF_SMOOTH_ZERO:
+                    assert launches >= (k0 if prec == "fp32_ir" else 0), (launches, k0)
+                    assert launches == 0 or 0.0 < ms / launches < 50.0, (ms, launches)
                 else:
                     assert launches >= k0, (kid, launches, k0)
                     assert 0.0 < ms / launches < 50.0, (kid, ms, launches)

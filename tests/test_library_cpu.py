@@ -126,9 +126,11 @@ def _aligned(nbytes):
     (dict(dim=3, n=384, levels=8, precision="fp32_ir"), False, 2),
     # CG keeps b natural (its residual is separate) but the cycles' iterate split
     (dict(dim=3, n=256, levels=8, flags=8), False, 2),
-    # the mass-shifted operator of the heat equation, two levels above 128 MB
+    # 257^3 FP32 vectors (68 MB) are split too
+    (dict(dim=3, n=256, levels=8, precision="fp32_ir"), False, 2),
+    # the mass-shifted operator of the heat equation, two levels above 64 MB
     (dict(dim=3, n=512, levels=9, sigma=200.0), True, 4),
-    # below 128 MB nothing is split
+    # below 64 MB nothing is split
     (dict(dim=3, n=128, levels=7), False, 0),
     # multicolour Gauss-Seidel and 2D grids keep every vector natural
     (dict(dim=3, n=256, levels=8, smoother="gs"), False, 0),
