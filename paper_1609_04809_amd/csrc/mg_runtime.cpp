@@ -818,11 +818,12 @@ void emit_split_run(mg_ctx* c, const Sink& sink, int l, const std::vector<int>& 
 // `skip`, the first step is not emitted: it has already been done, from
 // *spare into *cur.  With MG_FLAG_PAIR, consecutive red-black half-sweeps
 // on the large 3D stencil levels go out as pairs (one pass each, bitwise
-// the same result).
+// the same result).  state: the run is a split run whose halves are
+// tracked there (see emit_split_run), ending split unless !end_split.
 template <typename T>
 void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spare, bool* zero,
                   const T* b, bool skip = false, bool from_split = false,
-                  int* state = nullptr) {
+                  int* state = nullptr, bool end_split = true) {
   const int nu = pre ? c->o.nu_pre : c->o.nu_post;
   if (c->o.smoother == MG_SMOOTH_GS) {
     // multicolour Gauss-Seidel: one in-place launch per colour, colours in
@@ -851,8 +852,9 @@ void smooth_level(mg_ctx* c, const Sink& sink, int l, bool pre, T** cur, T** spa
   const bool pairs = !c->csr && c->o.smoother == MG_SMOOTH_RBGS &&
                      pair_sweeps(c->lv[l].g) && (c->o.flags & MG_FLAG_PAIR);
   if (state) {
-    // the iterate stays colour-split before and after the run
-    emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b, from_split, state, true);
+    // the iterate is colour-split before the run (or starts it) and stays
+    // split after it unless !end_split
+    emit_split_run<T>(c, sink, l, steps, cur, spare, zero, b, from_split, state, end_split);
     return;
   }
   if (from_split) {
@@ -952,10 +954,19 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     }
     bool z = zero;
     const bool s0 = l == 0 && split0;  // (head fusion: at least one pre-smoothing step)
+    // Otherwise, on a level-0 visit that starts from a natural iterate or
+    // from 0 (the FP32 cycles of refinement, the cycles of CG), the
+    // iterate stays colour-split from the pre-smoothing through the
+    // residual and the fused prolongation into the post-smoothing, whose
+    // last step writes it natural: halves tracked in spat
+    int spat[2] = {0, 0};
+    const bool sp = l == 0 && !split0 && !head_done && c->o.smoother == MG_SMOOTH_RBGS &&
+                    c->o.nu_pre >= 1 && split_iterate<T>(c, 0) && fuse_prolongation(c, 0);
+    int* const sat = s0 ? c->s0at : (sp ? spat : nullptr);
     smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
-                    l == 0 && head_done && split_iterate<T>(c, 0), s0 ? c->s0at : nullptr);
+                    l == 0 && head_done && split_iterate<T>(c, 0), sat);
     if (z) emit_fill<T>(c, sink, l, cur[l]);  // no pre-smoothing: x = 0
-    emit_resid_restrict<T>(c, sink, l, cur[l], bb[l], s0 ? c->s0at : nullptr);
+    emit_resid_restrict<T>(c, sink, l, cur[l], bb[l], sat);
     if (l + 1 == L - 1) {
       visit(l + 1, kind, true);
     } else {
@@ -975,16 +986,16 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       const bool sx = split_iterate<T>(c, l);
       Level& Lv = c->lv[l];
       const long lay = (Lv.g.nodes + 1) / 2;
-      if (s0) {
-        // x split in the halves c->s0at; x + P e changes every node, so
-        // both halves go to the other buffers (colour 1 updated)
+      if (sat) {
+        // x split in the halves sat; x + P e changes every node, so both
+        // halves go to the other buffers (colour 1 updated)
         o.sub |= XL_SPLIT_BOTH << 5;
-        o.item.a = Bufs<T>::xs(Lv, c->s0at[0]);
-        o.item.a2 = Bufs<T>::xs(Lv, c->s0at[1]) + lay;
-        c->s0at[0] = 1 - c->s0at[0];
-        c->s0at[1] = 1 - c->s0at[1];
-        o.item.c = Bufs<T>::xs(Lv, c->s0at[1]) + lay;
-        o.item.c2 = Bufs<T>::xs(Lv, c->s0at[0]);
+        o.item.a = Bufs<T>::xs(Lv, sat[0]);
+        o.item.a2 = Bufs<T>::xs(Lv, sat[1]) + lay;
+        sat[0] = 1 - sat[0];
+        sat[1] = 1 - sat[1];
+        o.item.c = Bufs<T>::xs(Lv, sat[1]) + lay;
+        o.item.c2 = Bufs<T>::xs(Lv, sat[0]);
       } else if (sx) {
         // colour 1 updated into the odd half, colour 0 copied to the even one
         o.sub |= XL_TO_SPLIT << 5;
@@ -994,7 +1005,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
       sink(o);
       std::swap(cur[l], spare[l]);
       smooth_level<T>(c, l == 0 && iru_u ? collect0 : sink, l, false, &cur[l], &spare[l], &nz,
-                      bb[l], true, sx || s0, s0 ? c->s0at : nullptr);
+                      bb[l], true, sx || sat, sat, s0);
       if (s0) {
         c->s0u[0] = c->s0at[0];
         c->s0u[1] = c->s0at[1];

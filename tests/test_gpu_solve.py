@@ -357,6 +357,8 @@ def test_paired_half_sweeps_agree_bitwise(dim, n, levels, kap, prec, nu):
     (3, 256, 8, False, "fp64", "rbgs", 200.0, "warm"),
     (3, 384, 8, False, "fp32_ir", "rbgs", 0.0, 0),
     (3, 384, 8, False, "fp32_ir", "rbgs", 0.0, "pcg"),
+    (3, 256, 8, False, "fp64", "rbgs", 0.0, "pcg"),
+    (3, 256, 8, False, "fp32_ir", "rbgs", 0.0, 0),
 ])
 def test_colour_split_right_hand_sides_agree_bitwise(dim, n, levels, kap, prec, smoother, sigma,
                                                      flags):
