@@ -84,10 +84,13 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 FP64 cycle, otherwise computed in one pass
                                 with the next cycle's first pre-smoothing
                                 step, and on 3D constant-coefficient stencil
-                                levels with n >= 32 the prolongation,
+                                levels with n >= 32 (coarse levels of a
+                                graph-replayed solve: n >= 96) the
+                                prolongation,
                                 otherwise done while the first
                                 post-smoothing step stages x */
-#define MG_FLAG_PAIR 16      /* on 3D stencil levels with n >= 32, launch
+#define MG_FLAG_PAIR 16      /* on 3D stencil levels with n >= 32 (coarse
+                                levels of a graph-replayed solve: n >= 96), launch
                                 consecutive red-black half-sweeps as one pass
                                 each (x, b and the result cross HBM once per
                                 pair; a halo of width 2 is recomputed in
@@ -310,7 +313,8 @@ mg_status mg_apply_restrict(mg_ctx* ctx, int level, int prec, const void* r,
                             void* b_coarse, void* stream);
 
 /* b_coarse = P^T (b - A_l x) (Algorithm 1: residual, then its restriction,
- * Sec. 5.4).  On 3D matrix-free levels with n >= 32 and the constant or
+ * Sec. 5.4).  On 3D matrix-free levels with n >= 32 (coarse levels of a
+ * context without MG_FLAG_NO_GRAPH: n >= 96) and the constant or
  * mass-shifted operator one pass, the fine residual not stored (the
  * context's residual buffer of the level serves as scratch), unless the
  * context was set up with MG_FLAG_NO_FUSE; elsewhere the residual and the

@@ -2429,7 +2429,7 @@ inline unsigned flat_blocks(long count) {
 // ---------------------------------------------------------------------------
 namespace {
 // 3D levels with at least 31 unknowns per direction use k_sweep3.
-inline bool use_sweep3(const Geo& g) { return g.dim == 3 && g.n >= 32; }
+inline bool use_sweep3(const Geo& g) { return g.s3; }
 
 inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc, int elem) {
   const int m = g.n - 1;

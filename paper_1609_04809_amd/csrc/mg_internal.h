@@ -19,6 +19,7 @@ struct Geo {
   long sy;    // node stride in y  (= n+1)
   long sz;    // node stride in z  (= (n+1)^2, 0 in 2D)
   long nodes; // (n+1)^dim
+  bool s3;    // the plane-marching kernels (k_sweep3 and its fused forms) run the level
 };
 
 inline Geo make_geo(int dim, int n) {
@@ -28,6 +29,7 @@ inline Geo make_geo(int dim, int n) {
   g.sy = n + 1;
   g.sz = dim == 3 ? (long)(n + 1) * (n + 1) : 0;
   g.nodes = dim == 3 ? (long)(n + 1) * (n + 1) * (n + 1) : (long)(n + 1) * (n + 1);
+  g.s3 = dim == 3 && n >= 32;
   return g;
 }
 
@@ -287,8 +289,9 @@ enum XLayout {
   XL_TO_NATURAL = 3,   // split in, natural out
   XL_SPLIT_BOTH = 4    // split in, both halves out (the fused prolongation)
 };
-// Whether k_sweep3 runs the level (3D, n >= 32), which is where split
-// iterates are possible.
+// Whether k_sweep3 runs the level (Geo::s3: 3D levels with n >= 32; the
+// runtime keeps coarse levels below n = 96 on the per-node kernels under
+// graph replay), which is where split iterates are possible.
 bool use_split_x(const Geo& g);
 // Two red-black half-sweeps in one pass, colour `first` (SM_RB0 / SM_RB1)
 // then the other; bitwise the result of two launch_smooth calls.  Only on

@@ -187,7 +187,16 @@ size_t plan(const mg_options& o, bool has_kappa, char* base, mg_ctx* c) {
   long maxpart = 1;
   for (int l = 0; l < o.levels; ++l) {
     const int nl = o.n >> l;
-    const Geo g = make_geo(o.dim, nl);
+    Geo g = make_geo(o.dim, nl);
+    // The plane-marching kernels run the 3D levels with n >= 32, except the
+    // coarse levels below n = 96 of a context whose cycles are replayed from
+    // graphs: there the per-node kernels are faster (their separate launches
+    // cost little in a graph; measured 2-3% of the 256^3 FP32-refinement and
+    // 192^3 kappa solves).  Launched one by one (MG_FLAG_NO_GRAPH, the
+    // server), the fused kernels' fewer launches pay.  Both compute every
+    // node bitwise alike, and no norm is formed on a coarse level, so the
+    // choice changes no result.
+    g.s3 = g.s3 && (l == 0 || nl >= 96 || (o.flags & MG_FLAG_NO_GRAPH));
     Level tmp;
     Level& L = c ? c->lv[l] : tmp;
     L.g = g;
@@ -1491,7 +1500,7 @@ bool batchable(const OpRec& a) {
 
 bool same_key(const OpRec& a, const OpRec& b) {
   return a.code == b.code && a.prec == b.prec && a.sub == b.sub && a.g.dim == b.g.dim &&
-         a.g.n == b.g.n && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
+         a.g.n == b.g.n && a.g.s3 == b.g.s3 && a.gc.n == b.gc.n && a.opkind == b.opkind && a.wc == b.wc &&
          a.w1 == b.w1 && a.w2 == b.w2 && a.s == b.s && a.wf == b.wf && a.omega == b.omega &&
          a.m == b.m && a.item.lay == b.item.lay &&
          a.count == b.count && batchable(a) && batchable(b);
