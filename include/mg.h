@@ -83,14 +83,14 @@ typedef enum { MG_CYCLE_V = 0, MG_CYCLE_W = 1, MG_CYCLE_F = 2 } mg_cycle;
                                 results bitwise): the stopping residual of an
                                 FP64 cycle, otherwise computed in one pass
                                 with the next cycle's first pre-smoothing
-                                step, and on 3D constant-coefficient stencil
-                                levels with n >= 32 (coarse levels of a
-                                graph-replayed solve: n >= 96) the
-                                prolongation,
-                                otherwise done while the first
+                                step, and on 3D stencil levels with n >= 32
+                                (coarse levels of a graph-replayed solve:
+                                n >= 96; per-cell kappa: FP64 only) the
+                                prolongation, otherwise done while the first
                                 post-smoothing step stages x */
 #define MG_FLAG_PAIR 16      /* on 3D stencil levels with n >= 32 (coarse
-                                levels of a graph-replayed solve: n >= 96), launch
+                                levels of a graph-replayed solve: n >= 96),
+                                launch
                                 consecutive red-black half-sweeps as one pass
                                 each (x, b and the result cross HBM once per
                                 pair; a halo of width 2 is recomputed in

@@ -902,6 +902,7 @@ inline int cycle_sub(int kind, int i) {
   return kind == MG_CYCLE_W ? MG_CYCLE_W : (kind == MG_CYCLE_F && i == 0 ? MG_CYCLE_F : MG_CYCLE_V);
 }
 
+template <typename T>
 bool fuse_prolongation(const mg_ctx* c, int l);
 
 // One cycle of the context's kind (Algorithm 1 for the V-cycle) for
@@ -970,7 +971,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     // last step writes it natural: halves tracked in spat
     int spat[2] = {0, 0};
     const bool sp = l == 0 && !split0 && !head_done && c->o.smoother == MG_SMOOTH_RBGS &&
-                    c->o.nu_pre >= 1 && split_iterate<T>(c, 0) && fuse_prolongation(c, 0);
+                    c->o.nu_pre >= 1 && split_iterate<T>(c, 0) && fuse_prolongation<T>(c, 0);
     int* const sat = s0 ? c->s0at : (sp ? spat : nullptr);
     smooth_level<T>(c, sink, l, true, &cur[l], &spare[l], &z, bb[l], l == 0 && head_done,
                     l == 0 && head_done && split_iterate<T>(c, 0), sat);
@@ -983,7 +984,7 @@ void emit_vcycle(mg_ctx* c, const Sink& sink, T* x0, T* spare0, const T* b0, boo
     }
     // the prolongation fused into the first post-smoothing step where that
     // pays (bitwise the same as the separate launches)
-    const bool fuse_pro = fuse_prolongation(c, l);
+    const bool fuse_pro = fuse_prolongation<T>(c, l);
     bool nz = false;
     if (fuse_pro) {
       OpRec o = base_op<T>(c, OC_SMOOTH_PRO, l);
@@ -1064,11 +1065,14 @@ bool head_fusion(const mg_ctx* c) {
 }
 
 // Whether the prolongation into level l is fused into its first
-// post-smoothing step: large 3D constant-coefficient stencil levels (with
-// per-cell kappa the fused kernel's register and LDS use cost more than the
-// pass it saves).
+// post-smoothing step: the 3D stencil levels k_sweep3 runs; with per-cell
+// kappa only in FP64 (the 192^3 kappa solve 12.65 -> 12.37 ms; in the FP32
+// cycles the fused kappa kernel's register and LDS use cost about what the
+// pass saves: 9.73 -> 9.77 ms).
+template <typename T>
 bool fuse_prolongation(const mg_ctx* c, int l) {
-  return !c->csr && !c->kappa && c->o.nu_post >= 1 && c->o.smoother != MG_SMOOTH_GS &&
+  return !c->csr && (!c->kappa || sizeof(T) == 8) && c->o.nu_post >= 1 &&
+         c->o.smoother != MG_SMOOTH_GS &&
          pair_sweeps(c->lv[l].g) && !(c->o.flags & (MG_FLAG_PAIR | MG_FLAG_NO_FUSE));
 }
 
@@ -1077,7 +1081,7 @@ bool fuse_prolongation(const mg_ctx* c, int l) {
 // split iterates, and both its fused steps (head, prolongation) are there
 // to read and write the halves.
 bool split_persist(const mg_ctx* c) {
-  return head_fusion(c) && split_iterate<double>(c, 0) && fuse_prolongation(c, 0);
+  return head_fusion(c) && split_iterate<double>(c, 0) && fuse_prolongation<double>(c, 0);
 }
 
 // Iteration kinds: IT_PLAIN = V-cycle, then residual norm;  IT_FUSED_FIRST =

@@ -236,20 +236,23 @@ def test_fused_stopping_residual_agrees_bitwise(dim, n, levels, op, smoother, ka
     assert abs(outs[0][0] - ko) <= 1
 
 
-@pytest.mark.parametrize("n,levels", [(128, 7), (192, 7)])
-def test_prolongation_chunks_agree_bitwise(n, levels):
+@pytest.mark.parametrize("n,levels,kap", [(128, 7, False), (192, 7, False), (96, 6, True),
+                                          (160, 6, True)])
+def test_prolongation_chunks_agree_bitwise(n, levels, kap):
     """The z-marching prolongation (2, 4 and 8 fine planes per block on the
     levels with 47, 95 and 191 or more unknowns per direction) gives
     bitwise the iterate and residual history of the prolongation fused
     into the first post-smoothing half-sweep, whose interpolation is the
-    per-node form."""
+    per-node form (with per-cell kappa too, fused in FP64)."""
     torch_cuda()
     from paper_1609_04809_amd.mg import FLAG_NO_FUSE, Solver
+    kappa = W.kappa_lognormal(3, n, 22) if kap else None
     b = W.rhs_uniform(3, n, 21)
     bd = dev_full(3, n, b)
     outs = []
     for flags in (0, FLAG_NO_FUSE):
-        with Solver(3, n, levels, op="stencil", smoother="rbgs", flags=flags) as S:
+        with Solver(3, n, levels, kappa=kappa, op="stencil", smoother="rbgs",
+                    flags=flags) as S:
             u, k, hist, st = S.solve(bd, 1e-8)
             assert st == "ok"
             outs.append((k, hist, host_full(u)))
