@@ -99,15 +99,21 @@ def test_fp32_ir_solve_matches_oracle(case):
     assert err < 1e-6, err
 
 
-def test_graph_and_eager_agree_bitwise():
+@pytest.mark.parametrize("n,levels,kap", [(32, 5, False), (128, 7, False), (96, 6, True)])
+def test_graph_and_eager_agree_bitwise(n, levels, kap):
+    """Graph replay and launches one by one (MG_FLAG_NO_GRAPH) give bitwise
+    the same iterate and history.  At 128^3 and 96^3 the coarse levels below
+    n = 96 run the per-node kernels under graph replay and the plane-marching
+    ones when launched one by one: the choice must not change a bit."""
     torch_cuda()
     from paper_1609_04809_amd.mg import FLAG_NO_GRAPH, Solver
-    dim, n = 3, 32
+    dim = 3
+    kappa = W.kappa_lognormal(dim, n, 8) if kap else None
     b = dev_full(dim, n, W.rhs_uniform(dim, n, 9))
     outs = []
     for flags in (0, FLAG_NO_GRAPH):
         for prec in ("fp64", "fp32_ir"):
-            with Solver(dim, n, 5, precision=prec, flags=flags) as S:
+            with Solver(dim, n, levels, kappa=kappa, precision=prec, flags=flags) as S:
                 u, k, hist, st = S.solve(b, 1e-8)
                 outs.append((prec, k, hist, host_full(u)))
     for a, c in ((0, 2), (1, 3)):
