@@ -1324,7 +1324,7 @@ __global__ __launch_bounds__(256) void k_restrict_xcols(Geo gf, int ncols, Batch
 }
 
 // ---------------------------------------------------------------------------
-// Two red-black half-sweeps in one pass on the 3D levels with n >= 32:
+// Two red-black half-sweeps in one pass on the 3D levels k_sweep3 runs:
 // colour CA, then colour 1-CA, bitwise what two k_sweep3 half-sweeps give.
 // A block owns the same 128 x 4 tile as k_sweep3 and marches its planes in
 // z.  At step s it stages plane s of x with a halo of 2 in x and y (LDS
@@ -2428,7 +2428,9 @@ inline unsigned flat_blocks(long count) {
 // launchers
 // ---------------------------------------------------------------------------
 namespace {
-// 3D levels with at least 31 unknowns per direction use k_sweep3.
+// Whether k_sweep3 (and its fused forms) runs the level: Geo::s3, set by
+// make_geo for the 3D levels with at least 31 unknowns per direction and
+// narrowed by the runtime per level.
 inline bool use_sweep3(const Geo& g) { return g.s3; }
 
 inline dim3 sweep3_grid(const Geo& g, int count, int* kz, int* nzc, int elem) {
